@@ -1,0 +1,301 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-derive the oracle's own formula: each checks it against an
+independent route (closed forms, visibility-space sums, the paper's printed
+numbers, invariants, statistics).  A dropped term, a wrong sign or index or a
+transposed operand in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import synthgen as sg
+
+
+def _c1_volts():
+    w = sg.make_workload("c1")
+    return w, sg.volts(w)
+
+
+# ------------------------------------------------------------------ decode --
+
+def test_decode_all_bytes_two_complement():
+    b = np.arange(256, dtype=np.uint8)
+    z = orc.decode_int4(b)
+    # independent route: arithmetic shifts of the signed byte view
+    sb = b.view(np.int8).astype(np.int64)
+    re = sb >> 4
+    im = ((b << 4).astype(np.uint8).view(np.int8).astype(np.int64)) >> 4
+    assert np.array_equal(z.real, re) and np.array_equal(z.imag, im)
+    assert z.real.min() == -8 and z.real.max() == 7
+
+
+def test_decode_pack_roundtrip():
+    re = np.arange(-8, 8).repeat(16)
+    im = np.tile(np.arange(-8, 8), 16)
+    z = orc.decode_int4(sg.pack_nibbles(re, im))
+    assert np.array_equal(z.real, re) and np.array_equal(z.imag, im)
+
+
+# ---------------------------------------------------------------- Parseval --
+
+@pytest.mark.parametrize("taper", [False, True])
+def test_parseval_exact(taper):
+    """sum_A |B_A|^2 = (M_ew M_ns / n_ew n_ns) sum_a |h eta_a|^2 (zero-padded DFT)."""
+    w, v = _c1_volts()
+    h = sg.gaussian_taper(w.n_ew, w.n_ns) if taper else None
+    i = orc.beamform_fft(v, w.m_ew, w.m_ns, w.block, taper=h)
+    eta = orc.decode_int4(v)
+    if h is not None:
+        eta = eta * h.astype(np.float64)
+    rhs = (w.m_ew * w.m_ns) / (w.n_ew * w.n_ns) * (np.abs(eta) ** 2).sum()
+    assert abs(i.sum() / rhs - 1) < 1e-12
+    if not taper:
+        assert abs(w.m_ew * w.m_ns / (w.n_ew * w.n_ns) - 2.0) < 1e-15
+
+
+# ---------------------------------------------- lattice-aligned source -----
+
+def _dirichlet(n, d):
+    """sin^2(n pi d) / sin^2(pi d), limit n^2 at integer d (e:pointed_beam_shape)."""
+    d = np.asarray(d, dtype=np.float64)
+    s = np.sin(np.pi * d)
+    out = np.full(d.shape, float(n * n))
+    ok = np.abs(s) > 1e-9
+    out[ok] = np.sin(n * np.pi * d[ok]) ** 2 / s[ok] ** 2
+    return out
+
+
+@pytest.mark.parametrize("q_ew,q_ns", [(0, 0), (1, 2), (3, 1), (2, 3)])
+def test_point_source_closed_form(q_ew, q_ns):
+    """Noise-free source at y = q/4 per axis: |B_A|^2 = (amp^2/n) D_ew D_ns."""
+    n_ew, n_ns, m_ew, m_ns, amp, nt = 4, 16, 4, 32, 7, 32
+    v = sg.point_source_volts(n_ew, n_ns, q_ew, q_ns, nt, amp)
+    i = orc.beamform_fft(v, m_ew, m_ns, 16)[0, 0, 0]          # [m_ew][m_ns]
+    y_ew, y_ns = q_ew / 4, q_ns / 4
+    de = _dirichlet(n_ew, y_ew - np.arange(m_ew) / m_ew)
+    dn = _dirichlet(n_ns, y_ns - np.arange(m_ns) / m_ns)
+    ref = 16 * amp ** 2 / (n_ew * n_ns) * de[:, None] * dn[None, :]
+    assert np.allclose(i, ref, rtol=1e-12, atol=1e-9 * ref.max())
+    # unpadded E-W axis: the source lands in exactly one E-W beam
+    row = i.sum(axis=1)
+    assert np.count_nonzero(row > 1e-9 * row.max()) == 1
+    assert np.argmax(row) == (q_ew * m_ew) // 4
+    # padded N-S axis (M = 2n): the peak beam holds half the row power,
+    # even offsets from the peak are exact zeros
+    pk = (q_ns * m_ns) // 4
+    r = i[np.argmax(row)]
+    assert abs(r[pk] / r.sum() - 0.5) < 1e-12
+    even = r[(pk + np.arange(2, m_ns, 2)) % m_ns]
+    assert np.all(even < 1e-20 * r.max())
+
+
+# -------------------------------------------------- visibility routes -----
+
+def _small_array(seed, n_ew, n_ns, nt=16):
+    w = sg.custom_workload(n_ew=n_ew, n_ns=n_ns, n_time=nt, seed=seed, snr=3.0)
+    return w, sg.volts(w)
+
+
+@pytest.mark.parametrize("taper", [False, True])
+def test_bruteforce_visibilities_2d(taper):
+    """b_A = (1/n) sum_ab h_a h_b exp(-i2pi A.(a-b)/M) V_ab (e:Vab, e:b2n-1)."""
+    n_ew, n_ns, m_ew, m_ns = 2, 4, 2, 8
+    w, v = _small_array(11, n_ew, n_ns)
+    h = sg.gaussian_taper(n_ew, n_ns) if taper else None
+    got = orc.beamform_fft(v, m_ew, m_ns, 16, taper=h)[0, 0, 0]
+    eta = orc.decode_int4(v)[:, 0, 0].reshape(16, n_ns * n_ew)
+    pos = np.array([(a % n_ew, a // n_ew) for a in range(n_ns * n_ew)])
+    vis = orc.visibilities(eta)
+    hv = None if h is None else h.reshape(-1).astype(np.float64)
+    ref = orc.beam_power_from_visibilities(vis, pos, (m_ew, m_ns), hv)
+    assert np.allclose(got, ref, rtol=1e-11, atol=1e-9)
+
+
+@pytest.mark.parametrize("m", [15, 16, 24])
+def test_stacked_visibilities_linear(m):
+    """b_A from the redundancy-stacked visibilities (e:b_V_delta, e:b2n-1)."""
+    n = 8
+    w, v = _small_array(12, 1, n)
+    got = orc.beamform_fft(v, 1, m, 16)[0, 0, 0, 0]
+    eta = orc.decode_int4(v)[:, 0, 0, :, 0]
+    vt = orc.stacked_visibilities(orc.visibilities(eta), n)
+    ref = orc.beam_power_from_stacked(vt, n, m)
+    assert np.allclose(got, ref, rtol=1e-11, atol=1e-9)
+
+
+def test_inverse_recovers_stacked_when_padded():
+    """V~_delta = (n/M) sum_A e^{i2pi delta A/M} b_A for M >= 2n-1 (e:inv_b2n-1)."""
+    n = 8
+    w, v = _small_array(13, 1, n)
+    eta = orc.decode_int4(v)[:, 0, 0, :, 0]
+    vt = orc.stacked_visibilities(orc.visibilities(eta), n)
+    for m in (2 * n - 1, 2 * n):
+        b = orc.beamform_fft(v, 1, m, 16)[0, 0, 0, 0]
+        assert np.allclose(orc.stacked_from_beams(b, n, m), vt, atol=1e-9)
+
+
+def test_unpadded_axis_only_recovers_aliased_lags():
+    """With M = n the beams hold only the circularly aliased lag sums."""
+    n = 4
+    w, v = _small_array(14, 1, n)
+    eta = orc.decode_int4(v)[:, 0, 0, :, 0]
+    vt = orc.stacked_visibilities(orc.visibilities(eta), n)
+    b = orc.beamform_fft(v, 1, n, 16)[0, 0, 0, 0]
+    circ = (1 / n) * np.exp(2j * np.pi * np.arange(n)[:, None] * np.arange(n)[None, :] / n) @ b * n
+    aliased = np.array([sum(vt[d + n - 1] for d in range(-(n - 1), n) if d % n == k) for k in range(n)])
+    assert np.allclose(circ, aliased, atol=1e-9)
+    assert not np.allclose(circ[1], vt[n])       # the lag-1 sum alone is lost
+
+
+# ------------------------------------------------------- tied beams -------
+
+def test_tied_on_grid_reproduces_fft_beams():
+    w, v = _c1_volts()
+    A = np.array([(a_ew, a_ns) for a_ew in range(4) for a_ns in (0, 5, 16, 31)])
+    dl = np.array([[0.5, 0.5]])
+    dircos = np.stack([A[:, 0] / w.m_ew / 0.5, A[:, 1] / w.m_ns / 0.5], axis=1)
+    tb = orc.tied_beams(v[:32], dircos, dl)[:, 0, 0]          # [t][P]
+    fb = orc.fft_beams(orc.decode_int4(v[:32]), w.m_ew, w.m_ns)[:, 0, 0]
+    ref = fb[:, A[:, 0], A[:, 1]]
+    assert np.allclose(tb, ref, atol=1e-11)
+
+
+@pytest.mark.parametrize("n,m", [(16, 32), (4, 4), (16, 16), (8, 13)])
+def test_complex_interpolation_equals_phased_sum(n, m):
+    """B_p = sum_A c_A(y) B_A exactly for M >= n (voltage analogue of e:bp_max_arbitrary)."""
+    w, v = _small_array(15, 1, n, nt=16)
+    rng = np.random.default_rng(0)
+    y = rng.uniform(-0.5, 0.5, 9)
+    fb = orc.fft_beams(orc.decode_int4(v), 1, m)[:, 0, 0]     # [t][1][m]
+    got = orc.interpolate_beams(fb, np.zeros(9), y, 1, n)
+    ref = orc.tied_beams(v, np.stack([np.zeros(9), y], axis=1), np.array([[1.0, 1.0]]))[:, 0, 0]
+    assert np.allclose(got, ref, atol=1e-11)
+
+
+@pytest.mark.parametrize("m", [31, 32])
+def test_paper_regridding_matches_phased_sum_intensity(m):
+    """Intensity regridding of eq. e:bp_max_arbitrary reproduces the pointed beam for M >= 2n-1."""
+    n = 16
+    w, v = _small_array(16, 1, n, nt=64)
+    b = orc.beamform_fft(v, 1, m, 16)[:, 0, 0, 0]               # [blk][m]
+    rng = np.random.default_rng(1)
+    for y in rng.uniform(-0.5, 0.5, 6):
+        wA = orc.regrid_weights_paper(n, m, y)
+        got = b @ wA
+        ref = orc.tied_intensity(v, np.array([[0.0, y]]), np.array([[1.0, 1.0]]), 16)[:, 0, 0, 0]
+        assert np.allclose(got, ref, rtol=1e-10)
+
+
+def test_paper_regridding_fails_below_2n_minus_1():
+    n, m = 16, 30
+    w, v = _small_array(16, 1, n, nt=64)
+    b = orc.beamform_fft(v, 1, m, 16)[:, 0, 0, 0]
+    y = 0.123
+    got = b @ orc.regrid_weights_paper(n, m, y)
+    ref = orc.tied_intensity(v, np.array([[0.0, y]]), np.array([[1.0, 1.0]]), 16)[:, 0, 0, 0]
+    assert np.max(np.abs(got / ref - 1)) > 1e-3
+
+
+# ------------------------------------------------------- statistics -------
+
+def test_noise_statistics():
+    """Normalisation e:w_norm, variance e:var_bV, and beam covariance e:pointed_beam_covar."""
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=4, n_pol=2, n_time=2048, seed=21, n_src=0)
+    v = sg.volts(w)
+    i = orc.beamform_fft(v, 4, 32, 16)                 # [blk][c][p][4][32]
+    eta = orc.decode_int4(v)
+    p_ant = np.mean(np.abs(eta) ** 2)
+    x = i.reshape(i.shape[0] * 8, 4, 32)
+    # sum |w_a|^2 = 1: each beam's mean intensity is block * <|eta|^2>
+    assert abs(x.mean() / (16 * p_ant) - 1) < 0.01
+    # Var(b_f) = <b_f>^2 / n_samp
+    ratio = x.var(axis=0).mean() / x.mean() ** 2
+    assert abs(ratio * 16 - 1) < 0.05
+    # M = n on E-W: independent beams; M = 2n on N-S: adjacent beams
+    # correlated by sin^2(n pi / M) / (n^2 sin^2(pi / M))
+    c_ew = np.corrcoef(x[:, 0, :].ravel(), x[:, 1, :].ravel())[0, 1]
+    assert abs(c_ew) < 0.03
+    c_ns = np.corrcoef(x[:, :, :-1].ravel(), x[:, :, 1:].ravel())[0, 1]
+    expect = math.sin(16 * math.pi / 32) ** 2 / (16 ** 2 * math.sin(math.pi / 32) ** 2)
+    assert abs(c_ns - expect) < 0.03
+
+
+# -------------------------------------------- printed window numbers ------
+
+def _peak_ratio(h1d):
+    """Naive-windowed peak response relative to the unwindowed pointed beam.
+
+    Beam normalised by N of eq. e:windowed_beam_shape, evaluated through the
+    oracle's sculpted FFT beamformer on a noise-free on-grid source.
+    """
+    n = len(h1d)
+    v = sg.point_source_volts(1, n, 0, 0, 16, 7)
+    taper = h1d.reshape(n, 1).astype(np.float32)
+    i_w = orc.beamform_fft(v, 1, 2 * n, 16, taper=taper)[0, 0, 0, 0, 0]
+    i_u = orc.beamform_fft(v, 1, 2 * n, 16)[0, 0, 0, 0, 0]
+    norm = np.mean(taper.astype(np.float64) ** 2)
+    return i_w / norm / i_u
+
+
+def test_window_peak_response_printed_value():
+    """The paper prints 83% for the n = 32 half-sine window (Sec. windowing).
+
+    The printed formula sin(pi (a + 1/2) / n) gives 81.1%; the window that
+    vanishes one spacing beyond the ends, sin(pi (a + 1) / (n + 1)), gives
+    the printed 83% -- our reading of the garbled example.
+    """
+    import os
+    here = os.path.dirname(__file__)
+    vals = dict(l.split()[:2] for l in open(os.path.join(here, "golden", "window_n32.txt"))
+                if l.strip() and not l.startswith("#"))
+    printed = float(vals["naive_peak_response"])
+    a = np.arange(32)
+    r_printed = _peak_ratio(np.sin(np.pi * (a + 0.5) / 32))
+    r_shifted = _peak_ratio(np.sin(np.pi * (a + 1) / 33))
+    assert round(r_shifted, 2) == printed
+    assert abs(r_printed - 8 / np.pi ** 2) < 0.005      # continuum limit of the printed form
+    # closed form for the on-grid peak: (sum h)^2 / (n sum h^2)
+    h = np.sin(np.pi * (a + 1) / 33)
+    assert abs(r_shifted - h.sum() ** 2 / (32 * (h ** 2).sum())) < 1e-6
+
+
+# ------------------------------------------------------ small pieces ------
+
+def test_accumulate_constant_modulus():
+    rng = np.random.default_rng(3)
+    r = rng.uniform(0.5, 2.0, 7)
+    ph = rng.uniform(0, 2 * np.pi, (64, 7))
+    z = r[None, :] * np.exp(1j * ph)
+    i = orc.accumulate_intensity(z, 16)
+    assert np.allclose(i, np.broadcast_to(16 * r ** 2, (4, 7)), rtol=1e-13)
+    assert np.allclose(orc.accumulate_intensity(z, 16, prev=i), 2 * i)
+
+
+def test_clamp_and_pol_sum_are_selections():
+    w = sg.custom_workload(n_ew=4, n_ns=8, n_chan=3, n_pol=2, n_time=32, seed=5, n_ns_keep=8,
+                           dl=(0.4, 0.8))
+    v = sg.volts(w)
+    sel = w.ns_select()
+    full = orc.beamform_fft(v, 4, 16, 16)
+    cl = orc.beamform_fft(v, 4, 16, 16, ns_select=sel)
+    for c in range(3):
+        assert np.array_equal(cl[:, c], full[:, c][..., sel[c]])
+    ps = orc.beamform_fft(v, 4, 16, 16, ns_select=sel, pol_sum=True)
+    assert np.allclose(ps, cl.sum(axis=2))
+
+
+def test_clamp_table_points_near_targets():
+    """Each kept beam A is the FFT beam nearest its target (e:theta_A)."""
+    w = sg.make_workload("c2")
+    sel = w.ns_select()
+    dl = w.d_over_lambda()[:, 1]
+    s = -1 + (np.arange(256) + 0.5) / 128
+    for c in (0, 100, 255):
+        A = sel[c].astype(np.float64)
+        A = np.where(A >= w.m_ns / 2, A - w.m_ns, A)
+        target = w.m_ns * dl[c] * s
+        wrapped = (target + w.m_ns / 2) % w.m_ns - w.m_ns / 2
+        assert np.all(np.abs(A - wrapped) <= 0.5 + 1e-9)
