@@ -1,0 +1,183 @@
+/*
+ * fftbf.h -- C ABI of the MI355X FFT beamformer (libfftbf.so).
+ *
+ * FFT beamforming of channelised antenna voltages on a regular 2-D lattice,
+ * after K. W. Masui et al., "Algorithms for FFT Beamforming Radio
+ * Interferometers" (arXiv:1710.08591).
+ *
+ * Conventions shared by every call:
+ *   - Voltages: uint8 volts[t][chan][pol][a_ns][a_ew], E-W index fastest.
+ *     Each byte is one complex sample: two's-complement 4-bit real part in
+ *     the high nibble, 4-bit imaginary part in the low nibble (the
+ *     digitised antenna signal eta_a[t] of eq. e:Vab).
+ *   - Beams: FFT beam (A_ew, A_ns) carries the voltage weights of eq.
+ *     e:w_A^a per axis, n^-1/2 exp(-i 2 pi A a / M), on the separable 2-D
+ *     lattice with n = n_ew * n_ns; the N-S axis is zero-padded from n_ns
+ *     to m_ns (Sec. "Redundant arrays and Fourier transform beamforming",
+ *     eq. e:fftbeamform).  Beam A points at sin(theta_A) = A lambda / (M d)
+ *     (eq. e:theta_A), natural FFT order A in [0, M).
+ *   - Intensities: |B|^2 summed (not averaged) over `block` consecutive
+ *     samples, blocks aligned to t = 0 of the call (the time sum of eqs.
+ *     e:bf and e:fftbeamform without the 1/n_samp and unit factors).
+ *   - Every device pointer is caller-owned device memory (the library never
+ *     allocates or frees caller memory).  The plan owns its device tables.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call other
+ *     than plan creation and destruction is asynchronous on that stream.
+ *   - Arguments are validated before any launch; on a validation error
+ *     nothing is written and nothing is launched.  No call aborts or throws.
+ *     Device faults surface as BF_ERR_DEVICE.  bf_last_error() gives a
+ *     thread-local description of the last failing call.
+ */
+#ifndef FFTBF_H
+#define FFTBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BF_OK = 0,
+  BF_ERR_INVALID_ARGUMENT = -1,
+  BF_ERR_UNSUPPORTED = -2,
+  BF_ERR_OUT_OF_MEMORY = -3,
+  BF_ERR_DEVICE = -4,
+  BF_ERR_REJECTED = -5,   /* serving: request exceeds the memory budget */
+  BF_ERR_EVICTED = -6,    /* serving: requested window left the ring    */
+  BF_ERR_NOT_READY = -7   /* serving: result not finished yet           */
+} bf_status;
+
+typedef enum {
+  BF_PREC_FP32 = 0,       /* FP32 radix FFT on the vector ALUs            */
+  BF_PREC_FP16_MFMA = 1,  /* N-S DFT stages on FP16 MFMA, FP32 accumulate */
+  BF_PREC_FP8_MFMA = 2    /* N-S DFT stages on FP8 MFMA, FP32 accumulate  */
+} bf_precision;
+
+typedef enum {
+  BF_OUT_INTENSITY = 0,   /* float intensities, see each call           */
+  BF_OUT_COMPLEX = 1      /* float2 complex beams, one per sample        */
+} bf_out_kind;
+
+typedef struct bf_plan bf_plan;
+
+/*
+ * Plan geometry.  Supported: n_ew = m_ew = 4 (unpadded E-W axis);
+ * n_ns a power of two in [16, 256] with m_ns = 2 n_ns (zero padding by two,
+ * the smallest power of two with M >= 2n - 1, eq. e:b2n-1); block a
+ * multiple of 16 (mixed precision) or of 4 (FP32); 1 <= n_pol <= 2.
+ * Other shapes return BF_ERR_UNSUPPORTED.
+ */
+typedef struct {
+  int32_t n_ew, n_ns;          /* antennas per axis                          */
+  int32_t m_ew, m_ns;          /* transform lengths per axis                 */
+  int32_t n_pol, n_chan;       /* polarisations (independent antennas), channels */
+  int32_t block;               /* samples summed per intensity (n_samp)      */
+  int32_t n_ns_keep;           /* N-S beams kept per channel; 0 -> m_ns      */
+  int32_t pol_sum;             /* 1: intensities summed over polarisations   */
+  int32_t precision;           /* bf_precision                               */
+  const double *d_over_lambda; /* host [n_chan][2] (ew, ns) spacing in wavelengths;
+                                  NULL -> 0.5 on both axes.  Used by tied beams. */
+  const int32_t *ns_select;    /* host [n_chan][n_ns_keep] kept N-S beam indices
+                                  in [0, m_ns); NULL -> identity (needs n_ns_keep
+                                  0 or m_ns).  Copied into the plan. */
+} bf_plan_desc;
+
+/* Validate the descriptor, build the plan's device tables (twiddles in FP64
+ * on the current device, rounded to the working precision; clamp table;
+ * d/lambda table).  Synchronous.  On success *plan owns device memory until
+ * bf_plan_destroy.  Errors: BF_ERR_INVALID_ARGUMENT (NULL pointers, bad
+ * sizes, ns_select entries out of range), BF_ERR_UNSUPPORTED (shape),
+ * BF_ERR_OUT_OF_MEMORY, BF_ERR_DEVICE. */
+bf_status bf_plan_create(const bf_plan_desc *desc, bf_plan **plan);
+
+/* Free the plan's device tables (synchronises the device first).  NULL is a no-op. */
+bf_status bf_plan_destroy(bf_plan *plan);
+
+/* Copy the plan's descriptor (pointers in the copy are NULL). */
+bf_status bf_plan_get_desc(const bf_plan *plan, bf_plan_desc *desc);
+
+/*
+ * FFT beamforming of a contiguous voltage time series (the hot path).
+ * Sec. "Redundant arrays and Fourier transform beamforming", eq.
+ * e:fftbeamform, with the per-antenna window of Sec. "Controlling beam
+ * shape with windowing" (w_nw^a ~ h^a w_p^a) applied before the transform.
+ *
+ *   volts  device uint8 [n_time][n_chan][n_pol][n_ns][n_ew]
+ *   n_time samples; a multiple of the plan's block for BF_OUT_INTENSITY
+ *   taper  device float [n_ns][n_ew] real per-antenna weights h_a, or NULL (h = 1)
+ *   kind   BF_OUT_INTENSITY: out is float
+ *            [n_time/block][n_chan][n_pol][m_ew][n_ns_keep]   (pol_sum = 0)
+ *            [n_time/block][n_chan][m_ew][n_ns_keep]          (pol_sum = 1)
+ *          holding sum over each block of |B|^2 for the kept N-S beams
+ *          ns_select[chan][j], j < n_ns_keep, in that order.
+ *          BF_OUT_COMPLEX (FP32 plans only): out is float2
+ *            [n_time][n_chan][n_pol][m_ew][m_ns], every beam, unclamped.
+ * The mixed-precision plans take the int4 samples exactly into FP16 / FP8
+ * operands and round the DFT coefficients (split into a high and a low
+ * part) to the working precision, accumulating in FP32.
+ */
+bf_status bf_beamform_fft(const bf_plan *plan, const uint8_t *volts, int64_t n_time,
+                          const float *taper, int32_t kind, void *out, void *stream);
+
+/*
+ * Tied-array (pointed) beams at arbitrary directions, formed by
+ * interpolating complex FFT beams.  The weights follow from substituting
+ * the zero-padded inverse transform into the pointed-beam weights of eq.
+ * e:c_pointed (the voltage-domain analogue of the regridding of eq.
+ * e:bp_max_arbitrary): per axis
+ *     c_A(y) = (1/M) sum_{a<n} exp(+i 2 pi a (A/M - y)),  y = (d/lambda) n_axis,
+ * exact for M >= n.  They are generated in FP64 on the device and applied
+ * in FP32: B_p[t] = sum_{A_ew, A_ns} c_{A_ew}(y_ew) c_{A_ns}(y_ns) B_A[t].
+ *
+ *   fft_beams  device float2 [n_time][n_chan][n_pol][m_ew][m_ns] (as written
+ *              by bf_beamform_fft with BF_OUT_COMPLEX)
+ *   chan_lo, n_chan_sub   channel range [chan_lo, chan_lo + n_chan_sub)
+ *   dircos     device double [n_point][2] direction cosines (ew, ns)
+ *   kind       BF_OUT_INTENSITY: out float [n_time/block][n_chan_sub][n_pol][n_point]
+ *              (pol_sum: [n_time/block][n_chan_sub][n_point]);
+ *              BF_OUT_COMPLEX: out float2 [n_time][n_chan_sub][n_pol][n_point]
+ * Per-channel d/lambda comes from the plan.
+ */
+bf_status bf_form_tied_beams(const bf_plan *plan, const void *fft_beams, int64_t n_time,
+                             int32_t chan_lo, int32_t n_chan_sub, const double *dircos,
+                             int32_t n_point, int32_t kind, void *out, void *stream);
+
+/*
+ * Tied-array beams straight from voltages: the FFT beams of each sample are
+ * formed on chip (FP32, as bf_beamform_fft) and interpolated as in
+ * bf_form_tied_beams without leaving the compute unit.
+ *
+ *   volts     device uint8 [n_time][n_chan][n_pol][n_ns][n_ew] (full channel set)
+ *   taper     device float [n_ns][n_ew] or NULL
+ *   other arguments as bf_form_tied_beams (intensity output only).
+ */
+bf_status bf_form_tied_beams_v(const bf_plan *plan, const uint8_t *volts, int64_t n_time,
+                               const float *taper, int32_t chan_lo, int32_t n_chan_sub,
+                               const double *dircos, int32_t n_point, void *out, void *stream);
+
+/*
+ * Standalone intensity accumulation (the |B|^2 time sum of eq. e:bf):
+ *   out[b][s] (+)= sum_{t in block b} |z[t][s]|^2
+ *   z    device float2 [n_time][n_series]
+ *   out  device float [n_time/block][n_series]
+ *   add  0: overwrite out, 1: add to out
+ * n_time must be a multiple of block (block >= 1).
+ */
+bf_status bf_accumulate_intensity(const void *z, int64_t n_time, int64_t n_series,
+                                  int32_t block, int32_t add, float *out, void *stream);
+
+/* Static description of a status code. */
+const char *bf_status_string(int32_t status);
+
+/* Thread-local detail of the last non-OK status returned on this thread. */
+const char *bf_last_error(void);
+
+/* Library version string. */
+const char *bf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTBF_H */

@@ -1,0 +1,233 @@
+"""MI355X FFT beamformer: Python binding of libfftbf (torch tensors in, torch tensors out).
+
+The functions here only check tensors and marshal pointers into the C ABI of
+include/fftbf.h; every step of the beamformer runs in the library's HIP
+kernels on the caller's current torch stream.  Importing this package does
+not load the library; the first call does, and fails loudly if it has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from ._lib import (BF_OK, BF_ERR_INVALID_ARGUMENT, BF_ERR_UNSUPPORTED, BF_ERR_OUT_OF_MEMORY,
+                   BF_ERR_DEVICE, BF_ERR_REJECTED, BF_ERR_EVICTED, BF_ERR_NOT_READY,
+                   BF_PREC_FP32, BF_PREC_FP16_MFMA, BF_PREC_FP8_MFMA, BF_OUT_INTENSITY,
+                   BF_OUT_COMPLEX, BFError, LibraryMissing, bf_plan_desc, check, lib)
+
+__all__ = [
+    "Plan", "plan_create", "plan_destroy", "beamform_fft", "form_tied_beams", "form_tied_beams_v",
+    "accumulate_intensity", "lib", "BFError", "LibraryMissing",
+    "BF_PREC_FP32", "BF_PREC_FP16_MFMA", "BF_PREC_FP8_MFMA", "BF_OUT_INTENSITY", "BF_OUT_COMPLEX",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> C.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _need(t, dtype, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """A beamforming plan: lattice geometry, precision, clamp table (bf_plan_create)."""
+
+    def __init__(self, n_ew: int = 4, n_ns: int = 16, m_ew: Optional[int] = None,
+                 m_ns: Optional[int] = None, n_pol: int = 1, n_chan: int = 1, block: int = 16,
+                 ns_select: Optional[np.ndarray] = None, pol_sum: bool = False,
+                 precision: int = BF_PREC_FP32, d_over_lambda: Optional[np.ndarray] = None):
+        m_ew = n_ew if m_ew is None else m_ew
+        m_ns = 2 * n_ns if m_ns is None else m_ns
+        keep = 0
+        self._sel = None
+        self._dl = None
+        d = bf_plan_desc()
+        d.n_ew, d.n_ns, d.m_ew, d.m_ns = n_ew, n_ns, m_ew, m_ns
+        d.n_pol, d.n_chan, d.block = n_pol, n_chan, block
+        d.pol_sum, d.precision = int(bool(pol_sum)), int(precision)
+        if ns_select is not None:
+            self._sel = np.ascontiguousarray(ns_select, dtype=np.int32)
+            if self._sel.ndim != 2 or self._sel.shape[0] != n_chan:
+                raise ValueError("ns_select must be [n_chan][n_ns_keep]")
+            keep = self._sel.shape[1]
+            d.ns_select = self._sel.ctypes.data_as(C.POINTER(C.c_int32))
+        if d_over_lambda is not None:
+            self._dl = np.ascontiguousarray(d_over_lambda, dtype=np.float64)
+            if self._dl.shape != (n_chan, 2):
+                raise ValueError("d_over_lambda must be [n_chan][2]")
+            d.d_over_lambda = self._dl.ctypes.data_as(C.POINTER(C.c_double))
+        d.n_ns_keep = keep
+        self.desc = d
+        self.n_ew, self.n_ns, self.m_ew, self.m_ns = n_ew, n_ns, m_ew, m_ns
+        self.n_pol, self.n_chan, self.block = n_pol, n_chan, block
+        self.keep = keep if keep else m_ns
+        self.pol_sum = bool(pol_sum)
+        self.precision = int(precision)
+        h = C.c_void_p()
+        check(lib().bf_plan_create(C.byref(d), C.byref(h)), "bf_plan_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().bf_plan_destroy(self.handle), "bf_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().bf_plan_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def volts_shape(self, n_time: int):
+        return (n_time, self.n_chan, self.n_pol, self.n_ns, self.n_ew)
+
+    def out_shape(self, n_time: int, kind: int = BF_OUT_INTENSITY):
+        if kind == BF_OUT_COMPLEX:
+            return (n_time, self.n_chan, self.n_pol, self.m_ew, self.m_ns)
+        nb = n_time // self.block
+        if self.pol_sum:
+            return (nb, self.n_chan, self.m_ew, self.keep)
+        return (nb, self.n_chan, self.n_pol, self.m_ew, self.keep)
+
+
+def plan_create(**kw) -> Plan:
+    return Plan(**kw)
+
+
+def plan_destroy(plan: Plan) -> None:
+    plan.close()
+
+
+def beamform_fft(plan: Plan, volts, taper=None, kind: int = BF_OUT_INTENSITY, out=None, stream=None):
+    """FFT beams of ``volts`` (uint8 [t][chan][pol][n_ns][n_ew]) -> intensities or complex beams."""
+    torch = _torch()
+    _need(volts, torch.uint8, "volts")
+    n_time = volts.shape[0]
+    if tuple(volts.shape) != plan.volts_shape(n_time):
+        raise ValueError(f"volts shape {tuple(volts.shape)} != {plan.volts_shape(n_time)}")
+    if taper is not None:
+        _need(taper, torch.float32, "taper")
+        if tuple(taper.shape) != (plan.n_ns, plan.n_ew):
+            raise ValueError("taper must be [n_ns][n_ew]")
+    shape = plan.out_shape(n_time, kind)
+    dt = torch.complex64 if kind == BF_OUT_COMPLEX else torch.float32
+    if out is None:
+        out = torch.empty(shape, dtype=dt, device=volts.device)
+    else:
+        _need(out, dt, "out")
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out shape {tuple(out.shape)} != {shape}")
+    check(lib().bf_beamform_fft(plan.handle, _ptr(volts), n_time, _ptr(taper), kind, _ptr(out),
+                                _stream_handle(stream)), "bf_beamform_fft")
+    return out
+
+
+def _dircos(dircos):
+    torch = _torch()
+    _need(dircos, torch.float64, "dircos")
+    if dircos.ndim != 2 or dircos.shape[1] != 2:
+        raise ValueError("dircos must be [n_point][2]")
+    return dircos.shape[0]
+
+
+def form_tied_beams(plan: Plan, fft_beams, chan_lo: int, n_chan_sub: int, dircos,
+                    kind: int = BF_OUT_INTENSITY, out=None, stream=None):
+    """Tied-array beams interpolated from complex FFT beams [t][chan][pol][m_ew][m_ns]."""
+    torch = _torch()
+    _need(fft_beams, torch.complex64, "fft_beams")
+    n_time = fft_beams.shape[0]
+    if tuple(fft_beams.shape) != (n_time, plan.n_chan, plan.n_pol, plan.m_ew, plan.m_ns):
+        raise ValueError("fft_beams must be [t][n_chan][n_pol][m_ew][m_ns]")
+    n_point = _dircos(dircos)
+    if kind == BF_OUT_COMPLEX:
+        shape, dt = (n_time, n_chan_sub, plan.n_pol, n_point), torch.complex64
+    elif plan.pol_sum:
+        shape, dt = (n_time // plan.block, n_chan_sub, n_point), torch.float32
+    else:
+        shape, dt = (n_time // plan.block, n_chan_sub, plan.n_pol, n_point), torch.float32
+    if out is None:
+        out = torch.empty(shape, dtype=dt, device=fft_beams.device)
+    else:
+        _need(out, dt, "out")
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out shape {tuple(out.shape)} != {shape}")
+    check(lib().bf_form_tied_beams(plan.handle, _ptr(fft_beams), n_time, chan_lo, n_chan_sub, _ptr(dircos),
+                                   n_point, kind, _ptr(out), _stream_handle(stream)), "bf_form_tied_beams")
+    return out
+
+
+def form_tied_beams_v(plan: Plan, volts, chan_lo: int, n_chan_sub: int, dircos, taper=None, out=None,
+                      stream=None):
+    """Tied-array beam intensities straight from voltages (FFT beams formed on chip)."""
+    torch = _torch()
+    _need(volts, torch.uint8, "volts")
+    n_time = volts.shape[0]
+    if tuple(volts.shape) != plan.volts_shape(n_time):
+        raise ValueError("volts shape does not match the plan")
+    if taper is not None:
+        _need(taper, torch.float32, "taper")
+    n_point = _dircos(dircos)
+    if plan.pol_sum:
+        shape = (n_time // plan.block, n_chan_sub, n_point)
+    else:
+        shape = (n_time // plan.block, n_chan_sub, plan.n_pol, n_point)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=volts.device)
+    else:
+        _need(out, torch.float32, "out")
+    check(lib().bf_form_tied_beams_v(plan.handle, _ptr(volts), n_time, _ptr(taper), chan_lo, n_chan_sub,
+                                     _ptr(dircos), n_point, _ptr(out), _stream_handle(stream)),
+          "bf_form_tied_beams_v")
+    return out
+
+
+def accumulate_intensity(z, block: int, out=None, add: bool = False, stream=None):
+    """sum over blocks of |z|^2 for complex64 z [t][series] (bf_accumulate_intensity)."""
+    torch = _torch()
+    _need(z, torch.complex64, "z")
+    if z.ndim != 2:
+        raise ValueError("z must be [n_time][n_series]")
+    n_time, n_series = z.shape
+    shape = (n_time // block if block > 0 else 0, n_series)
+    if out is None:
+        if add:
+            raise ValueError("add=True needs an existing out")
+        out = torch.empty(shape, dtype=torch.float32, device=z.device)
+    else:
+        _need(out, torch.float32, "out")
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out shape {tuple(out.shape)} != {shape}")
+    check(lib().bf_accumulate_intensity(_ptr(z), n_time, n_series, block, int(add), _ptr(out),
+                                        _stream_handle(stream)), "bf_accumulate_intensity")
+    return out

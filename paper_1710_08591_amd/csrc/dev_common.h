@@ -1,0 +1,136 @@
+// Device-side helpers for the gfx950 beamforming kernels: complex FP32
+// arithmetic, compile-time DFT coefficients (evaluated in double precision
+// by the compiler) and fully unrolled in-register radix-2 transforms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftbf {
+
+struct cf {
+  float r, i;
+};
+
+__device__ __forceinline__ cf cadd(cf a, cf b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cf csub(cf a, cf b) { return {a.r - b.r, a.i - b.i}; }
+// a * w, two multiplies and two fused multiply-adds
+__device__ __forceinline__ cf cmul(cf a, cf w) {
+  return {fmaf(a.r, w.r, -(a.i * w.i)), fmaf(a.r, w.i, a.i * w.r)};
+}
+__device__ __forceinline__ float cnorm(cf a) { return fmaf(a.r, a.r, a.i * a.i); }
+
+// ---- compile-time exp(-i 2 pi k / M) in double --------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double cx_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 24; ++n) {
+    term *= -x * x / double((2 * n) * (2 * n + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 24; ++n) {
+    term *= -x * x / double((2 * n - 1) * (2 * n));
+    sum += term;
+  }
+  return sum;
+}
+// angle reduced to [-pi, pi] through the integer index before the series
+constexpr double tw_re(int k, int m) {
+  k = ((k % m) + m) % m;
+  int s = (2 * k > m) ? k - m : k;
+  return cx_cos(-2.0 * kPi * double(s) / double(m));
+}
+constexpr double tw_im(int k, int m) {
+  k = ((k % m) + m) % m;
+  int s = (2 * k > m) ? k - m : k;
+  return cx_sin(-2.0 * kPi * double(s) / double(m));
+}
+
+// x * W_M^k for a compile-time (k, M); the four axis-aligned twiddles are
+// exact sign/swap operations.
+template <int K, int M>
+__device__ __forceinline__ cf twiddle(cf x) {
+  constexpr int k = ((K % M) + M) % M;
+  if constexpr (k == 0) {
+    return x;
+  } else if constexpr (4 * k == M) {          // -i
+    return {x.i, -x.r};
+  } else if constexpr (2 * k == M) {          // -1
+    return {-x.r, -x.i};
+  } else if constexpr (4 * k == 3 * M) {      // +i
+    return {-x.i, x.r};
+  } else {
+    constexpr float wr = float(tw_re(k, M));
+    constexpr float wi = float(tw_im(k, M));
+    return cmul(x, cf{wr, wi});
+  }
+}
+
+// ---- in-register radix-2 decimation-in-frequency ------------------------
+// Natural-order input, bit-reversed output: after dif<L>(x), x[bitrev(k)]
+// holds sum_j x_in[j] W_L^{jk}.
+template <int L, int SPAN, int S, int J>
+struct DifBfly {
+  static __device__ __forceinline__ void run(cf* x) {
+    cf a = x[S + J], b = x[S + J + SPAN];
+    x[S + J] = cadd(a, b);
+    x[S + J + SPAN] = twiddle<J, 2 * SPAN>(csub(a, b));
+    if constexpr (J + 1 < SPAN) DifBfly<L, SPAN, S, J + 1>::run(x);
+  }
+};
+template <int L, int SPAN, int S>
+struct DifGroup {
+  static __device__ __forceinline__ void run(cf* x) {
+    DifBfly<L, SPAN, S, 0>::run(x);
+    if constexpr (S + 2 * SPAN < L) DifGroup<L, SPAN, S + 2 * SPAN>::run(x);
+  }
+};
+template <int L, int SPAN>
+struct DifStage {
+  static __device__ __forceinline__ void run(cf* x) {
+    DifGroup<L, SPAN, 0>::run(x);
+    if constexpr (SPAN > 1) DifStage<L, SPAN / 2>::run(x);
+  }
+};
+template <int L>
+__device__ __forceinline__ void dif(cf* x) {
+  if constexpr (L > 1) DifStage<L, L / 2>::run(x);
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev(int k, int n) {
+  int r = 0;
+  for (int b = 0; b < ilog2(n); ++b) r |= ((k >> b) & 1) << (ilog2(n) - 1 - b);
+  return r;
+}
+
+// Zero-padded DFT, L non-zero inputs -> 2L outputs in natural order:
+// y[k] = sum_{j<L} x[j] W_{2L}^{jk}.  Even outputs are the L-point DFT of x,
+// odd outputs the L-point DFT of x_j W_{2L}^j (first DIF stage with a zero
+// upper half).
+template <int L, int J>
+struct PadPre {
+  static __device__ __forceinline__ void run(const cf* x, cf* xo) {
+    xo[J] = twiddle<J, 2 * L>(x[J]);
+    if constexpr (J + 1 < L) PadPre<L, J + 1>::run(x, xo);
+  }
+};
+template <int L>
+__device__ __forceinline__ void padded_dft(cf* x /* in: [L], */, cf* y /* out: [2L] */) {
+  cf xo[L];
+  PadPre<L, 0>::run(x, xo);
+  dif<L>(x);
+  dif<L>(xo);
+#pragma unroll
+  for (int m = 0; m < L; ++m) {
+    y[2 * m] = x[bitrev(m, L)];
+    y[2 * m + 1] = xo[bitrev(m, L)];
+  }
+}
+
+}  // namespace fftbf

@@ -1,0 +1,344 @@
+// C-ABI host layer of libfftbf: plan objects, argument validation,
+// dispatch of the gfx950 kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fftbf.h"
+#include "kernels.h"
+
+struct bf_plan {
+  bf_plan_desc d;          // copy; pointer members are NULL
+  int device = 0;
+  int g = 0, l2 = 0;       // FP32 N-S split: m_ns = l2 * g
+  float2* tw = nullptr;    // [g][l2] FP32 twiddles W_M^{a1 k2}
+  int32_t* sel = nullptr;  // [n_chan][n_ns_keep] or null (identity)
+  double* dl = nullptr;    // [n_chan][2]
+  void* mix = nullptr;     // mixed-precision operand tables
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+bf_status fail(bf_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+bf_status fail(bf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+bf_status dev_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? BF_ERR_OUT_OF_MEMORY : BF_ERR_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+void free_plan(bf_plan* p) {
+  if (!p) return;
+  if (p->tw) (void)hipFree(p->tw);
+  if (p->sel) (void)hipFree(p->sel);
+  if (p->dl) (void)hipFree(p->dl);
+  if (p->mix) (void)hipFree(p->mix);
+  delete p;
+}
+
+int keep_of(const bf_plan_desc& d) { return d.n_ns_keep ? d.n_ns_keep : d.m_ns; }
+
+}  // namespace
+
+extern "C" {
+
+const char* bf_version(void) { return "fftbf 0.1 (gfx950)"; }
+
+const char* bf_status_string(int32_t s) {
+  switch (s) {
+    case BF_OK: return "ok";
+    case BF_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case BF_ERR_UNSUPPORTED: return "unsupported shape or option";
+    case BF_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case BF_ERR_DEVICE: return "device error";
+    case BF_ERR_REJECTED: return "request rejected (over budget)";
+    case BF_ERR_EVICTED: return "requested window evicted from the ring";
+    case BF_ERR_NOT_READY: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+const char* bf_last_error(void) { return g_err.c_str(); }
+
+bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
+  if (!desc || !plan) return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: NULL desc or plan");
+  *plan = nullptr;
+  const bf_plan_desc& d = *desc;
+  if (d.n_ew <= 0 || d.n_ns <= 0 || d.m_ew <= 0 || d.m_ns <= 0 || d.n_pol <= 0 || d.n_chan <= 0 ||
+      d.block <= 0 || d.n_ns_keep < 0)
+    return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: sizes must be positive");
+  if (d.m_ew < d.n_ew || d.m_ns < d.n_ns)
+    return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: transform shorter than the array");
+  if (d.n_ew != 4 || d.m_ew != 4)
+    return fail(BF_ERR_UNSUPPORTED, "plan_create: only n_ew = m_ew = 4 is supported");
+  if (!is_pow2(d.n_ns) || d.n_ns < 16 || d.n_ns > 256 || d.m_ns != 2 * d.n_ns)
+    return fail(BF_ERR_UNSUPPORTED,
+                "plan_create: n_ns must be a power of two in [16, 256] with m_ns = 2 n_ns");
+  if (d.n_pol > 2) return fail(BF_ERR_UNSUPPORTED, "plan_create: at most 2 polarisations");
+  if (d.pol_sum != 0 && d.pol_sum != 1) return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: pol_sum is 0 or 1");
+  if (d.precision < BF_PREC_FP32 || d.precision > BF_PREC_FP8_MFMA)
+    return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: unknown precision %d", d.precision);
+  const int keep = keep_of(d);
+  if (keep > d.m_ns) return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: n_ns_keep > m_ns");
+  if (!d.ns_select && keep != d.m_ns)
+    return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: a clamp (n_ns_keep < m_ns) needs ns_select");
+  if (d.block % 4 != 0) return fail(BF_ERR_UNSUPPORTED, "plan_create: block must be a multiple of 4");
+  if (d.precision != BF_PREC_FP32 && !fftbf::mix_supported(d.n_ns, d.precision, d.block))
+    return fail(BF_ERR_UNSUPPORTED, "plan_create: mixed precision not available for n_ns=%d block=%d",
+                d.n_ns, d.block);
+  if (d.ns_select) {
+    for (int64_t i = 0; i < (int64_t)d.n_chan * keep; ++i)
+      if (d.ns_select[i] < 0 || d.ns_select[i] >= d.m_ns)
+        return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: ns_select[%lld] = %d out of [0, %d)",
+                    (long long)i, d.ns_select[i], d.m_ns);
+  }
+  if (d.d_over_lambda) {
+    for (int64_t i = 0; i < (int64_t)d.n_chan * 2; ++i)
+      if (!(d.d_over_lambda[i] > 0.0) || d.d_over_lambda[i] > 1e6)
+        return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: d_over_lambda must be positive and finite");
+  }
+
+  bf_plan* p = new (std::nothrow) bf_plan();
+  if (!p) return fail(BF_ERR_OUT_OF_MEMORY, "plan_create: host allocation");
+  p->d = d;
+  p->d.d_over_lambda = nullptr;
+  p->d.ns_select = nullptr;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { free_plan(p); return dev_fail(e, "plan_create: hipGetDevice"); }
+
+  p->g = fftbf::fft32_group(d.n_ns);
+  p->l2 = d.m_ns / p->g;
+  hipStream_t s = nullptr;
+  e = hipMalloc(&p->tw, sizeof(float2) * p->g * p->l2);
+  if (e == hipSuccess) e = fftbf::launch_twiddle_table(p->tw, p->g, p->l2, d.m_ns, s);
+  if (e == hipSuccess && d.ns_select) {
+    e = hipMalloc(&p->sel, sizeof(int32_t) * d.n_chan * keep);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->sel, d.ns_select, sizeof(int32_t) * d.n_chan * keep, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) {
+    std::vector<double> dl((size_t)d.n_chan * 2, 0.5);
+    if (d.d_over_lambda) std::memcpy(dl.data(), d.d_over_lambda, sizeof(double) * dl.size());
+    e = hipMalloc(&p->dl, sizeof(double) * dl.size());
+    if (e == hipSuccess) e = hipMemcpy(p->dl, dl.data(), sizeof(double) * dl.size(), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && d.precision != BF_PREC_FP32) {
+    e = hipMalloc(&p->mix, fftbf::mix_table_bytes(d.n_ns, d.precision));
+    if (e == hipSuccess) e = fftbf::launch_mix_tables(p->mix, d.n_ns, d.precision, s);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_plan(p);
+    return dev_fail(e, "plan_create: device tables");
+  }
+  *plan = p;
+  return BF_OK;
+}
+
+bf_status bf_plan_destroy(bf_plan* plan) {
+  if (!plan) return BF_OK;
+  hipError_t e = hipDeviceSynchronize();
+  free_plan(plan);
+  if (e != hipSuccess) return dev_fail(e, "plan_destroy: pending device error");
+  return BF_OK;
+}
+
+bf_status bf_plan_get_desc(const bf_plan* plan, bf_plan_desc* desc) {
+  if (!plan || !desc) return fail(BF_ERR_INVALID_ARGUMENT, "plan_get_desc: NULL argument");
+  *desc = plan->d;
+  return BF_OK;
+}
+
+bf_status bf_beamform_fft(const bf_plan* plan, const uint8_t* volts, int64_t n_time,
+                          const float* taper, int32_t kind, void* out, void* stream) {
+  if (!plan) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: NULL plan");
+  const bf_plan_desc& d = plan->d;
+  if (kind != BF_OUT_INTENSITY && kind != BF_OUT_COMPLEX)
+    return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: unknown output kind %d", kind);
+  if (n_time < 0) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: negative n_time");
+  if (n_time == 0) return BF_OK;
+  if (!volts || !out) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: NULL volts or out");
+  if (!aligned(volts, 4)) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: volts must be 4-byte aligned");
+  if (!aligned(out, kind == BF_OUT_COMPLEX ? 8 : 4))
+    return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: out is misaligned");
+  if (taper && !aligned(taper, 16)) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: taper must be 16-byte aligned");
+  if (kind == BF_OUT_INTENSITY && n_time % d.block)
+    return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: n_time %lld is not a multiple of block %d",
+                (long long)n_time, d.block);
+  if (kind == BF_OUT_COMPLEX && d.precision != BF_PREC_FP32)
+    return fail(BF_ERR_UNSUPPORTED, "beamform_fft: complex beams are produced by FP32 plans only");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n_blk = (n_time + d.block - 1) / d.block;
+  const int n_pg = (kind == BF_OUT_INTENSITY && d.pol_sum) ? 1 : d.n_pol;
+  const int64_t n_wg = n_blk * d.n_chan * n_pg;
+  if (n_wg > 0x7FFFFFFFLL) return fail(BF_ERR_UNSUPPORTED, "beamform_fft: grid too large, split the call");
+  hipError_t e;
+  if (d.precision == BF_PREC_FP32) {
+    fftbf::Fft32Args a{};
+    a.volts = reinterpret_cast<const uint32_t*>(volts);
+    a.n_time = n_time;
+    a.n_chan = d.n_chan;
+    a.n_pol = d.n_pol;
+    a.n_pg = n_pg;
+    a.pol_iter = (n_pg == 1) ? d.n_pol : 1;
+    a.block = d.block;
+    a.tw = plan->tw;
+    a.taper = taper;
+    a.sel = plan->sel;
+    a.n_keep = keep_of(d);
+    a.out = out;
+    const float inv_n = 1.0f / float(d.n_ew * d.n_ns);
+    a.norm = (kind == BF_OUT_COMPLEX) ? 1.0f / std::sqrt(float(d.n_ew * d.n_ns)) : inv_n;
+    e = fftbf::launch_fft32(a, d.n_ns, taper != nullptr, kind == BF_OUT_COMPLEX, n_wg, s);
+  } else {
+    fftbf::MixArgs a{};
+    a.volts = reinterpret_cast<const uint32_t*>(volts);
+    a.n_time = n_time;
+    a.n_chan = d.n_chan;
+    a.n_pol = d.n_pol;
+    a.n_pg = n_pg;
+    a.pol_iter = (n_pg == 1) ? d.n_pol : 1;
+    a.block = d.block;
+    a.mat = plan->mix;
+    a.taper = taper;
+    a.sel = plan->sel;
+    a.n_keep = keep_of(d);
+    a.out = static_cast<float*>(out);
+    a.norm = 1.0f / float(d.n_ew * d.n_ns);
+    e = fftbf::launch_mix(a, d.n_ns, d.precision, n_wg, s);
+  }
+  if (e != hipSuccess) return dev_fail(e, "beamform_fft: launch");
+  return BF_OK;
+}
+
+static bf_status tied_common(const bf_plan* plan, int64_t n_time, int32_t chan_lo, int32_t n_chan_sub,
+                             const double* dircos, int32_t n_point, const void* out, const char* who) {
+  if (!plan) return fail(BF_ERR_INVALID_ARGUMENT, "%s: NULL plan", who);
+  const bf_plan_desc& d = plan->d;
+  if (n_time < 0 || n_point < 0 || n_chan_sub < 0)
+    return fail(BF_ERR_INVALID_ARGUMENT, "%s: negative size", who);
+  if (chan_lo < 0 || (int64_t)chan_lo + n_chan_sub > d.n_chan)
+    return fail(BF_ERR_INVALID_ARGUMENT, "%s: channel range [%d, %d) outside [0, %d)", who, chan_lo,
+                chan_lo + n_chan_sub, d.n_chan);
+  if (n_time && n_point && n_chan_sub && (!dircos || !out))
+    return fail(BF_ERR_INVALID_ARGUMENT, "%s: NULL dircos or out", who);
+  if (dircos && !aligned(dircos, 8)) return fail(BF_ERR_INVALID_ARGUMENT, "%s: dircos misaligned", who);
+  if (out && !aligned(out, 8)) return fail(BF_ERR_INVALID_ARGUMENT, "%s: out must be 8-byte aligned", who);
+  if (n_point > 4096) return fail(BF_ERR_UNSUPPORTED, "%s: at most 4096 pointings per call", who);
+  return BF_OK;
+}
+
+bf_status bf_form_tied_beams(const bf_plan* plan, const void* fft_beams, int64_t n_time, int32_t chan_lo,
+                             int32_t n_chan_sub, const double* dircos, int32_t n_point, int32_t kind,
+                             void* out, void* stream) {
+  bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams");
+  if (st != BF_OK) return st;
+  const bf_plan_desc& d = plan->d;
+  if (kind != BF_OUT_INTENSITY && kind != BF_OUT_COMPLEX)
+    return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: unknown output kind %d", kind);
+  if (n_time == 0 || n_point == 0 || n_chan_sub == 0) return BF_OK;
+  if (!fft_beams || !aligned(fft_beams, 8))
+    return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: NULL or misaligned fft_beams");
+  if (kind == BF_OUT_INTENSITY && n_time % d.block)
+    return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: n_time not a multiple of block");
+  if (kind == BF_OUT_COMPLEX && d.pol_sum)
+    return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: complex output cannot sum polarisations");
+  if (d.m_ns != 32 && d.m_ns != 64)
+    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams: m_ns must be 32 or 64");
+  fftbf::TiedArgs a{};
+  a.beams = static_cast<const float2*>(fft_beams);
+  a.n_time = n_time;
+  a.n_chan = d.n_chan;
+  a.n_pol = d.n_pol;
+  a.chan_lo = chan_lo;
+  a.n_chan_sub = n_chan_sub;
+  a.n_ew = d.n_ew;
+  a.n_ns = d.n_ns;
+  a.m_ew = d.m_ew;
+  a.m_ns = d.m_ns;
+  a.dircos = dircos;
+  a.dl = plan->dl;
+  a.n_point = n_point;
+  a.block = d.block;
+  a.pol_sum = d.pol_sum;
+  a.complex_out = kind == BF_OUT_COMPLEX;
+  a.out = out;
+  hipError_t e = fftbf::launch_tied(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return dev_fail(e, "form_tied_beams: launch");
+  return BF_OK;
+}
+
+bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
+                               int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
+                               void* out, void* stream) {
+  bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams_v");
+  if (st != BF_OK) return st;
+  const bf_plan_desc& d = plan->d;
+  if (n_time == 0 || n_point == 0 || n_chan_sub == 0) return BF_OK;
+  if (!volts || !aligned(volts, 4)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v: NULL or misaligned volts");
+  if (taper && !aligned(taper, 16)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v: taper misaligned");
+  if (n_time % d.block) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v: n_time not a multiple of block");
+  if (d.n_ns != 16 || d.block % 16)
+    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams_v: needs the 4 x 16 lattice and block a multiple of 16");
+  fftbf::TiedArgs a{};
+  a.volts = reinterpret_cast<const uint32_t*>(volts);
+  a.taper = taper;
+  a.n_time = n_time;
+  a.n_chan = d.n_chan;
+  a.n_pol = d.n_pol;
+  a.chan_lo = chan_lo;
+  a.n_chan_sub = n_chan_sub;
+  a.n_ew = d.n_ew;
+  a.n_ns = d.n_ns;
+  a.m_ew = d.m_ew;
+  a.m_ns = d.m_ns;
+  a.dircos = dircos;
+  a.dl = plan->dl;
+  a.n_point = n_point;
+  a.block = d.block;
+  a.pol_sum = d.pol_sum;
+  a.complex_out = 0;
+  a.out = out;
+  hipError_t e = fftbf::launch_tied_v(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return dev_fail(e, e == hipErrorNotSupported ? "form_tied_beams_v: shape" : "form_tied_beams_v: launch");
+  return BF_OK;
+}
+
+bf_status bf_accumulate_intensity(const void* z, int64_t n_time, int64_t n_series, int32_t block, int32_t add,
+                                  float* out, void* stream) {
+  if (n_time < 0 || n_series < 0) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: negative size");
+  if (block <= 0) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: block must be positive");
+  if (add != 0 && add != 1) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: add is 0 or 1");
+  if (n_time % block) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: n_time %lld not a multiple of block %d",
+                                  (long long)n_time, block);
+  if (n_time == 0 || n_series == 0) return BF_OK;
+  if (!z || !out) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: NULL z or out");
+  if (!aligned(z, 8) || !aligned(out, 4)) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: misaligned buffer");
+  if ((n_time / block) * n_series > (int64_t)0x7FFFFFFF * 256)
+    return fail(BF_ERR_UNSUPPORTED, "accumulate_intensity: too many outputs for one launch");
+  hipError_t e = fftbf::launch_accumulate(static_cast<const float2*>(z), n_time, n_series, block, add, out,
+                                          static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return dev_fail(e, "accumulate_intensity: launch");
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,281 @@
+// FP32 FFT beamformer for gfx950 (the voltage-rate hot path).
+//
+// Computes, per (channel, polarisation, sample), the 2-D FFT beams of the
+// 4 x n_ns lattice -- inner sum of eq. e:fftbeamform with the voltage
+// weights of eq. e:w_A^a, E-W unpadded (M_ew = 4), N-S zero-padded to
+// M = 2 n_ns -- then |B|^2 summed over blocks of samples (the time sum of
+// eq. e:bf), clamped to the kept N-S beams of each channel.
+//
+// Work split (one 64-lane wavefront per workgroup, one workgroup per
+// (block, channel, polarisation group)):
+//   * the N-S transform M = (2L) x G, with n_ns = L G:
+//       a = a1 + G a2,  A = k2 + 2L k1
+//       pass 1 (one lane per (frame, E-W beam e, a1)): zero-padded 2L-point
+//         DFT over a2, in registers, then the twiddle W_M^{a1 k2};
+//       LDS transpose (rows padded by one element against bank conflicts);
+//       pass 2 (lanes over (frame, e, k2)): G-point DFT over a1, in registers.
+//   * the E-W 4-point DFT has twiddles in {1, -i, -1, +i}: without a window
+//     it is two signed 4-bit dot products per N-S position (v_dot8_i32_i4
+//     straight on the packed voltage bytes, exact integers); with a window
+//     the nibbles are sign-extended, converted and weighted in FP32.
+//   * |B|^2 accumulates in registers across the block; at the block end the
+//     sums go through LDS once more so the kept beams can be gathered in
+//     the channel's clamp-table order and stored with coalesced writes.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace fftbf {
+
+namespace {
+
+// Per-lane dot8 weights for the E-W beam e: real and imaginary part of
+// sum_q x_q (-i)^{e q}.  Nibble 2q is Im(x_q), nibble 2q+1 is Re(x_q).
+__device__ __forceinline__ void ew_weights(int e, int& wre, int& wim) {
+  wre = 0;
+  wim = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = (e * q) & 3;
+    const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
+    // Re: k0 +r, k1 +i, k2 -r, k3 -i ; Im: k0 +i, k1 -r, k2 -i, k3 +r
+    if (k == 0) { wre |= 1 << sr;   wim |= 1 << si; }
+    if (k == 1) { wre |= 1 << si;   wim |= 0xF << sr; }
+    if (k == 2) { wre |= 0xF << sr; wim |= 0xF << si; }
+    if (k == 3) { wre |= 0xF << si; wim |= 1 << sr; }
+  }
+}
+
+struct TaperLane {
+  bool swap[4];
+  float sre[4], sim[4];
+};
+
+__device__ __forceinline__ TaperLane taper_lane(int e) {
+  TaperLane t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = (e * q) & 3;
+    t.swap[q] = (k & 1) != 0;
+    t.sre[q] = (k < 2) ? 1.f : -1.f;
+    t.sim[q] = (k == 0 || k == 3) ? 1.f : -1.f;
+  }
+  return t;
+}
+
+// sign-extended 4-bit field (the builtin's result type is unsigned)
+__device__ __forceinline__ float nib(uint32_t d, int shift) {
+  return (float)(int)__builtin_amdgcn_sbfe((int)d, shift, 4);
+}
+
+template <int N, int G, bool TAPER, bool CPLX>
+__global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
+  constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
+  constexpr int F = 64 / (4 * G);      // frames handled side by side
+  constexpr int R2 = (F * 4 * L2) / 64; // pass-2 tasks per lane
+  constexpr int YS = L2 + 1;           // padded LDS row, complex elements
+  static_assert(F >= 1 && F * 4 * G == 64, "pass-1 lanes must fill the wavefront");
+  static_assert(R2 >= 1 && R2 * 64 == F * 4 * L2, "pass-2 tasks must tile the wavefront");
+  static_assert(F * 4 * M * 4 <= F * 4 * G * YS * 8, "block-end sums must fit the LDS");
+
+  __shared__ cf lds_y[F * 4 * G * YS];
+  __shared__ float lds_h[TAPER ? N * 4 : 1];
+
+  const int lane = threadIdx.x;
+  const int f1 = lane / (4 * G), e1 = (lane / G) & 3, a1 = lane % G;
+
+  int wg = blockIdx.x;
+  const int pg = wg % p.n_pg;
+  wg /= p.n_pg;
+  const int chan = wg % p.n_chan;
+  const int blk = wg / p.n_chan;
+
+  if constexpr (TAPER) {
+    for (int i = lane; i < N * 4; i += 64) lds_h[i] = p.taper[i];
+    __syncthreads();
+  }
+
+  // pass-1 twiddles W_M^{a1 k2}, generated in FP64 at plan creation
+  cf tw1[L2];
+#pragma unroll
+  for (int k = 0; k < L2; ++k) {
+    const float2 w = p.tw[a1 * L2 + k];
+    tw1[k] = cf{w.x, w.y};
+  }
+
+  int wre = 0, wim = 0;
+  TaperLane tl{};
+  if constexpr (TAPER) tl = taper_lane(e1); else ew_weights(e1, wre, wim);
+
+  float acc[R2][G];
+#pragma unroll
+  for (int r = 0; r < R2; ++r)
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc[r][k] = 0.f;
+
+  const int64_t t_base = (int64_t)blk * p.block;
+  const int n_it = p.block / F;
+  const int64_t frame_stride = (int64_t)p.n_chan * p.n_pol * N;  // dwords per sample
+
+  for (int pi = 0; pi < p.pol_iter; ++pi) {
+    const int pol = (p.pol_iter == 1) ? pg : pi;
+    const uint32_t* src = p.volts + ((int64_t)chan * p.n_pol + pol) * N + a1;
+
+    uint32_t cur[L], nxt[L];
+    {
+      const int64_t t = t_base + f1;
+      const bool ok = t < p.n_time;
+#pragma unroll
+      for (int j = 0; j < L; ++j) cur[j] = ok ? __builtin_nontemporal_load(src + t * frame_stride + G * j) : 0u;
+    }
+
+    for (int it = 0; it < n_it; ++it) {
+      const int64_t t = t_base + (int64_t)it * F + f1;
+      // prefetch the next group of frames
+      if (it + 1 < n_it) {
+        const int64_t tn = t + F;
+        const bool okn = tn < p.n_time;
+#pragma unroll
+        for (int j = 0; j < L; ++j) nxt[j] = okn ? __builtin_nontemporal_load(src + tn * frame_stride + G * j) : 0u;
+      }
+
+      // ---- E-W DFT for this lane's beam e1 at N-S positions a1 + G j ----
+      cf x[L];
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        const uint32_t d = cur[j];
+        if constexpr (TAPER) {
+          const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 4]);
+          const float hq[4] = {h.x, h.y, h.z, h.w};
+          float re = 0.f, im = 0.f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
+            const float u = tl.swap[q] ? xi : xr;
+            const float v = tl.swap[q] ? xr : xi;
+            re = fmaf(tl.sre[q] * hq[q], u, re);
+            im = fmaf(tl.sim[q] * hq[q], v, im);
+          }
+          x[j] = cf{re, im};
+        } else {
+          x[j] = cf{(float)__builtin_amdgcn_sdot8((int)d, wre, 0, false),
+                    (float)__builtin_amdgcn_sdot8((int)d, wim, 0, false)};
+        }
+      }
+
+      // ---- pass 1: zero-padded 2L-point DFT over a2, twiddle, to LDS ----
+      cf y[L2];
+      padded_dft<L>(x, y);
+      cf* row = &lds_y[((f1 * 4 + e1) * G + a1) * YS];
+      row[0] = y[0];
+#pragma unroll
+      for (int k = 1; k < L2; ++k) row[k] = cmul(y[k], tw1[k]);
+      __syncthreads();
+
+      // ---- pass 2: G-point DFT over a1 ----
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int q = lane + 64 * r;
+        const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+        cf z[G];
+        const cf* col = &lds_y[(f * 4 + e) * G * YS + k2];
+#pragma unroll
+        for (int j = 0; j < G; ++j) z[j] = col[j * YS];
+        dif<G>(z);
+        if constexpr (CPLX) {
+          const int64_t tt = t_base + (int64_t)it * F + f;
+          if (tt < p.n_time) {
+            float2* o = static_cast<float2*>(p.out) +
+                        (((tt * p.n_chan + chan) * p.n_pol + pg) * 4 + e) * M + k2;
+#pragma unroll
+            for (int k1 = 0; k1 < G; ++k1) {
+              const cf b = z[bitrev(k1, G)];
+              o[L2 * k1] = make_float2(b.r * p.norm, b.i * p.norm);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k1 = 0; k1 < G; ++k1) acc[r][k1] += cnorm(z[bitrev(k1, G)]);
+        }
+      }
+      __syncthreads();
+
+#pragma unroll
+      for (int j = 0; j < L; ++j) cur[j] = nxt[j];
+    }
+  }
+
+  if constexpr (!CPLX) {
+    // ---- block end: gather the kept beams, sum frame groups, store ----
+    float* lds_i = reinterpret_cast<float*>(lds_y);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int q = lane + 64 * r;
+      const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+#pragma unroll
+      for (int k1 = 0; k1 < G; ++k1) lds_i[(f * 4 + e) * M + k2 + L2 * k1] = acc[r][k1];
+    }
+    __syncthreads();
+    const int keep = p.n_keep;
+    const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
+    float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * 4 * keep;
+    for (int idx = lane; idx < 4 * keep; idx += 64) {
+      const int e = idx / keep, j = idx - e * keep;
+      const int A = sel ? sel[j] : j;
+      float v = 0.f;
+#pragma unroll
+      for (int f = 0; f < F; ++f) v += lds_i[(f * 4 + e) * M + A];
+      o[idx] = v * p.norm;
+    }
+  }
+}
+
+template <int N, int G>
+hipError_t launch_n(const Fft32Args& a, bool taper, bool cplx, int64_t n_wg, hipStream_t s) {
+  dim3 grid((unsigned)n_wg), blockd(64);
+  if (taper) {
+    if (cplx) hipLaunchKernelGGL((k_fft32<N, G, true, true>), grid, blockd, 0, s, a);
+    else hipLaunchKernelGGL((k_fft32<N, G, true, false>), grid, blockd, 0, s, a);
+  } else {
+    if (cplx) hipLaunchKernelGGL((k_fft32<N, G, false, true>), grid, blockd, 0, s, a);
+    else hipLaunchKernelGGL((k_fft32<N, G, false, false>), grid, blockd, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int fft32_frames_per_pass(int n_ns) {
+  switch (n_ns) {
+    case 16: return 64 / (4 * 4);
+    case 32: return 64 / (4 * 8);
+    case 64: return 64 / (4 * 8);
+    case 128: return 64 / (4 * 16);
+    case 256: return 64 / (4 * 16);
+    default: return 0;
+  }
+}
+
+int fft32_group(int n_ns) {
+  switch (n_ns) {
+    case 16: return 4;
+    case 32: return 8;
+    case 64: return 8;
+    case 128: return 16;
+    case 256: return 16;
+    default: return 0;
+  }
+}
+
+hipError_t launch_fft32(const Fft32Args& a, int n_ns, bool taper, bool cplx, int64_t n_wg,
+                        hipStream_t s) {
+  switch (n_ns) {
+    case 16: return launch_n<16, 4>(a, taper, cplx, n_wg, s);
+    case 32: return launch_n<32, 8>(a, taper, cplx, n_wg, s);
+    case 64: return launch_n<64, 8>(a, taper, cplx, n_wg, s);
+    case 128: return launch_n<128, 16>(a, taper, cplx, n_wg, s);
+    case 256: return launch_n<256, 16>(a, taper, cplx, n_wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fftbf

@@ -1,0 +1,249 @@
+// Tied-array (pointed) beams at arbitrary directions by interpolating the
+// complex FFT beams.
+//
+// Substituting the zero-padded inverse transform
+//   eta_a = (sqrt(n)/M) sum_A B_A exp(+i 2 pi A a / M),   a < n,
+// into the pointed weights of eq. e:c_pointed gives, per axis,
+//   B_p = sum_A c_A(y) B_A,   c_A(y) = (1/M) sum_{a<n} exp(+i 2 pi a (A/M - y)),
+// exact whenever M >= n -- the voltage-domain counterpart of the intensity
+// regridding of eq. e:bp_max_arbitrary, which needs M >= 2n - 1.  The
+// weights are generated in FP64 on the device (the series is summed term by
+// term with a unit-modulus recurrence, so on-grid pointings need no 0/0
+// limit) and applied in FP32.
+//
+// One 64-lane wavefront per (pointing tile, channel, polarisation group,
+// run of time blocks); lane = pointing.  Every lane of a wave reads the same
+// FFT beam at the same time, so beam reads are wave-uniform (scalar loads
+// from the complex-beam array, LDS broadcasts in the voltage variant).
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace fftbf {
+
+namespace {
+
+constexpr int kTiedBlocksPerWg = 16;
+
+template <int M>
+__device__ __forceinline__ void interp_weights(double y, int n, cf* c) {
+#pragma unroll
+  for (int A = 0; A < M; ++A) {
+    const double u = (double)A / (double)M - y;
+    double s, co;
+    sincospi(2.0 * u, &s, &co);
+    double wr = 1.0, wi = 0.0, ar = 0.0, ai = 0.0;
+    for (int a = 0; a < n; ++a) {
+      ar += wr;
+      ai += wi;
+      const double t = wr * co - wi * s;
+      wi = wr * s + wi * co;
+      wr = t;
+    }
+    c[A] = cf{(float)(ar / M), (float)(ai / M)};
+  }
+}
+
+template <int MNS>
+__device__ __forceinline__ cf interp_one(const cf* __restrict__ b /* [4][MNS] */, const cf* cew, const cf* cns) {
+  cf bp{0.f, 0.f};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float zr = 0.f, zi = 0.f;
+#pragma unroll
+    for (int A = 0; A < MNS; ++A) {
+      const cf v = b[e * MNS + A];
+      zr = fmaf(cns[A].r, v.r, zr);
+      zr = fmaf(-cns[A].i, v.i, zr);
+      zi = fmaf(cns[A].r, v.i, zi);
+      zi = fmaf(cns[A].i, v.r, zi);
+    }
+    bp.r = fmaf(cew[e].r, zr, fmaf(-cew[e].i, zi, bp.r));
+    bp.i = fmaf(cew[e].r, zi, fmaf(cew[e].i, zr, bp.i));
+  }
+  return bp;
+}
+
+template <int MNS>
+__global__ __launch_bounds__(64) void k_tied(TiedArgs a) {
+  const int lane = threadIdx.x;
+  const int n_ptile = (a.n_point + 63) / 64;
+  const int n_pg = a.pol_sum ? 1 : a.n_pol;
+  int wg = blockIdx.x;
+  const int ptile = wg % n_ptile;
+  wg /= n_ptile;
+  const int trun = wg;                     // run of kTiedBlocksPerWg blocks
+  const int cs = blockIdx.y, pg = blockIdx.z;
+  const int chan = a.chan_lo + cs;
+  const int p = ptile * 64 + lane;
+  const bool live = p < a.n_point;
+  const int pp = live ? p : a.n_point - 1;
+
+  cf cew[4], cns[MNS];
+  {
+    const double dl_ew = a.dl[2 * chan], dl_ns = a.dl[2 * chan + 1];
+    interp_weights<4>(dl_ew * a.dircos[2 * pp], a.n_ew, cew);
+    interp_weights<MNS>(dl_ns * a.dircos[2 * pp + 1], a.n_ns, cns);
+  }
+  const int pol_lo = a.pol_sum ? 0 : pg, pol_hi = a.pol_sum ? a.n_pol : pg + 1;
+  const int64_t span = (int64_t)(a.complex_out ? 16 : a.block) * kTiedBlocksPerWg;
+  const int64_t t0 = (int64_t)trun * span;
+  const int64_t t1 = t0 + span < a.n_time ? t0 + span : a.n_time;
+
+  if (a.complex_out) {
+    for (int64_t t = t0; t < t1; ++t) {
+      const cf* b = reinterpret_cast<const cf*>(a.beams) + ((t * a.n_chan + chan) * a.n_pol + pg) * 4 * MNS;
+      const cf bp = interp_one<MNS>(b, cew, cns);
+      if (live) {
+        float2* o = static_cast<float2*>(a.out) + ((t * a.n_chan_sub + cs) * a.n_pol + pg) * (int64_t)a.n_point + p;
+        *o = make_float2(bp.r, bp.i);
+      }
+    }
+    return;
+  }
+  for (int64_t tb = t0; tb < t1; tb += a.block) {
+    float acc = 0.f;
+    for (int t = 0; t < a.block; ++t) {
+      for (int pol = pol_lo; pol < pol_hi; ++pol) {
+        const cf* b = reinterpret_cast<const cf*>(a.beams) +
+                      (((tb + t) * a.n_chan + chan) * a.n_pol + pol) * 4 * MNS;
+        acc += cnorm(interp_one<MNS>(b, cew, cns));
+      }
+    }
+    if (live) {
+      const int64_t blk = tb / a.block;
+      float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
+      *o = acc;
+    }
+  }
+}
+
+// Voltage variant for the 4 x 16 lattice (M_ns = 32): per group of 16
+// samples the wave forms the 4 x 32 FFT beams of each sample in LDS (lane =
+// (sample, E-W beam): two signed 4-bit dot products per N-S position for the
+// E-W DFT, then the zero-padded 32-point N-S DFT in registers), then every
+// lane interpolates its own pointing from LDS broadcasts.
+template <bool TAPER>
+__global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
+  constexpr int N = 16, MNS = 32, TS = 16;
+  __shared__ cf lds_b[TS * 4 * MNS];
+  __shared__ float lds_h[TAPER ? N * 4 : 1];
+  const int lane = threadIdx.x;
+  const int n_ptile = (a.n_point + 63) / 64;
+  const int n_pg = a.pol_sum ? 1 : a.n_pol;
+  int wg = blockIdx.x;
+  const int ptile = wg % n_ptile;
+  const int trun = wg / n_ptile;
+  const int cs = blockIdx.y, pg = blockIdx.z;
+  const int chan = a.chan_lo + cs;
+  const int p = ptile * 64 + lane;
+  const bool live = p < a.n_point;
+  const int pp = live ? p : a.n_point - 1;
+
+  if constexpr (TAPER) {
+    for (int i = lane; i < N * 4; i += 64) lds_h[i] = a.taper[i];
+  }
+  cf cew[4], cns[MNS];
+  {
+    const double dl_ew = a.dl[2 * chan], dl_ns = a.dl[2 * chan + 1];
+    interp_weights<4>(dl_ew * a.dircos[2 * pp], 4, cew);
+    interp_weights<MNS>(dl_ns * a.dircos[2 * pp + 1], N, cns);
+  }
+  // FFT role of this lane: sample ts, E-W beam e
+  const int ts = lane >> 2, e = lane & 3;
+  int wre = 0, wim = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = (e * q) & 3;
+    const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
+    if (k == 0) { wre |= 1 << sr;   wim |= 1 << si; }
+    if (k == 1) { wre |= 1 << si;   wim |= 0xF << sr; }
+    if (k == 2) { wre |= 0xF << sr; wim |= 0xF << si; }
+    if (k == 3) { wre |= 0xF << si; wim |= 1 << sr; }
+  }
+  __syncthreads();
+
+  const int pol_lo = a.pol_sum ? 0 : pg, pol_hi = a.pol_sum ? a.n_pol : pg + 1;
+  const int64_t span = (int64_t)a.block * kTiedBlocksPerWg;
+  const int64_t t0 = (int64_t)trun * span;
+  const int64_t t1 = t0 + span < a.n_time ? t0 + span : a.n_time;
+  const int64_t frame_dw = (int64_t)a.n_chan * a.n_pol * N;   // dwords per sample
+  const float nrm = 0.125f;                                   // 1/sqrt(4*16)
+
+  for (int64_t tb = t0; tb < t1; tb += a.block) {
+    float acc = 0.f;
+    for (int tg = 0; tg < a.block; tg += TS) {
+      for (int pol = pol_lo; pol < pol_hi; ++pol) {
+        // ---- FFT beams of samples tb+tg .. +15 into LDS ----
+        const uint32_t* src = a.volts + (tb + tg + ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * N;
+        cf x[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const uint32_t d = src[j];
+          if constexpr (TAPER) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int k = (e * q) & 3;
+              const float h = lds_h[j * 4 + q];
+              const float xr = (float)(int)__builtin_amdgcn_sbfe((int)d, 8 * q + 4, 4) * h;
+              const float xi = (float)(int)__builtin_amdgcn_sbfe((int)d, 8 * q, 4) * h;
+              // x * (-i)^k
+              const float ur = (k == 0) ? xr : (k == 1) ? xi : (k == 2) ? -xr : -xi;
+              const float ui = (k == 0) ? xi : (k == 1) ? -xr : (k == 2) ? -xi : xr;
+              re += ur;
+              im += ui;
+            }
+            x[j] = cf{re, im};
+          } else {
+            x[j] = cf{(float)__builtin_amdgcn_sdot8((int)d, wre, 0, false),
+                      (float)__builtin_amdgcn_sdot8((int)d, wim, 0, false)};
+          }
+        }
+        cf y[MNS];
+        padded_dft<N>(x, y);
+        cf* row = &lds_b[(ts * 4 + e) * MNS];
+#pragma unroll
+        for (int k = 0; k < MNS; ++k) row[k] = cf{y[k].r * nrm, y[k].i * nrm};
+        __syncthreads();
+        // ---- interpolate this lane's pointing for the 16 samples ----
+        for (int s = 0; s < TS; ++s) acc += cnorm(interp_one<MNS>(&lds_b[s * 4 * MNS], cew, cns));
+        __syncthreads();
+      }
+    }
+    if (live) {
+      const int64_t blk = tb / a.block;
+      float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
+      *o = acc;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tied(const TiedArgs& a, hipStream_t s) {
+  const int n_ptile = (a.n_point + 63) / 64;
+  const int64_t span = (int64_t)(a.complex_out ? 16 : a.block) * kTiedBlocksPerWg;
+  const int64_t n_run = (a.n_time + span - 1) / span;
+  const int n_pg = (a.pol_sum && !a.complex_out) ? 1 : a.n_pol;
+  if ((int64_t)n_ptile * n_run > 0x7FFFFFFF || a.n_chan_sub > 65535) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(n_ptile * n_run), (unsigned)a.n_chan_sub, (unsigned)n_pg);
+  if (a.m_ns == 32) hipLaunchKernelGGL(k_tied<32>, grid, dim3(64), 0, s, a);
+  else if (a.m_ns == 64) hipLaunchKernelGGL(k_tied<64>, grid, dim3(64), 0, s, a);
+  else return hipErrorNotSupported;
+  return hipGetLastError();
+}
+
+hipError_t launch_tied_v(const TiedArgs& a, hipStream_t s) {
+  if (a.n_ns != 16 || a.m_ns != 32 || a.block % 16) return hipErrorNotSupported;
+  const int n_ptile = (a.n_point + 63) / 64;
+  const int64_t span = (int64_t)a.block * kTiedBlocksPerWg;
+  const int64_t n_run = (a.n_time + span - 1) / span;
+  const int n_pg = a.pol_sum ? 1 : a.n_pol;
+  if ((int64_t)n_ptile * n_run > 0x7FFFFFFF || a.n_chan_sub > 65535) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(n_ptile * n_run), (unsigned)a.n_chan_sub, (unsigned)n_pg);
+  if (a.taper) hipLaunchKernelGGL(k_tied_v16<true>, grid, dim3(64), 0, s, a);
+  else hipLaunchKernelGGL(k_tied_v16<false>, grid, dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fftbf

@@ -1,0 +1,73 @@
+// Internal launch interface between the C-ABI host layer and the gfx950
+// kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftbf {
+
+struct Fft32Args {
+  const uint32_t* volts;   // frames as dwords: [t][chan][pol][n_ns] (4 E-W bytes each)
+  int64_t n_time;
+  int n_chan, n_pol;
+  int n_pg;                // polarisation groups in the output (n_pol, or 1 when summed)
+  int pol_iter;            // polarisations folded into one workgroup (1 or n_pol)
+  int block;               // samples per intensity block (chunk for complex output)
+  const float2* tw;        // [G][2L] W_M^{a1 k2}
+  const float* taper;      // [n_ns][4] or null
+  const int32_t* sel;      // [n_chan][n_keep] or null (identity)
+  int n_keep;
+  void* out;
+  float norm;              // 1/(n_ew n_ns) for intensities, its square root for complex beams
+};
+
+int fft32_frames_per_pass(int n_ns);
+int fft32_group(int n_ns);
+hipError_t launch_fft32(const Fft32Args& a, int n_ns, bool taper, bool cplx, int64_t n_wg,
+                        hipStream_t s);
+
+// FP64 table generation on the device
+hipError_t launch_twiddle_table(float2* tw, int g, int l2, int m, hipStream_t s);
+
+// standalone |z|^2 block sums
+hipError_t launch_accumulate(const float2* z, int64_t n_time, int64_t n_series, int block,
+                             int add, float* out, hipStream_t s);
+
+// tied-array beams from complex FFT beams
+struct TiedArgs {
+  const float2* beams;     // [t][n_chan][n_pol][m_ew][m_ns]
+  const uint32_t* volts;   // voltage variant: [t][n_chan][n_pol][n_ns] dwords
+  const float* taper;      // voltage variant: [n_ns][4] or null
+  int64_t n_time;
+  int n_chan, n_pol, chan_lo, n_chan_sub;
+  int n_ew, n_ns, m_ew, m_ns;
+  const double* dircos;    // [n_point][2]
+  const double* dl;        // [n_chan][2] d/lambda
+  int n_point;
+  int block;
+  int pol_sum;
+  int complex_out;
+  void* out;
+};
+hipError_t launch_tied(const TiedArgs& a, hipStream_t s);
+hipError_t launch_tied_v(const TiedArgs& a, hipStream_t s);
+
+// mixed-precision (MFMA) beamformer
+struct MixArgs {
+  const uint32_t* volts;
+  int64_t n_time;
+  int n_chan, n_pol, n_pg, pol_iter, block;
+  const void* mat;         // per-precision DFT operand tables (plan-owned)
+  const float* taper;
+  const int32_t* sel;
+  int n_keep;
+  float* out;
+  float norm;
+};
+hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t n_wg, hipStream_t s);
+size_t mix_table_bytes(int n_ns, int prec);
+hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s);
+bool mix_supported(int n_ns, int prec, int block);
+
+}  // namespace fftbf

@@ -1,0 +1,178 @@
+"""GPU parity of the FP32 FFT beamformer against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import synthgen as sg
+from tests.helpers import TOL_FP32, peak_err, plan_for, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _run(w, v_np, taper=None, kind=0, pol_sum=False, clamp=True, block=None):
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    plan = plan_for(w, pol_sum=pol_sum, clamp=clamp, block=block)
+    v = torch.from_numpy(np.ascontiguousarray(v_np)).cuda()
+    h = None if taper is None else torch.from_numpy(taper).cuda()
+    out = bf.beamform_fft(plan, v, taper=h, kind=kind)
+    torch.cuda.synchronize()
+    plan.close()
+    return out.cpu().numpy()
+
+
+def test_c1_parity():
+    w = sg.make_workload("c1")
+    v = sg.volts(w)
+    got = _run(w, v)
+    ref = orc.beamform_fft(v, w.m_ew, w.m_ns, w.block)
+    assert got.shape == ref.shape == (64, 1, 1, 4, 32)
+    assert rel_err(got, ref) < TOL_FP32
+
+
+def test_c1_taper_parity():
+    w = sg.make_workload("c3")
+    v = sg.volts(w)
+    h = sg.gaussian_taper(w.n_ew, w.n_ns)
+    got = _run(w, v, taper=h)
+    ref = orc.beamform_fft(v, w.m_ew, w.m_ns, w.block, taper=h)
+    assert rel_err(got, ref) < TOL_FP32
+
+
+@pytest.mark.parametrize("n_ns", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("taper", [False, True])
+def test_shapes_parity(n_ns, taper):
+    """Every supported N-S length, 2 channels x 2 pols, several blocks."""
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=2, n_pol=2, n_time=48, seed=n_ns, n_src=2, snr=4.0)
+    v = sg.volts(w)
+    h = sg.half_sine_taper(4, n_ns, shifted=True) if taper else None
+    got = _run(w, v, taper=h, clamp=False)
+    ref = orc.beamform_fft(v, w.m_ew, w.m_ns, w.block, taper=h)
+    assert rel_err(got, ref) < TOL_FP32
+
+
+@pytest.mark.parametrize("q", [(0, 0), (1, 2), (3, 1), (2, 3)])
+def test_point_source_closed_form_gpu(q):
+    """Noise-free lattice-aligned source: compare with the Dirichlet closed form."""
+    n_ew, n_ns = 4, 16
+    v = sg.point_source_volts(n_ew, n_ns, q[0], q[1], 32, 7)
+    w = sg.custom_workload(n_ew=n_ew, n_ns=n_ns, n_time=32, n_src=0)
+    got = _run(w, v, clamp=False)[0, 0, 0]
+    de = np.array([(np.sin(n_ew * np.pi * d) ** 2 / np.sin(np.pi * d) ** 2) if abs(np.sin(np.pi * d)) > 1e-9 else n_ew ** 2
+                   for d in q[0] / 4 - np.arange(4) / 4])
+    dn = np.array([(np.sin(n_ns * np.pi * d) ** 2 / np.sin(np.pi * d) ** 2) if abs(np.sin(np.pi * d)) > 1e-9 else n_ns ** 2
+                   for d in q[1] / 4 - np.arange(32) / 32])
+    ref = 16 * 49 / 64 * de[:, None] * dn[None, :]
+    assert peak_err(got, ref) < TOL_FP32
+    # even N-S offsets from the peak stay at (rounding-level) zero
+    pk = q[1] * 8
+    row = got[q[0]]
+    assert np.all(row[(pk + np.arange(2, 32, 2)) % 32] <= 1e-5 * row.max())
+
+
+def test_clamp_and_pol_sum():
+    w = sg.custom_workload(n_ew=4, n_ns=64, n_chan=3, n_pol=2, n_time=32, seed=9, n_ns_keep=64, dl=(0.4, 0.8))
+    v = sg.volts(w)
+    got = _run(w, v)
+    ref = orc.beamform_fft(v, w.m_ew, w.m_ns, w.block, ns_select=w.ns_select())
+    assert rel_err(got, ref) < TOL_FP32
+    unc = _run(w, v, clamp=False)
+    sel = w.ns_select()
+    for c in range(3):                      # clamp is a bitwise selection
+        assert np.array_equal(got[:, c], unc[:, c][..., sel[c]])
+    ps = _run(w, v, pol_sum=True)
+    refp = orc.beamform_fft(v, w.m_ew, w.m_ns, w.block, ns_select=sel, pol_sum=True)
+    assert ps.shape == refp.shape
+    assert rel_err(ps, refp) < TOL_FP32
+
+
+@pytest.mark.parametrize("n_time", [1, 5, 17, 64])
+def test_complex_beams_ragged(n_time):
+    """Complex FFT beams for every sample, including a ragged last chunk."""
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=2, n_pol=2, n_time=n_time, seed=3)
+    v = sg.volts(w)
+    got = _run(w, v, kind=1, clamp=False)
+    ref = orc.fft_beams(orc.decode_int4(v), 4, 32)
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-6
+
+
+def test_block_sizes():
+    w = sg.custom_workload(n_ew=4, n_ns=32, n_chan=1, n_pol=1, n_time=96, seed=4)
+    v = sg.volts(w)
+    for blk in (4, 8, 32, 48):
+        got = _run(w, v, clamp=False, block=blk)
+        ref = orc.beamform_fft(v, w.m_ew, w.m_ns, blk)
+        assert rel_err(got, ref) < TOL_FP32
+
+
+def test_extreme_values():
+    """All antennas at -8 - 8i (the most negative nibble) and +7 + 7i."""
+    torch = _torch()
+    for b in (0x88, 0x77):
+        w = sg.custom_workload(n_ew=4, n_ns=256, n_time=16, n_src=0)
+        v = np.full((16, 1, 1, 256, 4), b, dtype=np.uint8)
+        got = _run(w, v, clamp=False)
+        ref = orc.beamform_fft(v, 4, 512, 16)
+        assert peak_err(got, ref) < TOL_FP32
+
+
+def test_empty_and_errors():
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c1")
+    plan = plan_for(w)
+    v = torch.zeros((0, 1, 1, 16, 4), dtype=torch.uint8, device="cuda")
+    out = bf.beamform_fft(plan, v)
+    assert out.shape == (0, 1, 1, 4, 32)
+    v = torch.zeros((24, 1, 1, 16, 4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(bf.BFError) as e:
+        bf.beamform_fft(plan, v, out=torch.full((1, 1, 1, 4, 32), 7.0, device="cuda"))
+    assert e.value.status == bf.BF_ERR_INVALID_ARGUMENT
+    plan.close()
+
+
+def test_repeatable_bitwise():
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=256, n_chan=4, n_pol=2, n_time=256, seed=8)
+    plan = plan_for(w, clamp=False)
+    v = torch.from_numpy(sg.volts(w)).cuda()
+    a = bf.beamform_fft(plan, v)
+    b = bf.beamform_fft(plan, v)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    plan.close()
+
+
+def test_c2_full_size_sampled():
+    """The CHIME-shaped workload at full size, in the launch configuration the
+    benchmark times; sampled (block, channel, polarisation) outputs against
+    the oracle, plus Parseval-type sums on whole blocks."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c2")
+    plan = plan_for(w)
+    v = sg.volts(w, backend="torch", device="cuda")
+    out = bf.beamform_fft(plan, v)
+    torch.cuda.synchronize()
+    assert out.shape == (1024, 256, 2, 4, 256)
+    rng = np.random.default_rng(0)
+    picks = [(0, 0, 0), (1023, 255, 1)] + [tuple(int(x) for x in (rng.integers(1024), rng.integers(256), rng.integers(2)))
+                                          for _ in range(6)]
+    sel = w.ns_select()
+    for blk, c, p in picks:
+        vs = sg.volts(w, blk * 16, 16, chans=[c], pols=[p])
+        assert np.array_equal(vs, v[blk * 16:(blk + 1) * 16, c:c + 1, p:p + 1].cpu().numpy())
+        ref = orc.beamform_fft(vs, w.m_ew, w.m_ns, 16)[0, 0, 0]           # [4][512]
+        got = out[blk, c, p].cpu().numpy()
+        assert rel_err(got, ref[:, sel[c]]) < TOL_FP32
+    plan.close()
+    del v, out
+    torch.cuda.empty_cache()
