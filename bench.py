@@ -93,6 +93,86 @@ def cpu_baseline(seconds: float = 15.0):
                       f"({done} antenna-samples, {elapsed:.1f} s of oracle time, generation excluded)"}
 
 
+def _time_launches(fn, n: int, warmup: int = 2) -> float:
+    """Average milliseconds of fn() (one launch on the current stream)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(n):
+        fn()
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / n
+
+
+def run_extras(dev) -> dict:
+    """Side-by-side precision variants, per-variant error, tied-beam throughput."""
+    import numpy as np
+    import torch
+
+    import oracle as orc
+    import paper_1710_08591_amd as bf
+    import synthgen as sg
+    ex = {}
+    # (1) FP32 FFT vs FP16 / FP8 MFMA on the 4 x 16 lattice at scale
+    w = sg.Workload("lattice4x16_scaled", 4, 16, 256, 2, 16384, 4, 32, 16, 6,
+                    src_dircos=((0.3, -0.2), (-0.7, 0.5)), src_snr=(10.0, 30.0), dl_lo=0.4, dl_hi=0.8)
+    volts = sg.volts(w, backend="torch", device=dev)
+    rng = np.random.default_rng(7)
+    picks = [(int(rng.integers(w.n_time // 16)), int(rng.integers(w.n_chan)), int(rng.integers(w.n_pol)))
+             for _ in range(4)]
+    refs = {}
+    for blk, c, p in picks:
+        vs = sg.volts(w, blk * 16, 16, chans=[c], pols=[p])
+        refs[(blk, c, p)] = orc.beamform_fft(vs, 4, 32, 16)[0, 0, 0]
+    in_b = w.n_time * w.n_chan * w.n_pol * w.frame_bytes
+    variants = {}
+    for prec, name in ((0, "fp32_fft"), (1, "fp16_mfma"), (2, "fp8_mfma")):
+        plan = bf.Plan(n_ew=4, n_ns=16, n_pol=2, n_chan=256, block=16, precision=prec)
+        out = torch.empty(plan.out_shape(w.n_time), dtype=torch.float32, device=dev)
+        ms = _time_launches(lambda: bf.beamform_fft(plan, volts, out=out), 10)
+        err = max(float(np.max(np.abs(out[b, c, p].cpu().numpy() - r) / r)) for (b, c, p), r in refs.items())
+        alg = in_b + out.numel() * 4
+        variants[name] = {"antenna_samples_per_s": w.antenna_samples / (ms / 1e3), "kernel_ms": ms,
+                          "hbm_alg_gbs": alg / (ms / 1e3) / 1e9, "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                          "max_rel_power_err_sampled": err}
+        if prec:
+            # MFMA work actually issued: N-S DFT as [64 x 32] real matrix per E-W column, per term
+            terms = 2 if prec == 1 else 3
+            mf = w.n_time * w.n_chan * w.n_pol * 4 * 64 * 32 * 2 * terms
+            variants[name]["mfma_tflops"] = mf / (ms / 1e3) / 1e12
+        plan.close()
+        del out
+    ex["precision_variants"] = {"workload": "4x16 lattice, 2 pol, 256 chan, 16384 samples (512 MiB int4+4), "
+                                            "M_ns = 32, |B|^2 over 16", "variants": variants}
+    del volts
+    # (2) the tiny workload's bytes through each variant: error vs the FP64 oracle, every beam
+    w1 = sg.make_workload("c4")
+    v1 = sg.volts(w1)
+    ref1 = orc.beamform_fft(v1, 4, 32, 16)
+    errs = {}
+    for prec, name in ((0, "fp32_fft"), (1, "fp16_mfma"), (2, "fp8_mfma")):
+        plan = bf.Plan(n_ew=4, n_ns=16, block=16, precision=prec)
+        o = bf.beamform_fft(plan, torch.from_numpy(v1).to(dev)).cpu().numpy()
+        errs[name] = float(np.max(np.abs(o - ref1) / ref1))
+        plan.close()
+    ex["tiny_workload_max_rel_power_err"] = errs
+    # (3) tied-array beams from voltages: 64 pointings, 256 channels, 16384 samples, 4 x 16 lattice
+    wt = sg.make_workload("c5")
+    vt = sg.volts(wt, 0, 16384, backend="torch", device=dev)
+    plan = bf.Plan(n_ew=4, n_ns=16, n_chan=256, block=16, d_over_lambda=wt.d_over_lambda())
+    d = torch.from_numpy(sg.pointings(64, 11)).to(dev)
+    ms = _time_launches(lambda: bf.form_tied_beams_v(plan, vt, 0, 256, d), 5, warmup=1)
+    ex["tied_beams_v"] = {"workload": "4x16 lattice, 256 chan, 16384 samples, 64 pointings, |B|^2 over 16",
+                          "kernel_ms": ms, "beam_samples_per_s": 64 * 256 * 16384 / (ms / 1e3)}
+    plan.close()
+    return ex
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +181,8 @@ def main():
     ap.add_argument("--skip-extras", action="store_true", help="only the headline FP32 measurement")
     ap.add_argument("--skip-cpu", action="store_true", help="no CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration for HBM bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the path shards by frequency channel "
@@ -115,6 +197,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)    # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": src.numel() * 4, "launches": max(1, args.steps)}))
+        return
     w = sg.make_workload("c2")
     plan = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=w.m_ew, m_ns=w.m_ns, n_pol=w.n_pol, n_chan=w.n_chan,
                    block=w.block, ns_select=w.ns_select(), d_over_lambda=w.d_over_lambda())
@@ -183,18 +273,12 @@ def main():
         "generation_s": gen_s,
     }
 
-    if not args.skip_extras:
-        extras = {}
-        try:
-            from bench_extras import run_extras
-            extras = run_extras(volts, w, plan, out)
-        except ImportError:
-            pass
-        rec["extras"] = extras
-
     del volts, out
     plan.close()
     torch.cuda.empty_cache()
+    if not args.skip_extras:
+        rec["extras"] = run_extras(dev)
+        torch.cuda.empty_cache()
     if not args.skip_cpu:
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(rec))

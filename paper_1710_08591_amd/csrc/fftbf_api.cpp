@@ -186,6 +186,10 @@ bf_status bf_beamform_fft(const bf_plan* plan, const uint8_t* volts, int64_t n_t
                 (long long)n_time, d.block);
   if (kind == BF_OUT_COMPLEX && d.precision != BF_PREC_FP32)
     return fail(BF_ERR_UNSUPPORTED, "beamform_fft: complex beams are produced by FP32 plans only");
+  if (d.precision != BF_PREC_FP32 && taper)
+    return fail(BF_ERR_UNSUPPORTED, "beamform_fft: mixed-precision plans take no window (use an FP32 plan)");
+  if (d.precision != BF_PREC_FP32 && !aligned(volts, 16))
+    return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: mixed-precision plans need 16-byte aligned volts");
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n_blk = (n_time + d.block - 1) / d.block;
   const int n_pg = (kind == BF_OUT_INTENSITY && d.pol_sum) ? 1 : d.n_pol;

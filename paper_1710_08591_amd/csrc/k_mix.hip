@@ -1,12 +1,284 @@
-// Mixed-precision (MFMA) beamformer -- placeholder until the MFMA path lands.
+// Mixed-precision FFT beamformer on the MFMA units (gfx950).
+//
+// On the 4 x 16 lattice the N-S transform is one dense, zero-padded DFT (16
+// non-zero inputs -> M = 32 beams; eq. e:fftbeamform with the weights of eq.
+// e:w_A^a), so it runs as a matrix product on the matrix cores:
+//
+//   C[sample][beam] += A[sample][k] * B[k][beam],   k = (re|im, a_ns)
+//
+// A holds the raw int4 voltages of one E-W column (exact in FP16 and in FP8
+// e4m3); B holds the realified DFT coefficients, split into terms of the
+// working precision that accumulate into the same FP32 accumulators:
+//   FP16:  W = hi + lo                               (two passes)
+//   FP8:   W = hi + 2^-5 lo1 + 2^-9 lo2              (three passes; the
+//          power-of-two factor moves onto the exact data operand so that
+//          every coefficient term sits in the normal range of e4m3)
+// The N-S transform goes first so that the data operand stays exact (E-W
+// sums reach +-32, not all of which e4m3 holds); the E-W 4-point DFT
+// (twiddles +-1, +-i) then runs in FP32 on the accumulators, in-lane,
+// followed by |B|^2 and the block sum.
+//
+// v_mfma_f32_16x16x32_{f16,fp8_fp8} operands (lane l): A row = l % 16 (one
+// sample), B column = l % 16 (one beam), both holding k in
+// [8 (l/16), 8 (l/16) + 8); C holds column l % 16, rows 4 (l/16) + i.
 #include "dev_common.h"
 #include "kernels.h"
 
 namespace fftbf {
 
-bool mix_supported(int, int, int) { return false; }
-size_t mix_table_bytes(int, int) { return 0; }
-hipError_t launch_mix_tables(void*, int, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_mix(const MixArgs&, int, int, int64_t, hipStream_t) { return hipErrorNotSupported; }
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPrecFp16 = 1;
+constexpr int kPrecFp8 = 2;
+constexpr int kMixBlocksPerWave = 4;
+
+template <int PREC> struct Mix;
+template <> struct Mix<kPrecFp16> {
+  static constexpr int P = 2;
+  using op_t = half8;
+  static constexpr int kEntryBytes = 2;
+};
+template <> struct Mix<kPrecFp8> {
+  static constexpr int P = 3;
+  using op_t = long;
+  static constexpr int kEntryBytes = 1;
+};
+
+// data scale exponent of each FP8 term (the coefficient term carries 2^+s)
+__host__ __device__ constexpr int fp8_shift(int p) { return p == 0 ? 0 : (p == 1 ? 5 : 9); }
+
+// realified DFT coefficient B[k][n] of output part `part` (0 re, 1 im) for
+// beam k_out = kt*16 + n of the zero-padded 16 -> 32 N-S transform
+__device__ double mix_coef(int kt, int part, int k, int n) {
+  const int kout = kt * 16 + n;
+  const int comp = k >> 4, a = k & 15;
+  const int r = (kout * a) & 31;
+  double s, c;
+  sincospi(-2.0 * (double)r / 32.0, &s, &c);     // W = c + i s = exp(-i 2 pi r / 32)
+  if (part == 0) return comp == 0 ? c : -s;        // Re(W x) = c xr - s xi
+  return comp == 0 ? s : c;                        // Im(W x) = s xr + c xi
+}
+
+__device__ __forceinline__ float fp8_to_f32(int byte) {
+  return __builtin_amdgcn_cvt_f32_fp8(byte, 0);
+}
+__device__ __forceinline__ int f32_to_fp8(float v) {
+  return __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xFF;
+}
+
+// Table layout: [P][kt 2][part 2][lane 64][j 8], entry = term p of
+// B[k = 8 (lane/16) + j][n = lane % 16].
+template <int PREC>
+__global__ void k_mix_tables(void* tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * 2 * 64 * 8) return;
+  const int j = i & 7, lane = (i >> 3) & 63, part = (i >> 9) & 1, kt = (i >> 10) & 1;
+  const int k = 8 * (lane >> 4) + j, n = lane & 15;
+  const double v = mix_coef(kt, part, k, n);
+  constexpr int P = Mix<PREC>::P;
+  const int stride = 2 * 2 * 64 * 8;   // entries per term
+  if constexpr (PREC == kPrecFp16) {
+    _Float16* t = static_cast<_Float16*>(tab);
+    const _Float16 hi = (_Float16)(float)v;
+    const _Float16 lo = (_Float16)(float)(v - (double)(float)hi);
+    t[0 * stride + i] = hi;
+    t[1 * stride + i] = lo;
+  } else {
+    uint8_t* t = static_cast<uint8_t*>(tab);
+    double r = v;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double sc = (double)(1 << fp8_shift(p));
+      const int b = f32_to_fp8((float)(r * sc));
+      t[p * stride + i] = (uint8_t)b;
+      r -= (double)fp8_to_f32(b) / sc;
+    }
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ typename Mix<PREC>::op_t load_b(const void* tab, int p, int kt, int part, int lane) {
+  const int off = (((p * 2 + kt) * 2 + part) * 64 + lane) * 8;
+  if constexpr (PREC == kPrecFp16) {
+    return *reinterpret_cast<const half8*>(static_cast<const _Float16*>(tab) + off);
+  } else {
+    return *reinterpret_cast<const long*>(static_cast<const uint8_t*>(tab) + off);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x4 mfma(typename Mix<PREC>::op_t a, typename Mix<PREC>::op_t b, f32x4 c) {
+  if constexpr (PREC == kPrecFp16) return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ half8 to_f16(const int* v) {
+  half8 h;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h[j] = (_Float16)(float)v[j];
+  return h;
+}
+
+__device__ __forceinline__ long to_fp8(const int* v, float scale) {
+  int w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0] * scale, (float)v[1] * scale, 0, false);
+  w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2] * scale, (float)v[3] * scale, w0, true);
+  int w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[4] * scale, (float)v[5] * scale, 0, false);
+  w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[6] * scale, (float)v[7] * scale, w1, true);
+  return (long)(unsigned)w0 | ((long)(unsigned)w1 << 32);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
+  constexpr int P = Mix<PREC>::P;
+  using op_t = typename Mix<PREC>::op_t;
+  __shared__ float lds_i[4 * 32];
+
+  const int lane = threadIdx.x;
+  const int n = lane & 15, g = lane >> 4;
+  int wg = blockIdx.x;
+  const int pg = wg % a.n_pg;
+  wg /= a.n_pg;
+  const int chan = wg % a.n_chan;
+  const int run = wg / a.n_chan;
+  const int64_t n_blk = a.n_time / a.block;
+  const int64_t blk0 = (int64_t)run * kMixBlocksPerWave;
+  const int64_t blk1 = blk0 + kMixBlocksPerWave < n_blk ? blk0 + kMixBlocksPerWave : n_blk;
+
+  op_t B[P][2][2];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int part = 0; part < 2; ++part) B[p][kt][part] = load_b<PREC>(a.mat, p, kt, part, lane);
+
+  const int sh = (g >> 1) ? 0 : 4;            // real part: high nibble, imaginary: low
+  const int pol_lo = (a.pol_iter == 1) ? pg : 0;
+  const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
+  const int keep = a.n_keep;
+  const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
+
+  for (int64_t blk = blk0; blk < blk1; ++blk) {
+    float ia[4][2];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ia[e][0] = ia[e][1] = 0.f;
+
+    for (int pol = pol_lo; pol < pol_hi; ++pol) {
+      for (int sub = 0; sub < a.block; sub += 16) {
+        const int64_t t = blk * a.block + sub + n;
+        const uint4* fr = reinterpret_cast<const uint4*>(a.volts + ((t * a.n_chan + chan) * a.n_pol + pol) * 16);
+        const uint4 d0 = fr[2 * (g & 1)], d1 = fr[2 * (g & 1) + 1];
+        const uint32_t dw[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+
+        f32x4 acc[4][2][2];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          int v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = (int)__builtin_amdgcn_sbfe((int)dw[j], 8 * c + sh, 4);
+#pragma unroll
+          for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int part = 0; part < 2; ++part) acc[c][kt][part] = f32x4{0.f, 0.f, 0.f, 0.f};
+          if constexpr (PREC == kPrecFp16) {
+            const op_t A = to_f16(v);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+              for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int part = 0; part < 2; ++part)
+                  acc[c][kt][part] = mfma<PREC>(A, B[p][kt][part], acc[c][kt][part]);
+          } else {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              const op_t A = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
+#pragma unroll
+              for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int part = 0; part < 2; ++part)
+                  acc[c][kt][part] = mfma<PREC>(A, B[p][kt][part], acc[c][kt][part]);
+            }
+          }
+        }
+
+        // E-W 4-point DFT across the four columns, |B|^2, sum of the lane's 4 samples
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float y0r = acc[0][kt][0][i], y0i = acc[0][kt][1][i];
+            const float y1r = acc[1][kt][0][i], y1i = acc[1][kt][1][i];
+            const float y2r = acc[2][kt][0][i], y2i = acc[2][kt][1][i];
+            const float y3r = acc[3][kt][0][i], y3i = acc[3][kt][1][i];
+            const float s02r = y0r + y2r, s02i = y0i + y2i, d02r = y0r - y2r, d02i = y0i - y2i;
+            const float s13r = y1r + y3r, s13i = y1i + y3i, d13r = y1r - y3r, d13i = y1i - y3i;
+            ia[0][kt] += cnorm(cf{s02r + s13r, s02i + s13i});
+            ia[2][kt] += cnorm(cf{s02r - s13r, s02i - s13i});
+            ia[1][kt] += cnorm(cf{d02r + d13i, d02i - d13r});
+            ia[3][kt] += cnorm(cf{d02r - d13i, d02i + d13r});
+          }
+        }
+      }
+    }
+
+    // sum the four sample groups (lanes l, l^16, l^32, l^48)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {
+        float v = ia[e][kt];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        ia[e][kt] = v;
+      }
+    if (g == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) lds_i[e * 32 + kt * 16 + n] = ia[e][kt] * a.norm;
+    }
+    __syncthreads();
+    float* o = a.out + ((blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
+    for (int idx = lane; idx < 4 * keep; idx += 64) {
+      const int e = idx / keep, j = idx - e * keep;
+      o[idx] = lds_i[e * 32 + (sel ? sel[j] : j)];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+bool mix_supported(int n_ns, int prec, int block) {
+  return n_ns == 16 && (prec == kPrecFp16 || prec == kPrecFp8) && block % 16 == 0;
+}
+
+size_t mix_table_bytes(int n_ns, int prec) {
+  (void)n_ns;
+  return prec == kPrecFp16 ? (size_t)Mix<kPrecFp16>::P * 2048 * 2 : (size_t)Mix<kPrecFp8>::P * 2048;
+}
+
+hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
+  if (!mix_supported(n_ns, prec, 16)) return hipErrorNotSupported;
+  if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix_tables<kPrecFp16>, dim3(8), dim3(256), 0, s, mat);
+  else hipLaunchKernelGGL(k_mix_tables<kPrecFp8>, dim3(8), dim3(256), 0, s, mat);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t, hipStream_t s) {
+  if (!mix_supported(n_ns, prec, a.block) || a.taper) return hipErrorNotSupported;
+  const int64_t n_blk = a.n_time / a.block;
+  const int64_t n_run = (n_blk + kMixBlocksPerWave - 1) / kMixBlocksPerWave;
+  const int64_t n_wg = n_run * a.n_chan * a.n_pg;
+  if (n_wg == 0) return hipSuccess;
+  if (n_wg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
+  if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix16<kPrecFp16>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL(k_mix16<kPrecFp8>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
 
 }  // namespace fftbf
