@@ -167,6 +167,80 @@ bf_status bf_form_tied_beams_v(const bf_plan *plan, const uint8_t *volts, int64_
 bf_status bf_accumulate_intensity(const void *z, int64_t n_time, int64_t n_series,
                                   int32_t block, int32_t add, float *out, void *stream);
 
+/*
+ * ---- Tied-beam server --------------------------------------------------
+ * Serves tied-array beam requests (arbitrary pointings, a contiguous channel
+ * range, the most recent n_time samples) from a device-resident voltage ring
+ * of the 4 x 16 lattice.  The beams are the interpolated FFT beams of
+ * bf_form_tied_beams_v; pointed beams formed from FFT beams are the use the
+ * paper gives for the regridding of eq. e:bp_max_arbitrary (Sec. "Discussion
+ * and Conclusions": tied-array beams from FFT beams).
+ *
+ * Requests are admitted against a fixed device-memory budget (outputs and
+ * pointing tables live in one pool of hbm_budget bytes), cut into tiles
+ * (channel x up to 64 pointings x blocks_per_tile blocks of 16 samples) and
+ * batched -- round robin over the active requests, at most
+ * max_tiles_per_launch tiles and two launches in flight -- into launches of
+ * a persistent tile worker on the server's own stream.  Requests that arrive
+ * while others run join at the next launch.  A tile's arithmetic does not
+ * depend on the batch, so a result is bitwise the same alone and in a mix.
+ * The ring holds the last ring_samples samples; a request's window is
+ * leased until it finishes and bf_server_advance refuses to overwrite it.
+ * Host calls are not thread safe: drive one server from one thread.
+ */
+typedef struct bf_server bf_server;
+
+typedef struct {
+  int64_t submitted, completed, rejected, evicted, in_flight;
+  int64_t budget_used;   /* bytes of the pool in use */
+  int64_t tiles_done, launches;
+} bf_server_stats;
+
+/* plan: FP32, n_ew = 4, n_ns = 16, m_ns = 32, block 16, pol_sum 0.
+ * ring_samples: multiple of 16.  Allocates the ring (ring_samples x n_chan x
+ * n_pol x 64 bytes, zero filled) and the pool (hbm_budget bytes).  The plan
+ * may be destroyed afterwards.  Errors: INVALID_ARGUMENT, UNSUPPORTED,
+ * OUT_OF_MEMORY, DEVICE. */
+bf_status bf_server_create(const bf_plan *plan, int64_t ring_samples, int64_t hbm_budget,
+                           int32_t blocks_per_tile, int32_t max_tiles_per_launch, bf_server **srv);
+/* Drain the server's stream and free everything. */
+bf_status bf_server_destroy(bf_server *srv);
+/* Device ring [ring_samples][n_chan][n_pol][16][4] uint8, its length, and
+ * the head (samples written so far; sample s lives in slot s mod ring). */
+bf_status bf_server_ring(bf_server *srv, void **ring, int64_t *ring_samples, int64_t *head);
+/* The writer appends n_samples: copies them from device src (or, if src is
+ * NULL, takes the ring contents as already written) and advances the head.
+ * Returns BF_ERR_NOT_READY without change if that would overwrite a leased
+ * window, unless force != 0 (then those requests end as BF_ERR_EVICTED). */
+bf_status bf_server_advance(bf_server *srv, int64_t n_samples, const uint8_t *src, int32_t force);
+/* Admit a request for the n_time samples before the head (n_time a multiple
+ * of 16, at most ring_samples), channels [chan_lo, chan_lo + n_chan),
+ * n_point pointings given as host double [n_point][2] direction cosines
+ * (copied).  arrival_s is the request's arrival time on bf_server_now's
+ * clock (latency is measured from it).  Errors: INVALID_ARGUMENT,
+ * EVICTED (window not in the ring), REJECTED (over the memory budget). */
+bf_status bf_server_submit(bf_server *srv, int32_t n_point, int32_t chan_lo, int32_t n_chan,
+                           int64_t n_time, const double *dircos, double arrival_s, int64_t *id);
+/* Retire finished launches and issue new ones; never blocks. */
+bf_status bf_server_pump(bf_server *srv);
+/* BF_OK when finished (latency_s = completion - arrival), BF_ERR_NOT_READY
+ * while running, BF_ERR_EVICTED, or BF_ERR_INVALID_ARGUMENT (unknown or
+ * cancelled). */
+bf_status bf_server_poll(bf_server *srv, int64_t id, double *latency_s);
+/* Device pointer to a finished request's intensities
+ * float [n_time/16][n_chan][n_pol][n_point], valid until released. */
+bf_status bf_server_result(bf_server *srv, int64_t id, float **out, int64_t *n_floats);
+/* Copy a finished result into caller device memory dst on stream. */
+bf_status bf_server_copy_result(bf_server *srv, int64_t id, float *dst, void *stream);
+/* Return a finished, cancelled or evicted request's memory to the pool
+ * (BF_ERR_NOT_READY while its tiles are still on the device). */
+bf_status bf_server_release(bf_server *srv, int64_t id);
+/* Stop issuing a request's remaining tiles. */
+bf_status bf_server_cancel(bf_server *srv, int64_t id);
+bf_status bf_server_stats_get(bf_server *srv, bf_server_stats *st);
+/* Seconds on the server's monotonic clock. */
+double bf_server_now(bf_server *srv);
+
 /* Static description of a status code. */
 const char *bf_status_string(int32_t status);
 

@@ -13,14 +13,14 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import (BF_OK, BF_ERR_INVALID_ARGUMENT, BF_ERR_UNSUPPORTED, BF_ERR_OUT_OF_MEMORY,
+from ._lib import (bf_server_stats, BF_OK, BF_ERR_INVALID_ARGUMENT, BF_ERR_UNSUPPORTED, BF_ERR_OUT_OF_MEMORY,
                    BF_ERR_DEVICE, BF_ERR_REJECTED, BF_ERR_EVICTED, BF_ERR_NOT_READY,
                    BF_PREC_FP32, BF_PREC_FP16_MFMA, BF_PREC_FP8_MFMA, BF_OUT_INTENSITY,
                    BF_OUT_COMPLEX, BFError, LibraryMissing, bf_plan_desc, check, lib)
 
 __all__ = [
     "Plan", "plan_create", "plan_destroy", "beamform_fft", "form_tied_beams", "form_tied_beams_v",
-    "accumulate_intensity", "lib", "BFError", "LibraryMissing",
+    "accumulate_intensity", "Server", "lib", "BFError", "LibraryMissing",
     "BF_PREC_FP32", "BF_PREC_FP16_MFMA", "BF_PREC_FP8_MFMA", "BF_OUT_INTENSITY", "BF_OUT_COMPLEX",
 ]
 
@@ -231,3 +231,112 @@ def accumulate_intensity(z, block: int, out=None, add: bool = False, stream=None
     check(lib().bf_accumulate_intensity(_ptr(z), n_time, n_series, block, int(add), _ptr(out),
                                         _stream_handle(stream)), "bf_accumulate_intensity")
     return out
+
+
+class Server:
+    """Tied-beam server over a device voltage ring (bf_server_*).
+
+    ``plan`` must be an FP32 4 x 16 lattice plan with block 16.  Requests are
+    admitted against ``hbm_budget`` bytes of device memory and executed by
+    batched launches on the server's own stream; call ``pump()`` often.
+    """
+
+    def __init__(self, plan: Plan, ring_samples: int = 65536, hbm_budget: int = 16 << 30,
+                 blocks_per_tile: int = 16, max_tiles_per_launch: int = 8192):
+        h = C.c_void_p()
+        check(lib().bf_server_create(plan.handle, ring_samples, hbm_budget, blocks_per_tile,
+                                     max_tiles_per_launch, C.byref(h)), "bf_server_create")
+        self.handle = h
+        self.n_chan, self.n_pol = plan.n_chan, plan.n_pol
+        self.ring_samples = ring_samples
+        self._shapes = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bf_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def now(self) -> float:
+        return lib().bf_server_now(self.handle)
+
+    def ring(self):
+        """(device pointer, ring_samples, head)."""
+        p, n, h = C.c_void_p(), C.c_int64(), C.c_int64()
+        check(lib().bf_server_ring(self.handle, C.byref(p), C.byref(n), C.byref(h)), "bf_server_ring")
+        return p.value, n.value, h.value
+
+    def advance(self, n_samples: int, src=None, force: bool = False) -> int:
+        """Append samples (uint8 tensor [n][n_chan][n_pol][16][4] on the GPU, or None)."""
+        if src is not None:
+            _need(src, _torch().uint8, "src")
+            if src.shape[0] != n_samples:
+                raise ValueError("src must hold n_samples samples")
+        return lib().bf_server_advance(self.handle, n_samples, _ptr(src), int(force))
+
+    def submit(self, dircos: np.ndarray, chan_lo: int, n_chan: int, n_time: int,
+               arrival: Optional[float] = None) -> int:
+        d = np.ascontiguousarray(dircos, dtype=np.float64)
+        if d.ndim != 2 or d.shape[1] != 2:
+            raise ValueError("dircos must be [n_point][2]")
+        rid = C.c_int64()
+        t = self.now() if arrival is None else float(arrival)
+        st = lib().bf_server_submit(self.handle, d.shape[0], chan_lo, n_chan, n_time,
+                                    d.ctypes.data_as(C.c_void_p), t, C.byref(rid))
+        check(st, "bf_server_submit")
+        self._shapes[rid.value] = (n_time // 16, n_chan, self.n_pol, d.shape[0])
+        return rid.value
+
+    def try_submit(self, dircos, chan_lo, n_chan, n_time, arrival=None):
+        """Like submit, but returns (status, id) instead of raising."""
+        try:
+            return BF_OK, self.submit(dircos, chan_lo, n_chan, n_time, arrival)
+        except BFError as e:
+            return e.status, 0
+
+    def pump(self) -> None:
+        check(lib().bf_server_pump(self.handle), "bf_server_pump")
+
+    def poll(self, rid: int):
+        """(status, latency seconds): BF_OK when finished, BF_ERR_NOT_READY while running."""
+        lat = C.c_double(-1.0)
+        st = lib().bf_server_poll(self.handle, rid, C.byref(lat))
+        return st, lat.value
+
+    def result(self, rid: int):
+        """Copy a finished request's intensities into a new tensor [blk][chan][pol][point]."""
+        torch = _torch()
+        out = torch.empty(self._shapes[rid], dtype=torch.float32, device="cuda")
+        check(lib().bf_server_copy_result(self.handle, rid, _ptr(out), _stream_handle()), "bf_server_copy_result")
+        return out
+
+    def release(self, rid: int) -> int:
+        st = lib().bf_server_release(self.handle, rid)
+        if st == BF_OK:
+            self._shapes.pop(rid, None)
+        return st
+
+    def cancel(self, rid: int) -> None:
+        check(lib().bf_server_cancel(self.handle, rid), "bf_server_cancel")
+
+    def stats(self) -> dict:
+        s = bf_server_stats()
+        check(lib().bf_server_stats_get(self.handle, C.byref(s)), "bf_server_stats_get")
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def wait(self, rid: int, timeout_s: float = 60.0):
+        """Pump until the request finishes; returns (status, latency)."""
+        import time
+        t0 = time.perf_counter()
+        while True:
+            self.pump()
+            st, lat = self.poll(rid)
+            if st != BF_ERR_NOT_READY:
+                return st, lat
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"request {rid} not finished after {timeout_s} s")

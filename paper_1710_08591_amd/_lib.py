@@ -61,20 +61,23 @@ _SIGS = {
                                          _P, _P]),
     "bf_accumulate_intensity": (C.c_int32, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P, _P]),
 }
-_OPTIONAL = {
+_SIGS.update({
     "bf_server_create": (C.c_int32, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)]),
     "bf_server_destroy": (C.c_int32, [_P]),
-    "bf_server_ring": (C.c_int32, [_P, C.POINTER(_P), C.POINTER(C.c_int64)]),
-    "bf_server_advance": (C.c_int32, [_P, C.c_int64, _P]),
-    "bf_server_submit": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int64, _P, C.c_int32, _P,
+    "bf_server_ring": (C.c_int32, [_P, C.POINTER(_P), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "bf_server_advance": (C.c_int32, [_P, C.c_int64, _P, C.c_int32]),
+    "bf_server_submit": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, _P, C.c_double,
                                      C.POINTER(C.c_int64)]),
+    "bf_server_pump": (C.c_int32, [_P]),
     "bf_server_poll": (C.c_int32, [_P, C.c_int64, C.POINTER(C.c_double)]),
+    "bf_server_result": (C.c_int32, [_P, C.c_int64, C.POINTER(_P), C.POINTER(C.c_int64)]),
+    "bf_server_copy_result": (C.c_int32, [_P, C.c_int64, _P, _P]),
     "bf_server_release": (C.c_int32, [_P, C.c_int64]),
     "bf_server_cancel": (C.c_int32, [_P, C.c_int64]),
-    "bf_server_pump": (C.c_int32, [_P]),
     "bf_server_stats_get": (C.c_int32, [_P, C.POINTER(bf_server_stats)]),
-    "bf_request_out_bytes": (C.c_int64, [_P, C.c_int32, C.c_int32, C.c_int64]),
-}
+    "bf_server_now": (C.c_double, [_P]),
+})
+_OPTIONAL = {}
 
 
 class LibraryMissing(RuntimeError):

@@ -79,6 +79,8 @@ const char* bf_status_string(int32_t s) {
 
 const char* bf_last_error(void) { return g_err.c_str(); }
 
+__attribute__((visibility("hidden"))) void bf_internal_set_error(const char* msg) { g_err = msg ? msg : ""; }
+
 bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
   if (!desc || !plan) return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: NULL desc or plan");
   *plan = nullptr;
@@ -160,6 +162,11 @@ bf_status bf_plan_destroy(bf_plan* plan) {
   free_plan(plan);
   if (e != hipSuccess) return dev_fail(e, "plan_destroy: pending device error");
   return BF_OK;
+}
+
+__attribute__((visibility("hidden"))) const double* bf_internal_plan_dl(const bf_plan* plan, bf_plan_desc* desc) {
+  *desc = plan->d;
+  return plan->dl;
 }
 
 bf_status bf_plan_get_desc(const bf_plan* plan, bf_plan_desc* desc) {

@@ -39,12 +39,10 @@ template <int PREC> struct Mix;
 template <> struct Mix<kPrecFp16> {
   static constexpr int P = 2;
   using op_t = half8;
-  static constexpr int kEntryBytes = 2;
 };
 template <> struct Mix<kPrecFp8> {
   static constexpr int P = 3;
   using op_t = long;
-  static constexpr int kEntryBytes = 1;
 };
 
 // data scale exponent of each FP8 term (the coefficient term carries 2^+s)

@@ -122,9 +122,78 @@ __global__ __launch_bounds__(64) void k_tied(TiedArgs a) {
 // (sample, E-W beam): two signed 4-bit dot products per N-S position for the
 // E-W DFT, then the zero-padded 32-point N-S DFT in registers), then every
 // lane interpolates its own pointing from LDS broadcasts.
+constexpr int kV16N = 16, kV16M = 32, kV16TS = 16;
+
+struct V16Lane {
+  int ts, e, wre, wim;
+};
+
+__device__ __forceinline__ V16Lane v16_lane(int lane) {
+  V16Lane l;
+  l.ts = lane >> 2;
+  l.e = lane & 3;
+  l.wre = 0;
+  l.wim = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = (l.e * q) & 3;
+    const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
+    if (k == 0) { l.wre |= 1 << sr;   l.wim |= 1 << si; }
+    if (k == 1) { l.wre |= 1 << si;   l.wim |= 0xF << sr; }
+    if (k == 2) { l.wre |= 0xF << sr; l.wim |= 0xF << si; }
+    if (k == 3) { l.wre |= 0xF << si; l.wim |= 1 << sr; }
+  }
+  return l;
+}
+
+// FFT beams of the 16 samples whose frames the lanes point at (lane's frame =
+// sample l.ts) into lds_b[sample][e][A], normalised by 1/sqrt(64).
+template <bool TAPER>
+__device__ __forceinline__ void v16_fft_to_lds(const uint32_t* __restrict__ src, const V16Lane& l,
+                                               const float* lds_h, cf* lds_b) {
+  constexpr int N = kV16N, MNS = kV16M;
+  cf x[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const uint32_t d = src[j];
+    if constexpr (TAPER) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = (l.e * q) & 3;
+        const float h = lds_h[j * 4 + q];
+        const float xr = (float)(int)__builtin_amdgcn_sbfe((int)d, 8 * q + 4, 4) * h;
+        const float xi = (float)(int)__builtin_amdgcn_sbfe((int)d, 8 * q, 4) * h;
+        // x * (-i)^k
+        const float ur = (k == 0) ? xr : (k == 1) ? xi : (k == 2) ? -xr : -xi;
+        const float ui = (k == 0) ? xi : (k == 1) ? -xr : (k == 2) ? -xi : xr;
+        re += ur;
+        im += ui;
+      }
+      x[j] = cf{re, im};
+    } else {
+      x[j] = cf{(float)__builtin_amdgcn_sdot8((int)d, l.wre, 0, false),
+                (float)__builtin_amdgcn_sdot8((int)d, l.wim, 0, false)};
+    }
+  }
+  cf y[MNS];
+  padded_dft<N>(x, y);
+  cf* row = &lds_b[(l.ts * 4 + l.e) * MNS];
+  const float nrm = 0.125f;   // 1/sqrt(4 * 16)
+#pragma unroll
+  for (int k = 0; k < MNS; ++k) row[k] = cf{y[k].r * nrm, y[k].i * nrm};
+}
+
+// sum over the 16 samples in LDS of |B_p|^2 for this lane's pointing
+__device__ __forceinline__ float v16_interp_block(const cf* lds_b, const cf* cew, const cf* cns) {
+  float acc = 0.f;
+  for (int s = 0; s < kV16TS; ++s) acc += cnorm(interp_one<kV16M>(&lds_b[s * 4 * kV16M], cew, cns));
+  return acc;
+}
+
 template <bool TAPER>
 __global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
-  constexpr int N = 16, MNS = 32, TS = 16;
+  constexpr int N = kV16N, MNS = kV16M, TS = kV16TS;
   __shared__ cf lds_b[TS * 4 * MNS];
   __shared__ float lds_h[TAPER ? N * 4 : 1];
   const int lane = threadIdx.x;
@@ -148,18 +217,7 @@ __global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
     interp_weights<4>(dl_ew * a.dircos[2 * pp], 4, cew);
     interp_weights<MNS>(dl_ns * a.dircos[2 * pp + 1], N, cns);
   }
-  // FFT role of this lane: sample ts, E-W beam e
-  const int ts = lane >> 2, e = lane & 3;
-  int wre = 0, wim = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int k = (e * q) & 3;
-    const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
-    if (k == 0) { wre |= 1 << sr;   wim |= 1 << si; }
-    if (k == 1) { wre |= 1 << si;   wim |= 0xF << sr; }
-    if (k == 2) { wre |= 0xF << sr; wim |= 0xF << si; }
-    if (k == 3) { wre |= 0xF << si; wim |= 1 << sr; }
-  }
+  const V16Lane l = v16_lane(lane);
   __syncthreads();
 
   const int pol_lo = a.pol_sum ? 0 : pg, pol_hi = a.pol_sum ? a.n_pol : pg + 1;
@@ -167,46 +225,15 @@ __global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
   const int64_t t0 = (int64_t)trun * span;
   const int64_t t1 = t0 + span < a.n_time ? t0 + span : a.n_time;
   const int64_t frame_dw = (int64_t)a.n_chan * a.n_pol * N;   // dwords per sample
-  const float nrm = 0.125f;                                   // 1/sqrt(4*16)
 
   for (int64_t tb = t0; tb < t1; tb += a.block) {
     float acc = 0.f;
     for (int tg = 0; tg < a.block; tg += TS) {
       for (int pol = pol_lo; pol < pol_hi; ++pol) {
-        // ---- FFT beams of samples tb+tg .. +15 into LDS ----
-        const uint32_t* src = a.volts + (tb + tg + ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * N;
-        cf x[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          const uint32_t d = src[j];
-          if constexpr (TAPER) {
-            float re = 0.f, im = 0.f;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int k = (e * q) & 3;
-              const float h = lds_h[j * 4 + q];
-              const float xr = (float)(int)__builtin_amdgcn_sbfe((int)d, 8 * q + 4, 4) * h;
-              const float xi = (float)(int)__builtin_amdgcn_sbfe((int)d, 8 * q, 4) * h;
-              // x * (-i)^k
-              const float ur = (k == 0) ? xr : (k == 1) ? xi : (k == 2) ? -xr : -xi;
-              const float ui = (k == 0) ? xi : (k == 1) ? -xr : (k == 2) ? -xi : xr;
-              re += ur;
-              im += ui;
-            }
-            x[j] = cf{re, im};
-          } else {
-            x[j] = cf{(float)__builtin_amdgcn_sdot8((int)d, wre, 0, false),
-                      (float)__builtin_amdgcn_sdot8((int)d, wim, 0, false)};
-          }
-        }
-        cf y[MNS];
-        padded_dft<N>(x, y);
-        cf* row = &lds_b[(ts * 4 + e) * MNS];
-#pragma unroll
-        for (int k = 0; k < MNS; ++k) row[k] = cf{y[k].r * nrm, y[k].i * nrm};
+        const uint32_t* src = a.volts + (tb + tg + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * N;
+        v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b);
         __syncthreads();
-        // ---- interpolate this lane's pointing for the 16 samples ----
-        for (int s = 0; s < TS; ++s) acc += cnorm(interp_one<MNS>(&lds_b[s * 4 * MNS], cew, cns));
+        acc += v16_interp_block(lds_b, cew, cns);
         __syncthreads();
       }
     }
@@ -214,6 +241,48 @@ __global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
       const int64_t blk = tb / a.block;
       float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
       *o = acc;
+    }
+  }
+}
+
+// Persistent tile worker of the tied-beam server: each workgroup takes tiles
+// (request, channel, 64 pointings, run of 16-sample blocks) from the batch,
+// reading voltages from the device ring (absolute sample s lives in slot
+// s mod ring_samples).  A tile's arithmetic is the same as k_tied_v16's and
+// does not depend on which other tiles share the launch.
+__global__ __launch_bounds__(64) void k_serve(const ServeTile* __restrict__ tiles, int n_tiles,
+                                              const uint32_t* __restrict__ ring, int64_t ring_samples,
+                                              int n_chan, int n_pol, const double* __restrict__ dl) {
+  constexpr int N = kV16N, MNS = kV16M, TS = kV16TS;
+  __shared__ cf lds_b[TS * 4 * MNS];
+  const int lane = threadIdx.x;
+  const V16Lane l = v16_lane(lane);
+  const int64_t frame_dw = (int64_t)n_chan * n_pol * N;
+  for (int ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+    const ServeTile t = tiles[ti];
+    const int p = t.ptile * 64 + lane;
+    const bool live = p < t.n_point;
+    const int pp = live ? p : t.n_point - 1;
+    cf cew[4], cns[MNS];
+    {
+      const double dl_ew = dl[2 * t.chan], dl_ns = dl[2 * t.chan + 1];
+      interp_weights<4>(dl_ew * t.dircos[2 * pp], 4, cew);
+      interp_weights<MNS>(dl_ns * t.dircos[2 * pp + 1], N, cns);
+    }
+    for (int b = 0; b < t.n_blk; ++b) {
+      const int64_t s0 = t.t_start + (int64_t)(t.blk0 + b) * TS;
+      for (int pol = 0; pol < n_pol; ++pol) {
+        const int64_t slot = (s0 + l.ts) % ring_samples;
+        const uint32_t* src = ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * N;
+        v16_fft_to_lds<false>(src, l, nullptr, lds_b);
+        __syncthreads();
+        const float acc = v16_interp_block(lds_b, cew, cns);
+        __syncthreads();
+        if (live) {
+          const int64_t ob = t.blk0 + b;
+          t.out[((ob * t.n_chan_req + (t.chan - t.chan_lo)) * n_pol + pol) * (int64_t)t.n_point + p] = acc;
+        }
+      }
     }
   }
 }
@@ -230,6 +299,14 @@ hipError_t launch_tied(const TiedArgs& a, hipStream_t s) {
   if (a.m_ns == 32) hipLaunchKernelGGL(k_tied<32>, grid, dim3(64), 0, s, a);
   else if (a.m_ns == 64) hipLaunchKernelGGL(k_tied<64>, grid, dim3(64), 0, s, a);
   else return hipErrorNotSupported;
+  return hipGetLastError();
+}
+
+hipError_t launch_serve(const ServeTile* tiles, int n_tiles, const uint32_t* ring, int64_t ring_samples,
+                        int n_chan, int n_pol, const double* dl, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  const int grid = n_tiles < 8192 ? n_tiles : 8192;
+  hipLaunchKernelGGL(k_serve, dim3(grid), dim3(64), 0, s, tiles, n_tiles, ring, ring_samples, n_chan, n_pol, dl);
   return hipGetLastError();
 }
 

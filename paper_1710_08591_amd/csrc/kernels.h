@@ -51,6 +51,17 @@ struct TiedArgs {
   void* out;
 };
 hipError_t launch_tied(const TiedArgs& a, hipStream_t s);
+
+// one tile of the tied-beam server (4 x 16 lattice, 16-sample blocks)
+struct ServeTile {
+  const double* dircos;    // request pointings [n_point][2]
+  float* out;              // request output [n_blk][n_chan_req][n_pol][n_point]
+  int64_t t_start;         // absolute sample index of the request window start
+  int32_t n_point, n_chan_req, chan_lo, chan;
+  int32_t ptile, blk0, n_blk, pad;
+};
+hipError_t launch_serve(const ServeTile* tiles, int n_tiles, const uint32_t* ring, int64_t ring_samples,
+                        int n_chan, int n_pol, const double* dl, hipStream_t s);
 hipError_t launch_tied_v(const TiedArgs& a, hipStream_t s);
 
 // mixed-precision (MFMA) beamformer
