@@ -208,11 +208,14 @@ bf_status bf_server_destroy(bf_server *srv);
 /* Device ring [ring_samples][n_chan][n_pol][16][4] uint8, its length, and
  * the head (samples written so far; sample s lives in slot s mod ring). */
 bf_status bf_server_ring(bf_server *srv, void **ring, int64_t *ring_samples, int64_t *head);
-/* The writer appends n_samples: copies them from device src (or, if src is
- * NULL, takes the ring contents as already written) and advances the head.
- * Returns BF_ERR_NOT_READY without change if that would overwrite a leased
- * window, unless force != 0 (then those requests end as BF_ERR_EVICTED). */
-bf_status bf_server_advance(bf_server *srv, int64_t n_samples, const uint8_t *src, int32_t force);
+/* The writer appends n_samples: copies them from device src, produced on
+ * `stream` (the copy waits for that stream, and that stream waits for the
+ * copy), or, if src is NULL, takes the ring contents as already written;
+ * then advances the head.  Returns BF_ERR_NOT_READY without change if that
+ * would overwrite a leased window, unless force != 0 (then those requests
+ * end as BF_ERR_EVICTED). */
+bf_status bf_server_advance(bf_server *srv, int64_t n_samples, const uint8_t *src, int32_t force,
+                            void *stream);
 /* Admit a request for the n_time samples before the head (n_time a multiple
  * of 16, at most ring_samples), channels [chan_lo, chan_lo + n_chan),
  * n_point pointings given as host double [n_point][2] direction cosines

@@ -277,7 +277,7 @@ class Server:
             _need(src, _torch().uint8, "src")
             if src.shape[0] != n_samples:
                 raise ValueError("src must hold n_samples samples")
-        return lib().bf_server_advance(self.handle, n_samples, _ptr(src), int(force))
+        return lib().bf_server_advance(self.handle, n_samples, _ptr(src), int(force), _stream_handle())
 
     def submit(self, dircos: np.ndarray, chan_lo: int, n_chan: int, n_time: int,
                arrival: Optional[float] = None) -> int:

@@ -65,7 +65,7 @@ _SIGS.update({
     "bf_server_create": (C.c_int32, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)]),
     "bf_server_destroy": (C.c_int32, [_P]),
     "bf_server_ring": (C.c_int32, [_P, C.POINTER(_P), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
-    "bf_server_advance": (C.c_int32, [_P, C.c_int64, _P, C.c_int32]),
+    "bf_server_advance": (C.c_int32, [_P, C.c_int64, _P, C.c_int32, _P]),
     "bf_server_submit": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, _P, C.c_double,
                                      C.POINTER(C.c_int64)]),
     "bf_server_pump": (C.c_int32, [_P]),

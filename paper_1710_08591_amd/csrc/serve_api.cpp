@@ -50,6 +50,8 @@ class HipBackend final : public fftbf::serve::Backend {
       if (host_[i]) (void)hipHostFree(host_[i]);
       if (dev_[i]) (void)hipFree(dev_[i]);
     }
+    if (ev_in_) (void)hipEventDestroy(ev_in_);
+    if (ev_out_) (void)hipEventDestroy(ev_out_);
     if (pool_) (void)hipFree(pool_);
     if (ring_) (void)hipFree(ring_);
     if (dl_) (void)hipFree(dl_);
@@ -74,6 +76,8 @@ class HipBackend final : public fftbf::serve::Backend {
       if (e == hipSuccess) e = hipMalloc(&dev_[i], sizeof(fftbf::ServeTile) * max_tiles);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_out_, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamSynchronize(stream_);
     t0_ = std::chrono::steady_clock::now();
     return e;
@@ -131,6 +135,7 @@ class HipBackend final : public fftbf::serve::Backend {
   }
 
   hipStream_t stream_ = nullptr;
+  hipEvent_t ev_in_ = nullptr, ev_out_ = nullptr;   // ordering against a caller's stream
   void* ring_ = nullptr;
   void* pool_ = nullptr;
   double* dl_ = nullptr;
@@ -216,7 +221,7 @@ bf_status bf_server_ring(bf_server* srv, void** ring, int64_t* ring_samples, int
   return BF_OK;
 }
 
-bf_status bf_server_advance(bf_server* srv, int64_t n_samples, const uint8_t* src, int32_t force) {
+bf_status bf_server_advance(bf_server* srv, int64_t n_samples, const uint8_t* src, int32_t force, void* stream) {
   if (!srv || n_samples < 0) return sfail(BF_ERR_INVALID_ARGUMENT, "server_advance: bad argument");
   if (src && n_samples > srv->ring_samples)
     return sfail(BF_ERR_INVALID_ARGUMENT, "server_advance: more samples than the ring holds");
@@ -225,7 +230,13 @@ bf_status bf_server_advance(bf_server* srv, int64_t n_samples, const uint8_t* sr
   if (r != fftbf::serve::kOk) return sfail(map_status(r), srv->sched->last_error);
   if (src && n_samples) {
     // copy into slots head mod ring .. (wrapping), on the server stream so the
-    // data lands before any later batch reads it
+    // data lands before any later batch reads it; the copy waits for the
+    // caller's stream (where src was produced) and the caller's stream waits
+    // for the copy (so src may be reused after the call on that stream)
+    const hipStream_t cs = static_cast<hipStream_t>(stream);
+    hipError_t e0 = hipEventRecord(srv->be.ev_in_, cs);
+    if (e0 == hipSuccess) e0 = hipStreamWaitEvent(srv->be.stream_, srv->be.ev_in_, 0);
+    if (e0 != hipSuccess) return sfail(BF_ERR_DEVICE, std::string("server_advance: ") + hipGetErrorString(e0));
     const size_t sb = srv->be.sample_bytes();
     int64_t done = 0;
     while (done < n_samples) {
@@ -236,6 +247,9 @@ bf_status bf_server_advance(bf_server* srv, int64_t n_samples, const uint8_t* sr
       if (e != hipSuccess) return sfail(BF_ERR_DEVICE, std::string("server_advance: ") + hipGetErrorString(e));
       done += n;
     }
+    e0 = hipEventRecord(srv->be.ev_out_, srv->be.stream_);
+    if (e0 == hipSuccess) e0 = hipStreamWaitEvent(cs, srv->be.ev_out_, 0);
+    if (e0 != hipSuccess) return sfail(BF_ERR_DEVICE, std::string("server_advance: ") + hipGetErrorString(e0));
   }
   return BF_OK;
 }
