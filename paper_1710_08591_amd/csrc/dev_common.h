@@ -109,10 +109,92 @@ constexpr int bitrev(int k, int n) {
   return r;
 }
 
+// ---- in-register radix-2 decimation-in-time ------------------------------
+// Butterfly a' = a + W b, b' = a - W b with W = W_M^K fixed at compile time.
+// A general twiddle is factored as W = c (1 + i t), t = s/c (|c| >= |s|), or
+// W = s (u + i), u = c/s (otherwise), so that W b costs two fused
+// multiply-adds and the outer factor folds into the butterfly's own four
+// fused multiply-adds: 6 operations instead of 8.
+constexpr double cx_abs(double v) { return v < 0 ? -v : v; }
+
+template <int K, int M>
+__device__ __forceinline__ void bfly(cf& a, cf& b) {
+  constexpr int k = ((K % M) + M) % M;
+  if constexpr (k == 0) {
+    const cf t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+  } else if constexpr (4 * k == M) {          // W = -i
+    const cf wb{b.i, -b.r}, t = a;
+    a = cadd(t, wb);
+    b = csub(t, wb);
+  } else if constexpr (2 * k == M) {          // W = -1
+    const cf t = a;
+    a = csub(t, b);
+    b = cadd(t, b);
+  } else if constexpr (4 * k == 3 * M) {      // W = +i
+    const cf wb{-b.i, b.r}, t = a;
+    a = cadd(t, wb);
+    b = csub(t, wb);
+  } else {
+    constexpr double c = tw_re(k, M), s = tw_im(k, M);
+    cf bp;
+    float f;
+    if constexpr (cx_abs(c) >= cx_abs(s)) {
+      constexpr float t = float(s / c);
+      f = float(c);
+      bp = cf{fmaf(-t, b.i, b.r), fmaf(t, b.r, b.i)};
+    } else {
+      constexpr float u = float(c / s);
+      f = float(s);
+      bp = cf{fmaf(u, b.r, -b.i), fmaf(u, b.i, b.r)};
+    }
+    const cf t0 = a;
+    a = cf{fmaf(f, bp.r, t0.r), fmaf(f, bp.i, t0.i)};
+    b = cf{fmaf(-f, bp.r, t0.r), fmaf(-f, bp.i, t0.i)};
+  }
+}
+
+template <int SIZE, int S, int J>
+struct DitBfly {
+  static __device__ __forceinline__ void run(cf* y) {
+    bfly<J, SIZE>(y[S + J], y[S + J + SIZE / 2]);
+    if constexpr (J + 1 < SIZE / 2) DitBfly<SIZE, S, J + 1>::run(y);
+  }
+};
+template <int L, int SIZE, int S>
+struct DitGroup {
+  static __device__ __forceinline__ void run(cf* y) {
+    DitBfly<SIZE, S, 0>::run(y);
+    if constexpr (S + SIZE < L) DitGroup<L, SIZE, S + SIZE>::run(y);
+  }
+};
+template <int L, int SIZE>
+struct DitStage {
+  static __device__ __forceinline__ void run(cf* y) {
+    DitGroup<L, SIZE, 0>::run(y);
+    if constexpr (SIZE < L) DitStage<L, SIZE * 2>::run(y);
+  }
+};
+
+// In-place L-point DFT, natural order in and out: x[k] <- sum_j x[j] W_L^{jk}.
+// (The bit-reversal permutation is a compile-time renaming of registers.)
+template <int L>
+__device__ __forceinline__ void dit(cf* x) {
+  if constexpr (L > 1) {
+    cf y[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) y[i] = x[bitrev(i, L)];
+    DitStage<L, 2>::run(y);
+#pragma unroll
+    for (int i = 0; i < L; ++i) x[i] = y[i];
+  }
+}
+
 // Zero-padded DFT, L non-zero inputs -> 2L outputs in natural order:
 // y[k] = sum_{j<L} x[j] W_{2L}^{jk}.  Even outputs are the L-point DFT of x,
-// odd outputs the L-point DFT of x_j W_{2L}^j (first DIF stage with a zero
-// upper half).
+// odd outputs the L-point DFT of x_j W_{2L}^j (the first stage of the 2L-point
+// transform with a zero upper half).
 template <int L, int J>
 struct PadPre {
   static __device__ __forceinline__ void run(const cf* x, cf* xo) {
@@ -124,13 +206,21 @@ template <int L>
 __device__ __forceinline__ void padded_dft(cf* x /* in: [L], */, cf* y /* out: [2L] */) {
   cf xo[L];
   PadPre<L, 0>::run(x, xo);
-  dif<L>(x);
-  dif<L>(xo);
+  dit<L>(x);
+  dit<L>(xo);
 #pragma unroll
   for (int m = 0; m < L; ++m) {
-    y[2 * m] = x[bitrev(m, L)];
-    y[2 * m + 1] = xo[bitrev(m, L)];
+    y[2 * m] = x[m];
+    y[2 * m + 1] = xo[m];
   }
+}
+
+// Signed 4-bit dot product of the eight nibbles of a and b, accumulator 0
+// (the three-operand VOP3P form, so no register has to be zeroed first).
+__device__ __forceinline__ int sdot8(int a, int b) {
+  int r;
+  asm("v_dot8_i32_i4 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
 }  // namespace fftbf

@@ -172,8 +172,7 @@ __device__ __forceinline__ void v16_fft_to_lds(const uint32_t* __restrict__ src,
       }
       x[j] = cf{re, im};
     } else {
-      x[j] = cf{(float)__builtin_amdgcn_sdot8((int)d, l.wre, 0, false),
-                (float)__builtin_amdgcn_sdot8((int)d, l.wim, 0, false)};
+      x[j] = cf{(float)sdot8((int)d, l.wre), (float)sdot8((int)d, l.wim)};
     }
   }
   cf y[MNS];
