@@ -22,6 +22,8 @@ namespace fftbf {
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kTiedBlocksPerWg = 16;
 
 template <int M>
@@ -146,11 +148,13 @@ __device__ __forceinline__ V16Lane v16_lane(int lane) {
   return l;
 }
 
-// FFT beams of the 16 samples whose frames the lanes point at (lane's frame =
-// sample l.ts) into lds_b[sample][e][A], normalised by 1/sqrt(64).
+// FFT beams of the 16 samples whose frames the lanes point at (lane = sample
+// l.ts, E-W beam l.e) into LDS as floats, sample fastest:
+//   lds_b[((beam * 2) + comp) * 16 + sample],  beam = e * 32 + A_ns,
+// normalised by 1/sqrt(64).
 template <bool TAPER>
 __device__ __forceinline__ void v16_fft_to_lds(const uint32_t* __restrict__ src, const V16Lane& l,
-                                               const float* lds_h, cf* lds_b) {
+                                               const float* lds_h, float* lds_b) {
   constexpr int N = kV16N, MNS = kV16M;
   cf x[N];
 #pragma unroll
@@ -177,25 +181,90 @@ __device__ __forceinline__ void v16_fft_to_lds(const uint32_t* __restrict__ src,
   }
   cf y[MNS];
   padded_dft<N>(x, y);
-  cf* row = &lds_b[(l.ts * 4 + l.e) * MNS];
   const float nrm = 0.125f;   // 1/sqrt(4 * 16)
+  float* col = lds_b + (l.e * MNS * 2) * 16 + l.ts;
 #pragma unroll
-  for (int k = 0; k < MNS; ++k) row[k] = cf{y[k].r * nrm, y[k].i * nrm};
+  for (int k = 0; k < MNS; ++k) {
+    col[(2 * k) * 16] = y[k].r * nrm;
+    col[(2 * k + 1) * 16] = y[k].i * nrm;
+  }
 }
 
-// sum over the 16 samples in LDS of |B_p|^2 for this lane's pointing
-__device__ __forceinline__ float v16_interp_block(const cf* lds_b, const cf* cew, const cf* cns) {
-  float acc = 0.f;
-  for (int s = 0; s < kV16TS; ++s) acc += cnorm(interp_one<kV16M>(&lds_b[s * 4 * kV16M], cew, cns));
-  return acc;
+// Interpolation weight c_A(y) of one FFT beam, in FP64 (series summed term by
+// term with a unit-modulus recurrence).
+__device__ __forceinline__ void interp_weight_d(int A, int m, int n, double y, double* wr_out, double* wi_out) {
+  const double u = (double)A / (double)m - y;
+  double s, co;
+  sincospi(2.0 * u, &s, &co);
+  double wr = 1.0, wi = 0.0, ar = 0.0, ai = 0.0;
+  for (int a = 0; a < n; ++a) {
+    ar += wr;
+    ai += wi;
+    const double t = wr * co - wi * s;
+    wi = wr * s + wi * co;
+    wr = t;
+  }
+  *wr_out = ar / m;
+  *wi_out = ai / m;
 }
 
+// Matrix-core interpolation of one pointing tile.  The complex product
+//   Out[s][p] = sum_beam B[s][beam] C[p][beam],   C = c_ew[e] c_ns[A_ns]
+// runs as real 16 x 16 x 4 FP32 MFMAs: rows = 16 samples, columns = 16
+// pointings (one per lane column), k = (beam, re|im) with beam = 2 kstep +
+// (l/16 >> 1) and re|im = (l/16) & 1; one product gives Re(Out), the other
+// Im(Out) from the same A operand.  The weight operands (64 + 64 floats per
+// lane) are generated once per tile in FP64 and stay in registers.
+struct TiedB {
+  float re[64], im[64];
+};
+
+__device__ __forceinline__ void tied_weights(double y_ew, double y_ns, int g, TiedB& w) {
+  const int par = g >> 1, comp = g & 1;
+  double ewr[4], ewi[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) interp_weight_d(e, 4, 4, y_ew, &ewr[e], &ewi[e]);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    double nr, ni;
+    interp_weight_d(2 * j + par, kV16M, kV16N, y_ns, &nr, &ni);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double cr = ewr[e] * nr - ewi[e] * ni, ci = ewr[e] * ni + ewi[e] * nr;
+      const int ks = e * 16 + j;               // beam e*32 + 2j + par = 2 ks + par
+      w.re[ks] = comp == 0 ? (float)cr : (float)(-ci);
+      w.im[ks] = comp == 0 ? (float)ci : (float)cr;
+    }
+  }
+}
+
+// sum over the block's 16 samples of |Out|^2 for this lane's pointing (valid
+// in lanes with l / 16 == 0 after the call)
+__device__ __forceinline__ float tied_block_mfma(const float* lds_b, const TiedB& w, int lane) {
+  const int s = lane & 15, g = lane >> 4, par = g >> 1, comp = g & 1;
+  f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 64; ++ks) {
+    const float a = lds_b[((2 * ks + par) * 2 + comp) * 16 + s];
+    cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w.re[ks], cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w.im[ks], cim, 0, 0, 0);
+  }
+  float v = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v += fmaf(cre[i], cre[i], cim[i] * cim[i]);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Voltage variant on the matrix cores: workgroup = 4 wavefronts = 64
+// pointings; wavefront 0 forms the FFT beams of 16 samples in LDS, then each
+// wavefront interpolates its 16 pointings.
 template <bool TAPER>
-__global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
-  constexpr int N = kV16N, MNS = kV16M, TS = kV16TS;
-  __shared__ cf lds_b[TS * 4 * MNS];
-  __shared__ float lds_h[TAPER ? N * 4 : 1];
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
+  __shared__ float lds_b[kV16TS * 4 * kV16M * 2];
+  __shared__ float lds_h[TAPER ? kV16N * 4 : 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n_ptile = (a.n_point + 63) / 64;
   const int n_pg = a.pol_sum ? 1 : a.n_pol;
   int wg = blockIdx.x;
@@ -203,19 +272,16 @@ __global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
   const int trun = wg / n_ptile;
   const int cs = blockIdx.y, pg = blockIdx.z;
   const int chan = a.chan_lo + cs;
-  const int p = ptile * 64 + lane;
+  const int p = ptile * 64 + wave * 16 + (lane & 15);
   const bool live = p < a.n_point;
+  const bool wave_live = ptile * 64 + wave * 16 < a.n_point;
   const int pp = live ? p : a.n_point - 1;
 
   if constexpr (TAPER) {
-    for (int i = lane; i < N * 4; i += 64) lds_h[i] = a.taper[i];
+    for (int i = tid; i < kV16N * 4; i += 256) lds_h[i] = a.taper[i];
   }
-  cf cew[4], cns[MNS];
-  {
-    const double dl_ew = a.dl[2 * chan], dl_ns = a.dl[2 * chan + 1];
-    interp_weights<4>(dl_ew * a.dircos[2 * pp], 4, cew);
-    interp_weights<MNS>(dl_ns * a.dircos[2 * pp + 1], N, cns);
-  }
+  TiedB w;
+  if (wave_live) tied_weights(a.dl[2 * chan] * a.dircos[2 * pp], a.dl[2 * chan + 1] * a.dircos[2 * pp + 1], lane >> 4, w);
   const V16Lane l = v16_lane(lane);
   __syncthreads();
 
@@ -223,20 +289,22 @@ __global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
   const int64_t span = (int64_t)a.block * kTiedBlocksPerWg;
   const int64_t t0 = (int64_t)trun * span;
   const int64_t t1 = t0 + span < a.n_time ? t0 + span : a.n_time;
-  const int64_t frame_dw = (int64_t)a.n_chan * a.n_pol * N;   // dwords per sample
+  const int64_t frame_dw = (int64_t)a.n_chan * a.n_pol * kV16N;   // dwords per sample
 
   for (int64_t tb = t0; tb < t1; tb += a.block) {
     float acc = 0.f;
-    for (int tg = 0; tg < a.block; tg += TS) {
+    for (int tg = 0; tg < a.block; tg += kV16TS) {
       for (int pol = pol_lo; pol < pol_hi; ++pol) {
-        const uint32_t* src = a.volts + (tb + tg + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * N;
-        v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b);
+        if (wave == 0) {
+          const uint32_t* src = a.volts + (tb + tg + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * kV16N;
+          v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b);
+        }
         __syncthreads();
-        acc += v16_interp_block(lds_b, cew, cns);
+        if (wave_live) acc += tied_block_mfma(lds_b, w, lane);
         __syncthreads();
       }
     }
-    if (live) {
+    if (live && lane < 16) {
       const int64_t blk = tb / a.block;
       float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
       *o = acc;
@@ -249,35 +317,35 @@ __global__ __launch_bounds__(64) void k_tied_v16(TiedArgs a) {
 // reading voltages from the device ring (absolute sample s lives in slot
 // s mod ring_samples).  A tile's arithmetic is the same as k_tied_v16's and
 // does not depend on which other tiles share the launch.
-__global__ __launch_bounds__(64) void k_serve(const ServeTile* __restrict__ tiles, int n_tiles,
-                                              const uint32_t* __restrict__ ring, int64_t ring_samples,
-                                              int n_chan, int n_pol, const double* __restrict__ dl) {
-  constexpr int N = kV16N, MNS = kV16M, TS = kV16TS;
-  __shared__ cf lds_b[TS * 4 * MNS];
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ tiles, int n_tiles,
+                                               const uint32_t* __restrict__ ring, int64_t ring_samples,
+                                               int n_chan, int n_pol, const double* __restrict__ dl) {
+  __shared__ float lds_b[kV16TS * 4 * kV16M * 2];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const V16Lane l = v16_lane(lane);
-  const int64_t frame_dw = (int64_t)n_chan * n_pol * N;
+  const int64_t frame_dw = (int64_t)n_chan * n_pol * kV16N;
   for (int ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const ServeTile t = tiles[ti];
-    const int p = t.ptile * 64 + lane;
+    const int p = t.ptile * 64 + wave * 16 + (lane & 15);
     const bool live = p < t.n_point;
+    const bool wave_live = t.ptile * 64 + wave * 16 < t.n_point;
     const int pp = live ? p : t.n_point - 1;
-    cf cew[4], cns[MNS];
-    {
-      const double dl_ew = dl[2 * t.chan], dl_ns = dl[2 * t.chan + 1];
-      interp_weights<4>(dl_ew * t.dircos[2 * pp], 4, cew);
-      interp_weights<MNS>(dl_ns * t.dircos[2 * pp + 1], N, cns);
-    }
+    TiedB w;
+    if (wave_live)
+      tied_weights(dl[2 * t.chan] * t.dircos[2 * pp], dl[2 * t.chan + 1] * t.dircos[2 * pp + 1], lane >> 4, w);
     for (int b = 0; b < t.n_blk; ++b) {
-      const int64_t s0 = t.t_start + (int64_t)(t.blk0 + b) * TS;
+      const int64_t s0 = t.t_start + (int64_t)(t.blk0 + b) * kV16TS;
       for (int pol = 0; pol < n_pol; ++pol) {
-        const int64_t slot = (s0 + l.ts) % ring_samples;
-        const uint32_t* src = ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * N;
-        v16_fft_to_lds<false>(src, l, nullptr, lds_b);
+        if (wave == 0) {
+          const int64_t slot = (s0 + l.ts) % ring_samples;
+          const uint32_t* src = ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * kV16N;
+          v16_fft_to_lds<false>(src, l, nullptr, lds_b);
+        }
         __syncthreads();
-        const float acc = v16_interp_block(lds_b, cew, cns);
+        float acc = 0.f;
+        if (wave_live) acc = tied_block_mfma(lds_b, w, lane);
         __syncthreads();
-        if (live) {
+        if (live && lane < 16) {
           const int64_t ob = t.blk0 + b;
           t.out[((ob * t.n_chan_req + (t.chan - t.chan_lo)) * n_pol + pol) * (int64_t)t.n_point + p] = acc;
         }
@@ -305,7 +373,7 @@ hipError_t launch_serve(const ServeTile* tiles, int n_tiles, const uint32_t* rin
                         int n_chan, int n_pol, const double* dl, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   const int grid = n_tiles < 8192 ? n_tiles : 8192;
-  hipLaunchKernelGGL(k_serve, dim3(grid), dim3(64), 0, s, tiles, n_tiles, ring, ring_samples, n_chan, n_pol, dl);
+  hipLaunchKernelGGL(k_serve, dim3(grid), dim3(256), 0, s, tiles, n_tiles, ring, ring_samples, n_chan, n_pol, dl);
   return hipGetLastError();
 }
 
@@ -317,8 +385,8 @@ hipError_t launch_tied_v(const TiedArgs& a, hipStream_t s) {
   const int n_pg = a.pol_sum ? 1 : a.n_pol;
   if ((int64_t)n_ptile * n_run > 0x7FFFFFFF || a.n_chan_sub > 65535) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(n_ptile * n_run), (unsigned)a.n_chan_sub, (unsigned)n_pg);
-  if (a.taper) hipLaunchKernelGGL(k_tied_v16<true>, grid, dim3(64), 0, s, a);
-  else hipLaunchKernelGGL(k_tied_v16<false>, grid, dim3(64), 0, s, a);
+  if (a.taper) hipLaunchKernelGGL(k_tied_v16<true>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_tied_v16<false>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
