@@ -109,6 +109,43 @@ def _time_launches(fn, n: int, warmup: int = 2) -> float:
     return a.elapsed_time(b) / n
 
 
+def run_chime_mixed(dev, w, volts, fp32_ms: float) -> dict:
+    """The same resident CHIME-shaped voltages through the FP16-MFMA plan."""
+    import numpy as np
+    import torch
+
+    import oracle as orc
+    import paper_1710_08591_amd as bf
+    import synthgen as sg
+    plan = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=w.m_ew, m_ns=w.m_ns, n_pol=w.n_pol, n_chan=w.n_chan,
+                   block=w.block, ns_select=w.ns_select(), d_over_lambda=w.d_over_lambda(),
+                   precision=bf.BF_PREC_FP16_MFMA)
+    out = torch.empty(plan.out_shape(w.n_time), dtype=torch.float32, device=dev)
+    ms = _time_launches(lambda: bf.beamform_fft(plan, volts, out=out), 10)
+    rng = np.random.default_rng(3)
+    sel = w.ns_select()
+    err = 0.0
+    for _ in range(4):
+        blk, c, p = int(rng.integers(1024)), int(rng.integers(256)), int(rng.integers(2))
+        vs = sg.volts(w, blk * 16, 16, chans=[c], pols=[p])
+        ref = orc.beamform_fft(vs, w.m_ew, w.m_ns, 16)[0, 0, 0][:, sel[c]]
+        err = max(err, float(np.max(np.abs(out[blk, c, p].cpu().numpy() - ref) / ref)))
+    alg = w.n_time * w.n_chan * w.n_pol * w.frame_bytes + out.numel() * 4
+    # MFMA work issued per sample frame: 4 E-W beams x (stage 1: 2 terms x [64 x 32] over 16 a1
+    # + stage 2: 3 products of [32 x 32] over 32 k2), 2 flop per multiply-add
+    frames = w.n_time * w.n_chan * w.n_pol
+    mfma_flops = frames * 4 * (2 * 64 * 32 * 16 + 3 * 32 * 32 * 32) * 2
+    plan.close()
+    return {"workload": "same as the headline (4x256, 2 pol, 256 chan, 16384 samples, clamp 256)",
+            "precision": "fp16 mfma: exact int inputs, two-term coefficients in stage 1; stage 2 with two-term data and coefficients (three products)",
+            "kernel_ms": ms, "antenna_samples_per_s": w.antenna_samples / (ms / 1e3),
+            "speedup_vs_fp32": fp32_ms / ms,
+            "hbm_alg_gbs": alg / (ms / 1e3) / 1e9, "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "mfma_tflops": mfma_flops / (ms / 1e3) / 1e12,
+            "mfma_frac_of_fp16_peak": mfma_flops / (ms / 1e3) / 1e12 / FP16_MFMA_PEAK_TFLOPS,
+            "max_rel_power_err_sampled": err}
+
+
 def run_extras(dev) -> dict:
     """Side-by-side precision variants, per-variant error, tied-beam throughput."""
     import numpy as np
@@ -337,11 +374,15 @@ def main():
         "generation_s": gen_s,
     }
 
+    chime_mixed = None
+    if not args.skip_extras:
+        chime_mixed = run_chime_mixed(dev, w, volts, ms_avg)
     del volts, out
     plan.close()
     torch.cuda.empty_cache()
     if not args.skip_extras:
-        rec["extras"] = run_extras(dev)
+        rec["extras"] = {"chime_fp16_mfma": chime_mixed}
+        rec["extras"].update(run_extras(dev))
         torch.cuda.empty_cache()
     if not args.skip_cpu:
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

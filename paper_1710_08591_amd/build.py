@@ -25,6 +25,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",     # MFMA results straight into VGPRs (no AGPR copies)
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -19,6 +19,8 @@ __device__ __forceinline__ cf cmul(cf a, cf w) {
   return {fmaf(a.r, w.r, -(a.i * w.i)), fmaf(a.r, w.i, a.i * w.r)};
 }
 __device__ __forceinline__ float cnorm(cf a) { return fmaf(a.r, a.r, a.i * a.i); }
+// acc + |a|^2 as two fused multiply-adds
+__device__ __forceinline__ float cnorm_acc(cf a, float acc) { return fmaf(a.r, a.r, fmaf(a.i, a.i, acc)); }
 
 // ---- compile-time exp(-i 2 pi k / M) in double --------------------------
 constexpr double kPi = 3.14159265358979323846264338327950288;

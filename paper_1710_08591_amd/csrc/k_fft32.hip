@@ -196,7 +196,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
           }
         } else {
 #pragma unroll
-          for (int k1 = 0; k1 < G; ++k1) acc[r][k1] += cnorm(z[k1]);
+          for (int k1 = 0; k1 < G; ++k1) acc[r][k1] = cnorm_acc(z[k1], acc[r][k1]);
         }
       }
       __syncthreads();

@@ -251,7 +251,7 @@ __device__ __forceinline__ float tied_block_mfma(const float* lds_b, const TiedB
   }
   float v = 0.f;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v += fmaf(cre[i], cre[i], cim[i] * cim[i]);
+  for (int i = 0; i < 4; ++i) v = fmaf(cre[i], cre[i], fmaf(cim[i], cim[i], v));
   v += __shfl_xor(v, 16);
   v += __shfl_xor(v, 32);
   return v;

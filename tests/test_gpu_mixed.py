@@ -90,3 +90,32 @@ def test_mixed_repeatable_and_unsupported():
     with pytest.raises(bf.BFError) as e:
         bf.Plan(n_ns=32, precision=1)
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
+
+
+def test_mix256_chime_lattice_parity():
+    """The two-stage FP16 MFMA transform on the 4 x 256 lattice (512 = 32 x 16)."""
+    w = sg.custom_workload(n_ew=4, n_ns=256, n_chan=3, n_pol=2, n_time=48, seed=77, n_src=4, snr=10.0,
+                           n_ns_keep=256, dl=(0.4, 0.8))
+    v = sg.volts(w)
+    ref = orc.beamform_fft(v, 4, 512, 16, ns_select=w.ns_select())
+    got = _run(w, v, 1)
+    err = rel_err(got, ref)
+    print(f"4x256 FP16 MFMA: max rel beam-power error {err:.3e}")
+    assert err < TOL_MIXED
+    refp = orc.beamform_fft(v, 4, 512, 16, ns_select=w.ns_select(), pol_sum=True)
+    assert rel_err(_run(w, v, 1, pol_sum=True), refp) < TOL_MIXED
+    unc = _run(w, v, 1, clamp=False, block=48)
+    assert rel_err(unc, orc.beamform_fft(v, 4, 512, 48)) < TOL_MIXED
+
+
+def test_mix256_extremes_and_point_source():
+    w = sg.custom_workload(n_ew=4, n_ns=256, n_time=16, n_src=0)
+    for b in (0x88, 0x77, 0x18):
+        v = np.full((16, 1, 1, 256, 4), b, dtype=np.uint8)
+        got = _run(w, v, 1, clamp=False)
+        ref = orc.beamform_fft(v, 4, 512, 16)
+        assert np.max(np.abs(got - ref)) / ref.max() < TOL_MIXED
+    v = sg.point_source_volts(4, 256, 1, 3, 16, 7)
+    got = _run(w, v, 1, clamp=False)
+    ref = orc.beamform_fft(v, 4, 512, 16)
+    assert np.max(np.abs(got - ref)) / ref.max() < TOL_MIXED
