@@ -168,6 +168,35 @@ bf_status bf_accumulate_intensity(const void *z, int64_t n_time, int64_t n_serie
                                   int32_t block, int32_t add, float *out, void *stream);
 
 /*
+ * ---- Regridding FFT-beam intensities to arbitrary steering angles ----
+ * Eq. e:bp_max_arbitrary (Sec. "Redundancy-stacked visibilities"): a beam
+ * pointed at sin(theta) is formed from the FFT-beam intensities b_A as
+ *     b = sum_A w^A b_A,   w^A = (1/M) sin((2n-1) pi y) / sin(pi y),
+ *     y = (d/lambda) sin(theta) - A/M,
+ * exact for M >= 2n - 1.  Applied along N-S (M = 2n) for each E-W FFT beam,
+ * so the same sin(theta) targets give achromatic beams in every channel
+ * (the FFT beams' own positions move with wavelength, eq. e:theta_A).
+ * The weights are generated in FP64 on the device at creation and stored
+ * in FP32 ([n_chan][targets][m_ns], owned by the regrid object); the
+ * contraction runs in FP32.
+ */
+typedef struct bf_regrid bf_regrid;
+
+/* plan: the geometry and per-channel d/lambda, without a clamp (n_ns_keep 0
+ * or m_ns).  sin_theta: host double [n_target] (copied).  Synchronous. */
+bf_status bf_regrid_create(const bf_plan *plan, const double *sin_theta, int32_t n_target,
+                           bf_regrid **rg);
+bf_status bf_regrid_destroy(bf_regrid *rg);
+/* fft_intensity: device float [n_blk][n_chan][n_pol][m_ew][m_ns] as written by
+ * bf_beamform_fft with the plan ([n_blk][n_chan][m_ew][m_ns] when it sums
+ * polarisations); out: device float [n_blk][n_chan][n_pol][m_ew][n_target]
+ * (or [n_blk][n_chan][m_ew][n_target]).  fft_intensity 16-byte aligned.
+ * n_blk = 0 is a no-op.  Asynchronous on stream; the caller owns both
+ * buffers. */
+bf_status bf_regrid_intensity(const bf_regrid *rg, const float *fft_intensity, int64_t n_blk,
+                              float *out, void *stream);
+
+/*
  * ---- Tied-beam server --------------------------------------------------
  * Serves tied-array beam requests (arbitrary pointings, a contiguous channel
  * range, the most recent n_time samples) from a device-resident voltage ring

@@ -20,7 +20,7 @@ from ._lib import (bf_server_stats, BF_OK, BF_ERR_INVALID_ARGUMENT, BF_ERR_UNSUP
 
 __all__ = [
     "Plan", "plan_create", "plan_destroy", "beamform_fft", "form_tied_beams", "form_tied_beams_v",
-    "accumulate_intensity", "Server", "lib", "BFError", "LibraryMissing",
+    "accumulate_intensity", "Regrid", "Server", "lib", "BFError", "LibraryMissing",
     "BF_PREC_FP32", "BF_PREC_FP16_MFMA", "BF_PREC_FP8_MFMA", "BF_OUT_INTENSITY", "BF_OUT_COMPLEX",
 ]
 
@@ -231,6 +231,50 @@ def accumulate_intensity(z, block: int, out=None, add: bool = False, stream=None
     check(lib().bf_accumulate_intensity(_ptr(z), n_time, n_series, block, int(add), _ptr(out),
                                         _stream_handle(stream)), "bf_accumulate_intensity")
     return out
+
+
+class Regrid:
+    """Achromatic beams regridded from FFT-beam intensities (bf_regrid_*)."""
+
+    def __init__(self, plan: Plan, sin_theta: np.ndarray):
+        st = np.ascontiguousarray(sin_theta, dtype=np.float64).ravel()
+        h = C.c_void_p()
+        check(lib().bf_regrid_create(plan.handle, st.ctypes.data_as(C.c_void_p), len(st), C.byref(h)),
+              "bf_regrid_create")
+        self.handle = h
+        self.n_target = len(st)
+        # the plan's intensity layout: the polarisation axis is absent when it sums them
+        self.plan_shape = ((plan.n_chan, plan.m_ew, plan.m_ns) if plan.pol_sum
+                           else (plan.n_chan, plan.n_pol, plan.m_ew, plan.m_ns))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bf_regrid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __call__(self, fft_intensity, out=None, stream=None):
+        """Regrid [n_blk][n_chan]([n_pol])[m_ew][m_ns] intensities to [..][n_target]."""
+        torch = _torch()
+        _need(fft_intensity, torch.float32, "fft_intensity")
+        n_blk = fft_intensity.shape[0]
+        if tuple(fft_intensity.shape[1:]) != self.plan_shape:
+            raise ValueError(f"fft_intensity must be [n_blk]{list(self.plan_shape)}")
+        shape = (n_blk,) + self.plan_shape[:-1] + (self.n_target,)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=fft_intensity.device)
+        else:
+            _need(out, torch.float32, "out")
+            if tuple(out.shape) != shape:
+                raise ValueError(f"out shape {tuple(out.shape)} != {shape}")
+        check(lib().bf_regrid_intensity(self.handle, _ptr(fft_intensity), n_blk, _ptr(out),
+                                        _stream_handle(stream)), "bf_regrid_intensity")
+        return out
 
 
 class Server:

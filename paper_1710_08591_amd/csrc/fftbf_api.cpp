@@ -334,6 +334,86 @@ bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_
   return BF_OK;
 }
 
+}  // extern "C"
+
+struct bf_regrid {
+  int n_chan = 0, n_pg = 0, m_ew = 0, m_ns = 0, n_ns = 0, n_target = 0, pad = 0;
+  float* w = nullptr;
+};
+
+extern "C" {
+
+bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t n_target, bf_regrid** rg) {
+  if (!rg) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: NULL rg");
+  *rg = nullptr;
+  if (!plan || !sin_theta) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: NULL plan or sin_theta");
+  const bf_plan_desc& d = plan->d;
+  if (plan->sel || keep_of(d) != d.m_ns)
+    return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: needs a plan without a clamp (all m_ns beams)");
+  if (d.m_ns < 2 * d.n_ns - 1)
+    return fail(BF_ERR_UNSUPPORTED, "regrid_create: exact regridding needs m_ns >= 2 n_ns - 1");
+  if (n_target < 1 || n_target > 65536) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: n_target out of [1, 65536]");
+  for (int j = 0; j < n_target; ++j)
+    if (!(sin_theta[j] >= -1e6 && sin_theta[j] <= 1e6))
+      return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: sin_theta[%d] not finite", j);
+  bf_regrid* r = new (std::nothrow) bf_regrid();
+  if (!r) return fail(BF_ERR_OUT_OF_MEMORY, "regrid_create: host allocation");
+  r->n_chan = d.n_chan;
+  r->n_pg = d.pol_sum ? 1 : d.n_pol;
+  r->m_ew = d.m_ew;
+  r->m_ns = d.m_ns;
+  r->n_ns = d.n_ns;
+  r->n_target = n_target;
+  r->pad = fftbf::regrid_target_pad(n_target);
+  double* st = nullptr;
+  hipError_t e = hipMalloc(&r->w, sizeof(float) * (size_t)r->n_chan * r->pad * r->m_ns);
+  if (e == hipSuccess) e = hipMalloc(&st, sizeof(double) * n_target);
+  if (e == hipSuccess) e = hipMemcpy(st, sin_theta, sizeof(double) * n_target, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = fftbf::launch_regrid_weights(r->w, plan->dl, st, r->n_chan, n_target, r->n_ns, r->m_ns, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (st) (void)hipFree(st);
+  if (e != hipSuccess) {
+    if (r->w) (void)hipFree(r->w);
+    delete r;
+    return dev_fail(e, "regrid_create: weights");
+  }
+  *rg = r;
+  return BF_OK;
+}
+
+bf_status bf_regrid_destroy(bf_regrid* rg) {
+  if (!rg) return BF_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (rg->w) (void)hipFree(rg->w);
+  delete rg;
+  if (e != hipSuccess) return dev_fail(e, "regrid_destroy: pending device error");
+  return BF_OK;
+}
+
+bf_status bf_regrid_intensity(const bf_regrid* rg, const float* fft_intensity, int64_t n_blk, float* out,
+                              void* stream) {
+  if (!rg) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_intensity: NULL regrid");
+  if (n_blk < 0) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_intensity: negative n_blk");
+  if (n_blk == 0) return BF_OK;
+  if (!fft_intensity || !out) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_intensity: NULL in or out");
+  if (!aligned(fft_intensity, 16) || !aligned(out, 4))
+    return fail(BF_ERR_INVALID_ARGUMENT, "regrid_intensity: fft_intensity must be 16-byte aligned, out 4-byte");
+  fftbf::RegridArgs a{};
+  a.in = fft_intensity;
+  a.w = rg->w;
+  a.out = out;
+  a.n_blk = n_blk;
+  a.n_chan = rg->n_chan;
+  a.n_pg = rg->n_pg;
+  a.m_ew = rg->m_ew;
+  a.m_ns = rg->m_ns;
+  a.n_target = rg->n_target;
+  a.n_target_pad = rg->pad;
+  hipError_t e = fftbf::launch_regrid(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return dev_fail(e, "regrid_intensity: launch");
+  return BF_OK;
+}
+
 bf_status bf_accumulate_intensity(const void* z, int64_t n_time, int64_t n_series, int32_t block, int32_t add,
                                   float* out, void* stream) {
   if (n_time < 0 || n_series < 0) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: negative size");

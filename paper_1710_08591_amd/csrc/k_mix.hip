@@ -309,7 +309,7 @@ __device__ __forceinline__ void split2(float v0, float v1, uint32_t& hi, uint32_
   hi = h;
 }
 
-__device__ __forceinline__ half8 pack8(const float* v) {
+__device__ __forceinline__ __attribute__((unused)) half8 pack8(const float* v) {
   half8 h;
 #pragma unroll
   for (int j = 0; j < 8; ++j) h[j] = (_Float16)v[j];

@@ -1,0 +1,186 @@
+// Intensity-domain regridding of FFT beams to arbitrary steering angles
+// (eq. e:bp_max_arbitrary, Sec. "Redundancy-stacked visibilities"):
+//
+//   b_p(theta) = sum_A w^A_p b_A,  w^A_p = (1/M) sin((2n-1) pi y) / sin(pi y),
+//   y = (d/lambda) sin(theta) - A/M,
+//
+// exact whenever M >= 2n - 1, which the zero-padded N-S axis (M = 2n)
+// satisfies.  Applied per channel along N-S for every E-W FFT beam, so the
+// targets can be the same sin(theta) in every channel (achromatic beams from
+// the chromatic FFT grid of eq. e:theta_A).
+//
+// The weights are generated once in FP64 on the device (the removable
+// singularity at integer y takes its limit (2n-1)/M) and stored in FP32.
+// The contraction Out[row][target] = sum_A I[row][A] W[target][A] (rows =
+// (block, polarisation, E-W beam) of one channel) runs on FP32 MFMA
+// (v_mfma_f32_16x16x4_f32).  A 256-thread workgroup owns 64 rows x TT
+// targets (TT = 64 or 256); wave w owns rows 16w..16w+15 against all TT
+// targets.  The K axis (beams A) is walked in chunks of KC:
+//   * the intensity operand goes straight from HBM to registers: lane
+//     (m, g) of a wave feeds row m and, at MFMA step s, beam g*KC/4 + s of
+//     the chunk (a permutation of K that both operands share), so its KC/4
+//     values are contiguous and arrive as float4 loads;
+//   * the weight chunk [TT][KC] is staged once per workgroup in LDS and read
+//     back as ds_read_b128 in the same permuted order;
+//   * the next chunk's global loads are issued before the current chunk's
+//     MFMAs, so their latency hides under the matrix work.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace fftbf {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void k_regrid_weights(float* w, const double* dl, const double* sin_t, int n_chan, int n_target,
+                                 int n_target_pad, int n, int m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n_chan * n_target_pad * m;
+  if (i >= total) return;
+  const int A = (int)(i % m);
+  const int j = (int)((i / m) % n_target_pad);
+  const int c = (int)(i / ((int64_t)m * n_target_pad));
+  if (j >= n_target) {
+    w[i] = 0.f;
+    return;
+  }
+  const double y = dl[2 * c + 1] * sin_t[j] - (double)A / (double)m;
+  const double den = sinpi(y);
+  double v;
+  if (fabs(den) < 1e-12) {
+    v = (double)(2 * n - 1);
+  } else {
+    v = sinpi((double)(2 * n - 1) * y) / den;
+  }
+  w[i] = (float)(v / m);
+}
+
+// KC: beams per chunk (32 when M = 32, else 64).  NT: 16-target MFMA tiles
+// per wave (TT = 16 NT targets per workgroup).
+template <int KC, int NT>
+__global__ __launch_bounds__(256, 2) void k_regrid(RegridArgs a) {
+  constexpr int TT = 16 * NT;
+  constexpr int KS = KC / 4;              // MFMA steps per chunk = beams per lane per chunk
+  constexpr int KV = KS / 4;              // float4 per lane per row per chunk
+  constexpr int LDW = KC + 4;             // LDS row stride (floats) of the weight chunk
+  constexpr int WV = TT * KC / 4 / 256;   // weight float4 staged per thread per chunk
+  __shared__ __attribute__((aligned(16))) float lds_w[TT * LDW];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m = lane & 15, g = lane >> 4;
+  const int chan = blockIdx.z;
+  const int rows = a.rows_per_chan;
+  const int t0 = blockIdx.y * TT;
+  const float* wbase = a.w + ((int64_t)chan * a.n_target_pad + t0) * a.m_ns;
+
+  // this lane's intensity row (channel-local r -> global row through the
+  // R = n_pg * m_ew rows of one block, R a power of two)
+  const int r = blockIdx.x * 64 + wave * 16 + m;
+  const bool row_ok = r < rows;
+  const int64_t grow = ((int64_t)(r >> a.log2_r) * a.n_chan + chan) * (1 << a.log2_r) + (r & ((1 << a.log2_r) - 1));
+  const float* arow = a.in + (row_ok ? grow : 0) * a.m_ns + g * KS;
+
+  f32x4 acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  f32x4 av_next[KV], wv_next[WV];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < KV; ++v)
+      av_next[v] = row_ok ? *reinterpret_cast<const f32x4*>(arow + k0 + 4 * v) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int it = 0; it < WV; ++it) {
+      const int idx = tid + 256 * it;
+      const int tr = idx / (KC / 4), c4 = idx % (KC / 4);
+      wv_next[it] = *reinterpret_cast<const f32x4*>(wbase + (int64_t)tr * a.m_ns + k0 + 4 * c4);
+    }
+  };
+
+  load_chunk(0);
+  for (int k0 = 0; k0 < a.m_ns; k0 += KC) {
+    f32x4 av[KV];
+#pragma unroll
+    for (int v = 0; v < KV; ++v) av[v] = av_next[v];
+#pragma unroll
+    for (int it = 0; it < WV; ++it) {
+      const int idx = tid + 256 * it;
+      const int tr = idx / (KC / 4), c4 = idx % (KC / 4);
+      *reinterpret_cast<f32x4*>(&lds_w[tr * LDW + 4 * c4]) = wv_next[it];
+    }
+    if (k0 + KC < a.m_ns) load_chunk(k0 + KC);
+    __syncthreads();
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const float* wrow = &lds_w[(16 * nt + m) * LDW + g * KS];
+#pragma unroll
+      for (int v = 0; v < KV; ++v) {
+        const f32x4 bv = *reinterpret_cast<const f32x4*>(wrow + 4 * v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[v][q], bv[q], acc[nt], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // acc[nt][i]: row 16 wave + 4 g + i, target t0 + 16 nt + lane % 16
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int ro = blockIdx.x * 64 + wave * 16 + 4 * g + i;
+    if (ro >= rows) continue;
+    const int64_t go = ((int64_t)(ro >> a.log2_r) * a.n_chan + chan) * (1 << a.log2_r) + (ro & ((1 << a.log2_r) - 1));
+    float* o = a.out + go * a.n_target;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int t = t0 + 16 * nt + m;
+      if (t < a.n_target) o[t] = acc[nt][i];
+    }
+  }
+}
+
+template <int KC>
+hipError_t launch_kc(const RegridArgs& a, dim3 grid, bool wide, hipStream_t s) {
+  if (wide)
+    hipLaunchKernelGGL((k_regrid<KC, 16>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_regrid<KC, 4>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Targets are padded to the workgroup's target tile: 64 for up to 64
+// targets, else a multiple of 256.
+int regrid_target_pad(int n_target) {
+  return n_target <= 64 ? 64 : (n_target + 255) / 256 * 256;
+}
+
+hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t, int n_chan, int n_target,
+                                 int n, int m, hipStream_t s) {
+  const int pad = regrid_target_pad(n_target);
+  const int64_t total = (int64_t)n_chan * pad * m;
+  hipLaunchKernelGGL(k_regrid_weights, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, dl, sin_t, n_chan,
+                     n_target, pad, n, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_regrid(const RegridArgs& a_in, hipStream_t s) {
+  RegridArgs a = a_in;
+  if (a.m_ns < 32 || (a.m_ns & (a.m_ns - 1))) return hipErrorNotSupported;
+  const int r_blk = a.n_pg * a.m_ew;
+  if (r_blk <= 0 || (r_blk & (r_blk - 1))) return hipErrorNotSupported;
+  a.log2_r = 0;
+  while ((1 << a.log2_r) < r_blk) ++a.log2_r;
+  const int64_t rows = a.n_blk * r_blk;
+  if (rows == 0) return hipSuccess;
+  if (rows > 0x7FFFFF00LL || a.n_chan > 65535) return hipErrorInvalidConfiguration;
+  a.rows_per_chan = (int)rows;
+  const bool wide = a.n_target_pad > 64;
+  const int tt = wide ? a.n_target_pad / 256 : 1;
+  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)tt, (unsigned)a.n_chan);
+  return a.m_ns == 32 ? launch_kc<32>(a, grid, wide, s) : launch_kc<64>(a, grid, wide, s);
+}
+
+}  // namespace fftbf

@@ -64,6 +64,20 @@ hipError_t launch_serve(const ServeTile* tiles, int n_tiles, const uint32_t* rin
                         int n_chan, int n_pol, const double* dl, hipStream_t s);
 hipError_t launch_tied_v(const TiedArgs& a, hipStream_t s);
 
+// intensity-domain regridding of FFT beams (N-S axis)
+struct RegridArgs {
+  const float* in;         // [n_blk][n_chan][n_pg][m_ew][m_ns]
+  const float* w;          // [n_chan][n_target_pad][m_ns]
+  float* out;              // [n_blk][n_chan][n_pg][m_ew][n_target]
+  int64_t n_blk;
+  int n_chan, n_pg, m_ew, m_ns, n_target, n_target_pad;
+  int rows_per_chan, log2_r;   // set by launch_regrid
+};
+int regrid_target_pad(int n_target);
+hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t, int n_chan, int n_target,
+                                 int n, int m, hipStream_t s);
+hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);
+
 // mixed-precision (MFMA) beamformer
 struct MixArgs {
   const uint32_t* volts;
