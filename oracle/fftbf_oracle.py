@@ -42,6 +42,8 @@ __all__ = [
     "visibilities", "beam_power_from_visibilities", "stacked_visibilities",
     "beam_power_from_stacked", "stacked_from_beams", "regrid_weights_paper",
     "interp_weights", "interpolate_beams", "rel_power_error",
+    "window_autocorr", "optimal_window_norm", "optimal_window_lag_weights",
+    "optimal_window_weights", "compact_taps", "regrid_intensity",
 ]
 
 
@@ -253,6 +255,94 @@ def regrid_weights_paper(n: int, m: int, y: float) -> np.ndarray:
     w = np.where(near, (2 * n - 1) * np.cos((2 * n - 1) * np.pi * ya) / np.where(near, np.cos(np.pi * ya), 1.0),
                  num / np.where(near, 1.0, s))
     return w / m
+
+
+def window_autocorr(h: np.ndarray) -> np.ndarray:
+    """Auto-convolution of the window, R_delta = sum_alpha h^{alpha+delta} conj(h^alpha),
+    for delta = -(n-1) .. n-1 (index delta + n - 1); the sum over redundant
+    pairs in eq. e:w_opt."""
+    h = np.asarray(h, dtype=np.complex128)
+    n = len(h)
+    out = np.zeros(2 * n - 1, dtype=np.complex128)
+    for d in range(-(n - 1), n):
+        for al in range(n):
+            if 0 <= al + d < n:
+                out[d + n - 1] += h[al + d] * np.conj(h[al])
+    return out
+
+
+def optimal_window_norm(h: np.ndarray) -> float:
+    """The normalisation N of the optimally windowed beam (eq. e:w_opt).
+
+    The paper leaves N to be computed numerically.  Reading: N makes the
+    beam's noise equal to the unwindowed pointed beam's when the visibility
+    noise is dominated by the auto-correlations (eq. e:var_bV): each of the
+    n - |delta| redundant visibilities of lag delta carries the weight
+    w^delta, so sum_delta (n - |delta|) |w^delta|^2 must equal the pointed
+    beam's sum_delta (n - |delta|) / n^2 = 1.  With
+    w^delta = R_delta e^{-i 2 pi delta y} / (n N (n - |delta|)) that gives
+    N = (1/n) sqrt(sum_delta |R_delta|^2 / (n - |delta|)).  N = 1 for h = 1.
+    """
+    r = window_autocorr(h)
+    n = len(h)
+    lag = np.arange(-(n - 1), n)
+    return float(np.sqrt(np.sum(np.abs(r) ** 2 / (n - np.abs(lag)))) / n)
+
+
+def optimal_window_lag_weights(h: np.ndarray, y: float) -> np.ndarray:
+    """Lag-domain weights w_ow^delta of eq. e:w_opt, delta = -(n-1) .. n-1.
+
+    w_ow^delta = w_p^delta R_delta / (N (n - |delta|)) with the pointed lag
+    weight w_p^delta = (1/n) e^{-i 2 pi delta y} (the weights that make
+    sum_delta w_p^delta V~_delta the pointed beam of eq. e:b2n-1 at y), so
+    that the beam is b = sum_delta w^delta V~_delta.
+    """
+    n = len(h)
+    lag = np.arange(-(n - 1), n)
+    wp = np.exp(-2j * np.pi * lag * y) / n
+    return wp * window_autocorr(h) / (optimal_window_norm(h) * (n - np.abs(lag)))
+
+
+def optimal_window_weights(h: np.ndarray, m: int, y: float) -> np.ndarray:
+    """FFT-beam weights w_ow^A of eq. e:wA_windowed, [M], real for a real window.
+
+    Lag weights mapped to the FFT-beam basis by eq. e:wA_from_wdelta,
+    w^A = (n/M) sum_delta e^{+i 2 pi delta A / M} w^delta (valid for
+    M >= 2n - 1).  The paper's second form carries n/(M N) in front; with
+    h = 1 that would be n times the pointed regridding weights of eq.
+    e:bp_max_arbitrary, so the reading kept here is the first form, whose
+    prefactor works out to 1/(M N).
+    """
+    n = len(h)
+    lag = np.arange(-(n - 1), n)
+    wd = optimal_window_lag_weights(h, y)
+    A = np.arange(m)
+    w = (n / m) * np.exp(2j * np.pi * np.outer(A, lag) / m) @ wd
+    if np.isrealobj(h):
+        assert np.max(np.abs(w.imag)) < 1e-9 * max(1.0, np.max(np.abs(w.real)))
+        return w.real
+    return w
+
+
+def compact_taps(w: np.ndarray, y: float, k: int):
+    """Compact k-tap version of a regridding kernel (Sec. "Controlling beam
+    shape with windowing": a few weights around the pointing approximate the
+    full set).
+
+    Reading: keep the k FFT beams nearest the pointing on the circular beam
+    grid, A = round(y M) - (k-1)//2 + j mod M for j < k (round half to even),
+    with their full-kernel weights unchanged; every other weight is zero.
+    Returns (first tap index mod M, [k] weights).
+    """
+    m = len(w)
+    first = int(np.round(y * m)) - (k - 1) // 2
+    idx = (first + np.arange(k)) % m
+    return first % m, np.asarray(w)[idx]
+
+
+def regrid_intensity(b: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """Regridded beams sum_A w^A b_A: b [..., M] intensities, weights [T][M] -> [..., T]."""
+    return np.asarray(b, dtype=np.float64) @ np.asarray(weights, dtype=np.float64).T
 
 
 def interp_weights(n: int, m: int, y: np.ndarray) -> np.ndarray:
