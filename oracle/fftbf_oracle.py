@@ -265,9 +265,8 @@ def window_autocorr(h: np.ndarray) -> np.ndarray:
     n = len(h)
     out = np.zeros(2 * n - 1, dtype=np.complex128)
     for d in range(-(n - 1), n):
-        for al in range(n):
-            if 0 <= al + d < n:
-                out[d + n - 1] += h[al + d] * np.conj(h[al])
+        al = np.arange(max(0, -d), min(n, n - d))        # alpha with 0 <= alpha + d < n
+        out[d + n - 1] = np.sum(h[al + d] * np.conj(h[al]))
     return out
 
 
@@ -289,8 +288,9 @@ def optimal_window_norm(h: np.ndarray) -> float:
     return float(np.sqrt(np.sum(np.abs(r) ** 2 / (n - np.abs(lag)))) / n)
 
 
-def optimal_window_lag_weights(h: np.ndarray, y: float) -> np.ndarray:
-    """Lag-domain weights w_ow^delta of eq. e:w_opt, delta = -(n-1) .. n-1.
+def optimal_window_lag_weights(h: np.ndarray, y) -> np.ndarray:
+    """Lag-domain weights w_ow^delta of eq. e:w_opt, delta = -(n-1) .. n-1
+    (last axis), for a scalar or an array of steerings y.
 
     w_ow^delta = w_p^delta R_delta / (N (n - |delta|)) with the pointed lag
     weight w_p^delta = (1/n) e^{-i 2 pi delta y} (the weights that make
@@ -299,12 +299,13 @@ def optimal_window_lag_weights(h: np.ndarray, y: float) -> np.ndarray:
     """
     n = len(h)
     lag = np.arange(-(n - 1), n)
-    wp = np.exp(-2j * np.pi * lag * y) / n
+    wp = np.exp(-2j * np.pi * np.multiply.outer(np.asarray(y, dtype=np.float64), lag)) / n
     return wp * window_autocorr(h) / (optimal_window_norm(h) * (n - np.abs(lag)))
 
 
-def optimal_window_weights(h: np.ndarray, m: int, y: float) -> np.ndarray:
-    """FFT-beam weights w_ow^A of eq. e:wA_windowed, [M], real for a real window.
+def optimal_window_weights(h: np.ndarray, m: int, y) -> np.ndarray:
+    """FFT-beam weights w_ow^A of eq. e:wA_windowed: [M] for a scalar y,
+    [T][M] for an array; real for a real window.
 
     Lag weights mapped to the FFT-beam basis by eq. e:wA_from_wdelta,
     w^A = (n/M) sum_delta e^{+i 2 pi delta A / M} w^delta (valid for
@@ -315,9 +316,9 @@ def optimal_window_weights(h: np.ndarray, m: int, y: float) -> np.ndarray:
     """
     n = len(h)
     lag = np.arange(-(n - 1), n)
-    wd = optimal_window_lag_weights(h, y)
-    A = np.arange(m)
-    w = (n / m) * np.exp(2j * np.pi * np.outer(A, lag) / m) @ wd
+    wd = optimal_window_lag_weights(h, y)                          # [..., 2n-1]
+    e = np.exp(2j * np.pi * np.outer(np.arange(m), lag) / m)       # [M][2n-1]
+    w = (n / m) * wd @ e.T
     if np.isrealobj(h):
         assert np.max(np.abs(w.imag)) < 1e-9 * max(1.0, np.max(np.abs(w.real)))
         return w.real

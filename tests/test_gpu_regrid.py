@@ -125,6 +125,113 @@ def test_regrid_kernel_on_oracle_intensities(n_ns, n_blk, n_target):
     plan.close()
 
 
+def _window(kind, n):
+    if kind == "sine":
+        return np.sin(np.pi * (np.arange(n) + 1) / (n + 1))
+    rng = np.random.default_rng(n)
+    return 0.2 + rng.random(n)                     # real, asymmetric
+
+
+def _oracle_case(n_ns, n_blk, n_chan=3, seed=7):
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=n_chan, n_pol=2, n_time=16 * n_blk, seed=seed, n_src=3,
+                           snr=1.0, dl=(0.3, 0.9))
+    x = orc.beamform_fft(sg.volts(w), 4, 2 * n_ns, 16).astype(np.float32)       # [blk][chan][pol][4][M]
+    return w, x
+
+
+@pytest.mark.parametrize("n_ns,n_blk,n_target,kind", [(16, 5, 40, "sine"), (64, 9, 100, "asym"),
+                                                      (256, 6, 256, "sine")])
+def test_regrid_windowed_kernel_on_oracle_intensities(n_ns, n_blk, n_target, kind):
+    """Optimally windowed weights (eq. e:wA_windowed) generated on the device,
+    applied to oracle FFT intensities, against the FP64 oracle weights."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    m = 2 * n_ns
+    w, x = _oracle_case(n_ns, n_blk)
+    h = _window(kind, n_ns)
+    plan = bf.Plan(n_ew=4, n_ns=n_ns, n_chan=3, n_pol=2, block=16, d_over_lambda=w.d_over_lambda())
+    st = _targets(n_target, 5)
+    rg = bf.Regrid(plan, st, window=h)
+    got = rg(torch.from_numpy(x).cuda()).cpu().numpy()
+    x64 = x.astype(np.float64)
+    for c in range(3):
+        W = orc.optimal_window_weights(h, m, w.d_over_lambda()[c, 1] * st)
+        ref = orc.regrid_intensity(x64[:, c], W)
+        scale = orc.regrid_intensity(np.abs(x64[:, c]), np.abs(W))
+        assert np.all(np.abs(got[:, c] - ref) <= 2e-6 * scale)
+        assert rel_err(got[:, c], ref) < TOL_FP32
+    rg.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("n_ns,k,kind", [(16, 1, None), (16, 5, "sine"), (64, 3, None), (64, 8, "asym"),
+                                         (256, 5, "sine"), (128, 4, "sine")])
+def test_regrid_compact_taps_on_oracle_intensities(n_ns, k, kind):
+    """Compact k-tap kernels: the nearest-beam taps and their weights against
+    the oracle's truncation of the full kernel, then the gather."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    m = 2 * n_ns
+    w, x = _oracle_case(n_ns, 11)
+    h = _window(kind, n_ns) if kind else None
+    plan = bf.Plan(n_ew=4, n_ns=n_ns, n_chan=3, n_pol=2, block=16, d_over_lambda=w.d_over_lambda())
+    st = _targets(300, 9)                          # more targets than one pass of 256 threads
+    rg = bf.Regrid(plan, st, window=h, n_taps=k)
+    got = rg(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert got.shape == (11, 3, 2, 4, 300)
+    x64 = x.astype(np.float64)
+    for c in range(3):
+        ref = np.empty(x64.shape[:1] + x64.shape[2:-1] + (len(st),))
+        scale = np.empty_like(ref)
+        ys = w.d_over_lambda()[c, 1] * st
+        fulls = orc.optimal_window_weights(h, m, ys) if kind else None
+        for t, y in enumerate(ys):
+            full = fulls[t] if kind else orc.regrid_weights_paper(n_ns, m, y)
+            first, taps = orc.compact_taps(full, y, k)
+            idx = (first + np.arange(k)) % m
+            ref[..., t] = x64[:, c][..., idx] @ taps
+            scale[..., t] = np.abs(x64[:, c][..., idx]) @ np.abs(taps)
+        assert np.all(np.abs(got[:, c] - ref) <= 1e-6 * scale)
+    rg.close()
+    plan.close()
+
+
+def test_regrid_windowed_chain():
+    """Voltages -> FP32 FFT intensities (no taper) -> optimally windowed
+    beams with the dense and the 5-tap kernels, against the oracle's beams
+    regridded in FP64, to the FP32 bar carried through the weights."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    n_ns, m = 64, 128
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=4, n_pol=2, n_time=512, seed=31, n_src=3, snr=5.0,
+                           dl=(0.4, 0.8))
+    v = sg.volts(w)
+    plan = bf.Plan(n_ew=4, n_ns=n_ns, n_chan=4, n_pol=2, block=16, d_over_lambda=w.d_over_lambda())
+    fft_i = bf.beamform_fft(plan, torch.from_numpy(v).cuda())
+    b = orc.beamform_fft(v, 4, m, 16)
+    h = _window("sine", n_ns)
+    st = _targets(77, 2)
+    for k in (0, 5):
+        rg = bf.Regrid(plan, st, window=h, n_taps=k)
+        got = rg(fft_i).cpu().numpy()
+        for c in range(4):
+            W = np.zeros((len(st), m))
+            ys = w.d_over_lambda()[c, 1] * st
+            fulls = orc.optimal_window_weights(h, m, ys)
+            for t, y in enumerate(ys):
+                full = fulls[t]
+                if k:
+                    first, taps = orc.compact_taps(full, y, k)
+                    W[t, (first + np.arange(k)) % m] = taps
+                else:
+                    W[t] = full
+            ref = orc.regrid_intensity(b[:, c], W)
+            scale = orc.regrid_intensity(b[:, c], np.abs(W))
+            assert np.all(np.abs(got[:, c] - ref) <= TOL_FP32 * scale)
+        rg.close()
+    plan.close()
+
+
 def test_regrid_at_zenith_is_the_fft_beam():
     """sin(theta) = 0 is the position of FFT beam A = 0 in every channel, so the
     regridded beam (a sum over all M beams: weight (2n-1)/M on A = 0 and
@@ -162,6 +269,12 @@ def test_regrid_empty_and_validation():
     with pytest.raises(bf.BFError) as e:
         bf.Regrid(plan, np.array([np.nan]))
     assert e.value.status == bf.BF_ERR_INVALID_ARGUMENT
+    for kw in ({"n_taps": 9}, {"n_taps": -1}, {"window": np.zeros(16)}, {"window": np.full(16, np.inf)}):
+        with pytest.raises(bf.BFError) as e:
+            bf.Regrid(plan, np.array([0.0]), **kw)
+        assert e.value.status == bf.BF_ERR_INVALID_ARGUMENT
+    with pytest.raises(ValueError):
+        bf.Regrid(plan, np.array([0.0]), window=np.ones(8))
     clamped.close()
     plan.close()
 
