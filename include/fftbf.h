@@ -176,16 +176,35 @@ bf_status bf_accumulate_intensity(const void *z, int64_t n_time, int64_t n_serie
  * exact for M >= 2n - 1.  Applied along N-S (M = 2n) for each E-W FFT beam,
  * so the same sin(theta) targets give achromatic beams in every channel
  * (the FFT beams' own positions move with wavelength, eq. e:theta_A).
- * The weights are generated in FP64 on the device at creation and stored
- * in FP32 ([n_chan][targets][m_ns], owned by the regrid object); the
- * contraction runs in FP32.
+ *
+ * With a window h (Sec. "Controlling beam shape with windowing"), the
+ * weights are those of the optimally windowed beam, eq. e:w_opt carried to
+ * the FFT beams by eq. e:wA_from_wdelta (eq. e:wA_windowed):
+ *     w^A = (1/M) [c_0 + 2 sum_{d=1}^{n-1} c_d cos(2 pi d (A/M - (d/lambda) sin(theta)))],
+ *     c_d = R_d / ((n - d) N),  R_d = sum_a h[a+d] h[a],
+ * N chosen so that the beam's noise equals the unwindowed pointed beam's
+ * (N = 1 without a window).  Pass intensities formed without a voltage
+ * taper for the beam of eq. e:w_opt.
+ *
+ * Compact kernels (n_taps = k > 0): only the k FFT beams nearest each
+ * target on the circular beam grid, A = rint(y M) - (k-1)/2 + j (mod M),
+ * j < k, with their full-kernel weights; an approximation, much cheaper
+ * than the dense form.
+ *
+ * The weights are generated in FP64 on the device at creation and stored in
+ * FP32 (owned by the regrid object); the contraction runs in FP32.
  */
 typedef struct bf_regrid bf_regrid;
 
 /* plan: the geometry and per-channel d/lambda, without a clamp (n_ns_keep 0
- * or m_ns).  sin_theta: host double [n_target] (copied).  Synchronous. */
+ * or m_ns).  sin_theta: host double [n_target] (copied), n_target in
+ * [1, 65536].  window: host double [n_ns] (real, copied) or NULL.  n_taps:
+ * 0 (dense, exact) or 1..8 (compact).  Synchronous.  Errors:
+ * BF_ERR_INVALID_ARGUMENT (NULLs, clamped plan, non-finite values, window
+ * without power, n_taps out of range), BF_ERR_UNSUPPORTED (m_ns < 2 n_ns - 1),
+ * BF_ERR_OUT_OF_MEMORY / BF_ERR_DEVICE. */
 bf_status bf_regrid_create(const bf_plan *plan, const double *sin_theta, int32_t n_target,
-                           bf_regrid **rg);
+                           const double *window, int32_t n_taps, bf_regrid **rg);
 bf_status bf_regrid_destroy(bf_regrid *rg);
 /* fft_intensity: device float [n_blk][n_chan][n_pol][m_ew][m_ns] as written by
  * bf_beamform_fft with the plan ([n_blk][n_chan][m_ew][m_ns] when it sums

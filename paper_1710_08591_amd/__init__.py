@@ -234,13 +234,22 @@ def accumulate_intensity(z, block: int, out=None, add: bool = False, stream=None
 
 
 class Regrid:
-    """Achromatic beams regridded from FFT-beam intensities (bf_regrid_*)."""
+    """Achromatic beams regridded from FFT-beam intensities (bf_regrid_*).
 
-    def __init__(self, plan: Plan, sin_theta: np.ndarray):
+    window: optional real N-S window [n_ns] for the optimally windowed beam;
+    n_taps: 0 for the exact dense kernel, 1..8 for the compact kernel."""
+
+    def __init__(self, plan: Plan, sin_theta: np.ndarray, window: Optional[np.ndarray] = None, n_taps: int = 0):
         st = np.ascontiguousarray(sin_theta, dtype=np.float64).ravel()
+        win = None
+        if window is not None:
+            win = np.ascontiguousarray(window, dtype=np.float64).ravel()
+            if len(win) != plan.n_ns:
+                raise ValueError("window must have n_ns entries")
         h = C.c_void_p()
-        check(lib().bf_regrid_create(plan.handle, st.ctypes.data_as(C.c_void_p), len(st), C.byref(h)),
-              "bf_regrid_create")
+        check(lib().bf_regrid_create(plan.handle, st.ctypes.data_as(C.c_void_p), len(st),
+                                     None if win is None else win.ctypes.data_as(C.c_void_p), int(n_taps),
+                                     C.byref(h)), "bf_regrid_create")
         self.handle = h
         self.n_target = len(st)
         # the plan's intensity layout: the polarisation axis is absent when it sums them

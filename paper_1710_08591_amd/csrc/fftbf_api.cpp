@@ -337,13 +337,46 @@ bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_
 }  // extern "C"
 
 struct bf_regrid {
-  int n_chan = 0, n_pg = 0, m_ew = 0, m_ns = 0, n_ns = 0, n_target = 0, pad = 0;
-  float* w = nullptr;
+  int n_chan = 0, n_pg = 0, m_ew = 0, m_ns = 0, n_ns = 0, n_target = 0, pad = 0, n_taps = 0;
+  float* w = nullptr;       // dense weights [n_chan][pad][m_ns]
+  int* first = nullptr;     // compact kernels [n_chan][n_target]
+  float* tw = nullptr;      //                 [n_chan][n_taps][n_target]
 };
+
+namespace {
+
+// Lag coefficients of the optimally windowed kernel (eq. e:w_opt): with the
+// window's auto-convolution R_d = sum_a h[a + d] h[a] (real window, so
+// R_-d = R_d), c_d = R_d / ((n - d) N) for d = 0 .. n-1, where N makes the
+// beam's noise equal to the unwindowed pointed beam's:
+// N = (1/n) sqrt(sum_{d=-(n-1)}^{n-1} R_d^2 / (n - |d|)).  Returns false when
+// the window has no power.
+bool window_lag_coefficients(const double* h, int n, std::vector<double>& c) {
+  std::vector<double> r(n, 0.0);
+  for (int d = 0; d < n; ++d)
+    for (int a = 0; a + d < n; ++a) r[d] += h[a + d] * h[a];
+  double s = r[0] * r[0] / n;
+  for (int d = 1; d < n; ++d) s += 2.0 * r[d] * r[d] / (n - d);
+  if (!(s > 0.0)) return false;
+  const double norm = std::sqrt(s) / n;
+  c.resize(n);
+  for (int d = 0; d < n; ++d) c[d] = r[d] / ((n - d) * norm);
+  return true;
+}
+
+void regrid_free(bf_regrid* r) {
+  if (r->w) (void)hipFree(r->w);
+  if (r->first) (void)hipFree(r->first);
+  if (r->tw) (void)hipFree(r->tw);
+  delete r;
+}
+
+}  // namespace
 
 extern "C" {
 
-bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t n_target, bf_regrid** rg) {
+bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t n_target, const double* window,
+                           int32_t n_taps, bf_regrid** rg) {
   if (!rg) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: NULL rg");
   *rg = nullptr;
   if (!plan || !sin_theta) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: NULL plan or sin_theta");
@@ -353,9 +386,19 @@ bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t
   if (d.m_ns < 2 * d.n_ns - 1)
     return fail(BF_ERR_UNSUPPORTED, "regrid_create: exact regridding needs m_ns >= 2 n_ns - 1");
   if (n_target < 1 || n_target > 65536) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: n_target out of [1, 65536]");
+  if (n_taps < 0 || n_taps > fftbf::kRegridMaxTaps)
+    return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: n_taps out of [0, %d]", fftbf::kRegridMaxTaps);
   for (int j = 0; j < n_target; ++j)
     if (!(sin_theta[j] >= -1e6 && sin_theta[j] <= 1e6))
       return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: sin_theta[%d] not finite", j);
+  std::vector<double> coef;
+  if (window) {
+    for (int a = 0; a < d.n_ns; ++a)
+      if (!(window[a] >= -1e30 && window[a] <= 1e30))
+        return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: window[%d] not finite", a);
+    if (!window_lag_coefficients(window, d.n_ns, coef))
+      return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: window has no power");
+  }
   bf_regrid* r = new (std::nothrow) bf_regrid();
   if (!r) return fail(BF_ERR_OUT_OF_MEMORY, "regrid_create: host allocation");
   r->n_chan = d.n_chan;
@@ -364,17 +407,31 @@ bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t
   r->m_ns = d.m_ns;
   r->n_ns = d.n_ns;
   r->n_target = n_target;
+  r->n_taps = n_taps;
   r->pad = fftbf::regrid_target_pad(n_target);
-  double* st = nullptr;
-  hipError_t e = hipMalloc(&r->w, sizeof(float) * (size_t)r->n_chan * r->pad * r->m_ns);
-  if (e == hipSuccess) e = hipMalloc(&st, sizeof(double) * n_target);
+  double *st = nullptr, *dcoef = nullptr;
+  hipError_t e = hipMalloc(&st, sizeof(double) * n_target);
   if (e == hipSuccess) e = hipMemcpy(st, sin_theta, sizeof(double) * n_target, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = fftbf::launch_regrid_weights(r->w, plan->dl, st, r->n_chan, n_target, r->n_ns, r->m_ns, nullptr);
+  if (e == hipSuccess && window) {
+    e = hipMalloc(&dcoef, sizeof(double) * d.n_ns);
+    if (e == hipSuccess) e = hipMemcpy(dcoef, coef.data(), sizeof(double) * d.n_ns, hipMemcpyHostToDevice);
+  }
+  if (n_taps == 0) {
+    if (e == hipSuccess) e = hipMalloc(&r->w, sizeof(float) * (size_t)r->n_chan * r->pad * r->m_ns);
+    if (e == hipSuccess)
+      e = fftbf::launch_regrid_weights(r->w, plan->dl, st, dcoef, r->n_chan, n_target, r->n_ns, r->m_ns, nullptr);
+  } else {
+    if (e == hipSuccess) e = hipMalloc(&r->first, sizeof(int) * (size_t)r->n_chan * n_target);
+    if (e == hipSuccess) e = hipMalloc(&r->tw, sizeof(float) * (size_t)r->n_chan * n_taps * n_target);
+    if (e == hipSuccess)
+      e = fftbf::launch_regrid_tap_table(r->first, r->tw, plan->dl, st, dcoef, r->n_chan, n_target, n_taps, r->n_ns,
+                                         r->m_ns, nullptr);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (st) (void)hipFree(st);
+  if (dcoef) (void)hipFree(dcoef);
   if (e != hipSuccess) {
-    if (r->w) (void)hipFree(r->w);
-    delete r;
+    regrid_free(r);
     return dev_fail(e, "regrid_create: weights");
   }
   *rg = r;
@@ -384,8 +441,7 @@ bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t
 bf_status bf_regrid_destroy(bf_regrid* rg) {
   if (!rg) return BF_OK;
   hipError_t e = hipDeviceSynchronize();
-  if (rg->w) (void)hipFree(rg->w);
-  delete rg;
+  regrid_free(rg);
   if (e != hipSuccess) return dev_fail(e, "regrid_destroy: pending device error");
   return BF_OK;
 }
@@ -409,6 +465,9 @@ bf_status bf_regrid_intensity(const bf_regrid* rg, const float* fft_intensity, i
   a.m_ns = rg->m_ns;
   a.n_target = rg->n_target;
   a.n_target_pad = rg->pad;
+  a.n_taps = rg->n_taps;
+  a.first = rg->first;
+  a.tw = rg->tw;
   hipError_t e = fftbf::launch_regrid(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return dev_fail(e, "regrid_intensity: launch");
   return BF_OK;

@@ -33,8 +33,33 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__global__ void k_regrid_weights(float* w, const double* dl, const double* sin_t, int n_chan, int n_target,
-                                 int n_target_pad, int n, int m) {
+// Weight w^A of FFT beam A for the steering y (FP64).  coef == nullptr: the
+// pointed kernel of eq. e:bp_max_arbitrary in closed form.  Otherwise the
+// optimally windowed kernel (eq. e:w_opt mapped by eq. e:wA_from_wdelta):
+// w^A = (1/M) [c_0 + 2 sum_{d=1}^{n-1} c_d cos(2 pi d (A/M - y))] with the
+// window's lag coefficients c_d = R_d / ((n - d) N), summed with a
+// unit-modulus recurrence.
+__device__ double regrid_weight(int A, double y, int n, int m, const double* coef) {
+  const double ya = y - (double)A / (double)m;
+  if (!coef) {
+    const double den = sinpi(ya);
+    if (fabs(den) < 1e-12) return (double)(2 * n - 1) / m;
+    return sinpi((double)(2 * n - 1) * ya) / den / m;
+  }
+  double s1, c1;
+  sincospi(2.0 * ya, &s1, &c1);
+  double er = c1, ei = s1, acc = coef[0];
+  for (int d = 1; d < n; ++d) {
+    acc += 2.0 * coef[d] * er;
+    const double nr = er * c1 - ei * s1;
+    ei = er * s1 + ei * c1;
+    er = nr;
+  }
+  return acc / m;
+}
+
+__global__ void k_regrid_weights(float* w, const double* dl, const double* sin_t, const double* coef, int n_chan,
+                                 int n_target, int n_target_pad, int n, int m) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)n_chan * n_target_pad * m;
   if (i >= total) return;
@@ -45,15 +70,25 @@ __global__ void k_regrid_weights(float* w, const double* dl, const double* sin_t
     w[i] = 0.f;
     return;
   }
-  const double y = dl[2 * c + 1] * sin_t[j] - (double)A / (double)m;
-  const double den = sinpi(y);
-  double v;
-  if (fabs(den) < 1e-12) {
-    v = (double)(2 * n - 1);
-  } else {
-    v = sinpi((double)(2 * n - 1) * y) / den;
-  }
-  w[i] = (float)(v / m);
+  w[i] = (float)regrid_weight(A, dl[2 * c + 1] * sin_t[j], n, m, coef);
+}
+
+// Compact kernels: the k FFT beams nearest the steering on the circular beam
+// grid, first = rint(y M) - (k-1)/2 (mod M), with their full-kernel weights.
+// Layout: first[chan][target], tw[chan][tap][target].
+__global__ void k_regrid_tap_table(int* first, float* tw, const double* dl, const double* sin_t, const double* coef,
+                                   int n_chan, int n_target, int k, int n, int m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n_chan * k * n_target;
+  if (i >= total) return;
+  const int t = (int)(i % n_target);
+  const int j = (int)((i / n_target) % k);
+  const int c = (int)(i / ((int64_t)n_target * k));
+  const double y = dl[2 * c + 1] * sin_t[t];
+  const int64_t f0 = (int64_t)rint(y * (double)m) - (k - 1) / 2;
+  const int f = (int)(((f0 % m) + m) % m);
+  if (j == 0) first[(int64_t)c * n_target + t] = f;
+  tw[i] = (float)regrid_weight((f + j) % m, y, n, m, coef);
 }
 
 // KC: beams per chunk (32 when M = 32, else 64).  NT: 16-target MFMA tiles
@@ -140,6 +175,47 @@ __global__ __launch_bounds__(256, 2) void k_regrid(RegridArgs a) {
   }
 }
 
+// Compact-kernel regridding (K taps per target): an HBM-bound gather.  A
+// 256-thread workgroup stages 16 rows (all M beams) of one channel in LDS with
+// float4 loads; each thread then takes targets t = tid, tid + 256, ... and
+// forms sum_j tw[j][t] I[row][(first[t] + j) mod M] for the 16 rows, writing
+// each row's targets contiguously.
+template <int K>
+__global__ __launch_bounds__(256) void k_regrid_taps(RegridArgs a) {
+  constexpr int RT = 16;
+  __shared__ __attribute__((aligned(16))) float lds[RT * 512];
+  const int tid = threadIdx.x, chan = blockIdx.y;
+  const int m = a.m_ns, mv = m >> 2;
+  const int r0 = blockIdx.x * RT;
+  const int nr = min(RT, a.rows_per_chan - r0);
+  const int lr = a.log2_r, rmask = (1 << lr) - 1;
+  auto grow = [&](int r) -> int64_t { return ((int64_t)(r >> lr) * a.n_chan + chan) * (1 << lr) + (r & rmask); };
+  for (int idx = tid; idx < nr * mv; idx += 256) {
+    const int rr = idx / mv, c4 = idx - rr * mv;
+    *reinterpret_cast<f32x4*>(&lds[rr * m + 4 * c4]) =
+        *reinterpret_cast<const f32x4*>(a.in + grow(r0 + rr) * m + 4 * c4);
+  }
+  __syncthreads();
+  const int T = a.n_target;
+  for (int t = tid; t < T; t += 256) {
+    const int f = a.first[(int64_t)chan * T + t];
+    float w[K];
+    int ix[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      w[j] = a.tw[((int64_t)chan * K + j) * T + t];
+      ix[j] = (f + j) & (m - 1);
+    }
+    for (int rr = 0; rr < nr; ++rr) {
+      const float* row = &lds[rr * m];
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j) acc = fmaf(w[j], row[ix[j]], acc);
+      a.out[grow(r0 + rr) * T + t] = acc;
+    }
+  }
+}
+
 template <int KC>
 hipError_t launch_kc(const RegridArgs& a, dim3 grid, bool wide, hipStream_t s) {
   if (wide)
@@ -157,12 +233,20 @@ int regrid_target_pad(int n_target) {
   return n_target <= 64 ? 64 : (n_target + 255) / 256 * 256;
 }
 
-hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t, int n_chan, int n_target,
-                                 int n, int m, hipStream_t s) {
+hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t, const double* coef, int n_chan,
+                                 int n_target, int n, int m, hipStream_t s) {
   const int pad = regrid_target_pad(n_target);
   const int64_t total = (int64_t)n_chan * pad * m;
-  hipLaunchKernelGGL(k_regrid_weights, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, dl, sin_t, n_chan,
-                     n_target, pad, n, m);
+  hipLaunchKernelGGL(k_regrid_weights, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, dl, sin_t, coef,
+                     n_chan, n_target, pad, n, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_regrid_tap_table(int* first, float* tw, const double* dl, const double* sin_t, const double* coef,
+                                   int n_chan, int n_target, int k, int n, int m, hipStream_t s) {
+  const int64_t total = (int64_t)n_chan * k * n_target;
+  hipLaunchKernelGGL(k_regrid_tap_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, first, tw, dl, sin_t,
+                     coef, n_chan, n_target, k, n, m);
   return hipGetLastError();
 }
 
@@ -177,6 +261,21 @@ hipError_t launch_regrid(const RegridArgs& a_in, hipStream_t s) {
   if (rows == 0) return hipSuccess;
   if (rows > 0x7FFFFF00LL || a.n_chan > 65535) return hipErrorInvalidConfiguration;
   a.rows_per_chan = (int)rows;
+  if (a.n_taps > 0) {
+    if (a.n_taps > kRegridMaxTaps || a.m_ns > 512) return hipErrorNotSupported;
+    const dim3 g((unsigned)((rows + 15) / 16), (unsigned)a.n_chan);
+    switch (a.n_taps) {
+      case 1: hipLaunchKernelGGL(k_regrid_taps<1>, g, dim3(256), 0, s, a); break;
+      case 2: hipLaunchKernelGGL(k_regrid_taps<2>, g, dim3(256), 0, s, a); break;
+      case 3: hipLaunchKernelGGL(k_regrid_taps<3>, g, dim3(256), 0, s, a); break;
+      case 4: hipLaunchKernelGGL(k_regrid_taps<4>, g, dim3(256), 0, s, a); break;
+      case 5: hipLaunchKernelGGL(k_regrid_taps<5>, g, dim3(256), 0, s, a); break;
+      case 6: hipLaunchKernelGGL(k_regrid_taps<6>, g, dim3(256), 0, s, a); break;
+      case 7: hipLaunchKernelGGL(k_regrid_taps<7>, g, dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL(k_regrid_taps<8>, g, dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+  }
   const bool wide = a.n_target_pad > 64;
   const int tt = wide ? a.n_target_pad / 256 : 1;
   const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)tt, (unsigned)a.n_chan);

@@ -69,13 +69,20 @@ struct RegridArgs {
   const float* in;         // [n_blk][n_chan][n_pg][m_ew][m_ns]
   const float* w;          // [n_chan][n_target_pad][m_ns]
   float* out;              // [n_blk][n_chan][n_pg][m_ew][n_target]
+  const int* first;        // compact kernels: [n_chan][n_target] first tap (mod m_ns)
+  const float* tw;         //                  [n_chan][n_taps][n_target] tap weights
   int64_t n_blk;
   int n_chan, n_pg, m_ew, m_ns, n_target, n_target_pad;
+  int n_taps;              // 0: dense weights w; 1..kRegridMaxTaps: compact kernels
   int rows_per_chan, log2_r;   // set by launch_regrid
 };
+constexpr int kRegridMaxTaps = 8;
 int regrid_target_pad(int n_target);
-hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t, int n_chan, int n_target,
-                                 int n, int m, hipStream_t s);
+// coef: device double [n] window lag coefficients, or nullptr for the pointed kernel
+hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t, const double* coef, int n_chan,
+                                 int n_target, int n, int m, hipStream_t s);
+hipError_t launch_regrid_tap_table(int* first, float* tw, const double* dl, const double* sin_t, const double* coef,
+                                   int n_chan, int n_target, int k, int n, int m, hipStream_t s);
 hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);
 
 // mixed-precision (MFMA) beamformer
