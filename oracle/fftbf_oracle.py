@@ -44,6 +44,7 @@ __all__ = [
     "interp_weights", "interpolate_beams", "rel_power_error",
     "window_autocorr", "optimal_window_norm", "optimal_window_lag_weights",
     "optimal_window_weights", "compact_taps", "regrid_intensity",
+    "baseline_moi", "pointed_power_and_slope", "localize_row", "localize",
 ]
 
 
@@ -344,6 +345,83 @@ def compact_taps(w: np.ndarray, y: float, k: int):
 def regrid_intensity(b: np.ndarray, weights: np.ndarray) -> np.ndarray:
     """Regridded beams sum_A w^A b_A: b [..., M] intensities, weights [T][M] -> [..., T]."""
     return np.asarray(b, dtype=np.float64) @ np.asarray(weights, dtype=np.float64).T
+
+
+def baseline_moi(n: int) -> int:
+    """sum over lags of delta^2 (n - |delta|) for a linear array: the moment
+    of inertia of the baseline distribution (eq. e:baseline_MOI), summed term
+    by term."""
+    return sum(d * d * (n - abs(d)) for d in range(-(n - 1), n))
+
+
+def pointed_power_and_slope(b: np.ndarray, beams: np.ndarray, n: int, m: int, y: float):
+    """(b_p(y), d b_p / dy) from FFT-beam intensities b over the listed beams.
+
+    b_p(y) = sum_A w^A(y) b_A with the regridding weights of eq.
+    e:bp_max_arbitrary written as their lag sum,
+    w^A(y) = (1/M) sum_{|delta|<n} e^{+i 2 pi delta (A/M - y)}, and its
+    derivative in y term by term.
+    """
+    lag = np.arange(-(n - 1), n)
+    ph = np.exp(2j * np.pi * np.outer(np.asarray(beams) / m - y, lag))     # [K][2n-1]
+    w = ph.sum(axis=1).real / m
+    dw = (ph * (-2j * np.pi * lag)).sum(axis=1).real / m
+    bb = np.asarray(b, dtype=np.float64)[np.asarray(beams)]
+    return float(w @ bb), float(dw @ bb)
+
+
+def localize_row(b: np.ndarray, n: int, d_over_lambda: float, n_window: int, n_iter: int):
+    """Newton's-method estimate of a point source's sin(theta) from one row of
+    M FFT-beam intensities of a linear array (Sec. "Localization").
+
+    Steps, in the paper's order:
+    * initial guess: the beam of strongest detection, y_0 = A_0 / M
+      (A_0 = first index of the maximum);
+    * sums truncated to the n_window beams nearest A_0 on the circular grid
+      (the paper keeps the ~10 beams around the source; n_window = M keeps
+      all), A = A_0 - (n_window - 1)//2 + j mod M;
+    * update with the curvature replaced by its value at the maximum (the
+      baseline moment of inertia, eq. e:baseline_MOI), in y = (d/lambda) sin(theta):
+          y <- y + n^2 b_p'(y) / (4 pi^2 MOI b_p(y)),
+      i.e. the first form of the paper's final estimator (its second form
+      prints n^3 where the substitution gives n^2);
+    * n_iter updates; an update is not taken (and the iteration stops) when
+      b_p(y) <= 0 or when it would leave [y_0 - 1/M, y_0 + 1/M] (the maximum
+      lies within half a beam spacing of the strongest beam, so a step beyond
+      one spacing is heading for a sidelobe).
+    Returns (sin(theta) estimate with y wrapped to [-1/2, 1/2), b_p at it).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    m = len(b)
+    a0 = int(np.argmax(b))
+    beams = (a0 - (n_window - 1) // 2 + np.arange(n_window)) % m
+    moi = baseline_moi(n)
+    y0 = a0 / m
+    y = y0
+    for _ in range(n_iter):
+        p, dp = pointed_power_and_slope(b, beams, n, m, y)
+        if not p > 0:
+            break
+        y_new = y + n * n * dp / (4 * np.pi ** 2 * moi * p)
+        if abs(y_new - y0) > 1.0 / m:
+            break
+        y = y_new
+    p, _ = pointed_power_and_slope(b, beams, n, m, y)
+    yw = (y + 0.5) % 1.0 - 0.5
+    return yw / d_over_lambda, p
+
+
+def localize(intensity: np.ndarray, n: int, d_over_lambda_ns: np.ndarray, n_window: int, n_iter: int,
+             chans=None):
+    """localize_row over every row of [blk][chan][..][M] intensities; returns
+    (sin(theta) [blk][chan][..], peak [blk][chan][..])."""
+    x = np.asarray(intensity, dtype=np.float64)
+    chans = np.arange(x.shape[1]) if chans is None else np.asarray(chans)
+    st = np.empty(x.shape[:-1])
+    pk = np.empty(x.shape[:-1])
+    for idx in np.ndindex(*x.shape[:-1]):
+        st[idx], pk[idx] = localize_row(x[idx], n, float(d_over_lambda_ns[chans[idx[1]]]), n_window, n_iter)
+    return st, pk
 
 
 def interp_weights(n: int, m: int, y: np.ndarray) -> np.ndarray:

@@ -365,6 +365,77 @@ def test_compact_taps_nearest_beams():
         assert np.sum(taps ** 2) > 0.99 * np.sum(w ** 2)
 
 
+# ------------------------------------------------------ localisation -----
+
+def test_baseline_moi_closed_form():
+    """eq. e:baseline_MOI: the lag sum equals the printed closed form and tends to n^4/6."""
+    for n in range(1, 41):
+        closed = 2 * n * n * (n - 1) * ((2 * n - 1) / 6 - (n - 1) / 4)
+        assert abs(orc.baseline_moi(n) - closed) < 1e-9 * max(1, closed)
+    assert abs(orc.baseline_moi(256) / (256 ** 4 / 6) - 1) < 0.01
+
+
+def _point_source_beams(n, m, y, amp=1.0):
+    eta = amp * np.exp(2j * np.pi * np.arange(n) * y)[None, :]
+    return _beams_1d(eta, m)
+
+
+def test_pointed_slope_is_derivative_of_power():
+    n, m = 16, 32
+    rng = np.random.default_rng(2)
+    b = rng.random(m) * 10
+    beams = np.arange(m)
+    for y in (0.013, 0.3, -0.21):
+        p0, dp = orc.pointed_power_and_slope(b, beams, n, m, y)
+        h = 1e-6
+        num = (orc.pointed_power_and_slope(b, beams, n, m, y + h)[0]
+               - orc.pointed_power_and_slope(b, beams, n, m, y - h)[0]) / (2 * h)
+        assert abs(dp - num) < 1e-6 * max(1.0, abs(dp))
+        assert abs(p0 - b @ orc.regrid_weights_paper(n, m, y)) < 1e-10 * abs(p0)
+
+
+@pytest.mark.parametrize("n,m", [(16, 32), (32, 64), (8, 15)])
+def test_localize_noise_free_source(n, m):
+    """A noise-free point source: with all M beams the estimator's fixed point
+    is the source (flux T cancels), the peak is the pointed beam's n T, and the
+    ~10-beam truncation moves it by a negligible fraction of a beam."""
+    for ys, amp in ((0.1234, 1.0), (-0.3011, 3.0), (0.2, 0.5)):
+        b = _point_source_beams(n, m, ys, amp)
+        for scale in (1.0, 1e-3, 7.5):
+            st, pk = orc.localize_row(scale * b, n, 0.8, m, 8)
+            assert abs(st * 0.8 - ys) < 1e-11
+            assert abs(pk - scale * n * amp ** 2) < 1e-9 * scale * n * amp ** 2
+        st, _ = orc.localize_row(b, n, 0.8, 10, 8)
+        assert abs(st * 0.8 - ys) < 0.01 / m
+
+
+def test_localize_variance_matches_printed_uncertainty():
+    """Sec. "Localization": once converged, the estimator's standard deviation
+    is (sqrt(6) / 2 pi) (lambda / (n d)) / SNR, SNR being the pointed beam's
+    signal-to-noise ratio.  Monte Carlo under the simple noise model:
+    stacked visibilities (n - |delta|) T e^{i 2 pi delta y_s} plus independent
+    noise of variance (n - |delta|) sigma^2 per lag (Hermitian), beams from
+    eq. e:b2n-1, so that the pointed beam's noise is sigma and SNR = n T / sigma."""
+    n, m, snr, trials = 16, 32, 25.0, 3000
+    rng = np.random.default_rng(12)
+    lag = np.arange(-(n - 1), n)
+    red = n - np.abs(lag)
+    est = []
+    for _ in range(trials):
+        ys = rng.uniform(-0.5, 0.5)
+        sig = red * np.exp(2j * np.pi * lag * ys)               # T = 1
+        sigma = n / snr
+        pos = (rng.normal(size=n - 1) + 1j * rng.normal(size=n - 1)) * np.sqrt(red[n:] / 2.0) * sigma
+        noise = np.concatenate([np.conj(pos[::-1]), [rng.normal() * np.sqrt(n) * sigma], pos])
+        b = orc.beam_power_from_stacked(sig + noise, n, m)
+        st, _ = orc.localize_row(b, n, 1.0, m, 6)
+        est.append(((st - ys) + 0.5) % 1.0 - 0.5)
+    est = np.array(est)
+    predicted = np.sqrt(6) / (2 * np.pi) / n / snr
+    assert abs(np.mean(est)) < 4 * predicted / np.sqrt(trials)
+    assert abs(np.std(est) / predicted - 1) < 0.06
+
+
 # ------------------------------------------------------ small pieces ------
 
 def test_accumulate_constant_modulus():
