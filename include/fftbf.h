@@ -216,6 +216,33 @@ bf_status bf_regrid_intensity(const bf_regrid *rg, const float *fft_intensity, i
                               float *out, void *stream);
 
 /*
+ * ---- Localisation of a point source (Sec. "Localization") ----
+ * Newton's-method maximum-likelihood estimate of sin(theta) along N-S, for
+ * every row (block, channel, polarisation, E-W beam) of FFT-beam
+ * intensities.  In y = (d/lambda) sin(theta), with the regridded pointed
+ * beam b_p(y) = sum_A w^A(y) b_A of eq. e:bp_max_arbitrary:
+ *     y <- y + n^2 b_p'(y) / (4 pi^2 MOI b_p(y)),
+ *     MOI = sum_delta delta^2 (n - |delta|)        (eq. e:baseline_MOI),
+ * the likelihood's curvature taken at its maximum, so the source flux
+ * cancels.  Start: y_0 = A_0 / M for the strongest beam A_0 (lowest index on
+ * ties).  Sums over the n_window beams A_0 - (n_window-1)/2 + j (mod M).
+ * n_iter updates; an update is not taken, and the iteration stops, when
+ * b_p(y) <= 0 or when it would leave [y_0 - 1/M, y_0 + 1/M].  The estimator
+ * is meant for the source's contribution to the intensities (background
+ * removed); the arithmetic is applied to whatever is passed.  FP64.
+ *
+ * plan: without a clamp, m_ns >= 2 n_ns - 1 (d/lambda per channel from the
+ * plan).  fft_intensity: device float [n_blk][n_chan][n_pol][m_ew][m_ns]
+ * ([n_blk][n_chan][m_ew][m_ns] when the plan sums polarisations), finite.
+ * n_window in [1, min(64, m_ns)], n_iter in [0, 64].
+ * sin_theta: device double, one per row (y wrapped to [-1/2, 1/2) and divided
+ * by d/lambda); peak: device float b_p at the estimate, one per row, or NULL.
+ * n_blk = 0 is a no-op.  Asynchronous on stream; the caller owns the buffers.
+ */
+bf_status bf_localize(const bf_plan *plan, const float *fft_intensity, int64_t n_blk, int32_t n_window,
+                      int32_t n_iter, double *sin_theta, float *peak, void *stream);
+
+/*
  * ---- Tied-beam server --------------------------------------------------
  * Serves tied-array beam requests (arbitrary pointings, a contiguous channel
  * range, the most recent n_time samples) from a device-resident voltage ring

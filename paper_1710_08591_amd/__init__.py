@@ -20,7 +20,7 @@ from ._lib import (bf_server_stats, BF_OK, BF_ERR_INVALID_ARGUMENT, BF_ERR_UNSUP
 
 __all__ = [
     "Plan", "plan_create", "plan_destroy", "beamform_fft", "form_tied_beams", "form_tied_beams_v",
-    "accumulate_intensity", "Regrid", "Server", "lib", "BFError", "LibraryMissing",
+    "accumulate_intensity", "Regrid", "localize", "Server", "lib", "BFError", "LibraryMissing",
     "BF_PREC_FP32", "BF_PREC_FP16_MFMA", "BF_PREC_FP8_MFMA", "BF_OUT_INTENSITY", "BF_OUT_COMPLEX",
 ]
 
@@ -231,6 +231,26 @@ def accumulate_intensity(z, block: int, out=None, add: bool = False, stream=None
     check(lib().bf_accumulate_intensity(_ptr(z), n_time, n_series, block, int(add), _ptr(out),
                                         _stream_handle(stream)), "bf_accumulate_intensity")
     return out
+
+
+def localize(plan: Plan, fft_intensity, n_window: int = 10, n_iter: int = 6, stream=None):
+    """Newton localisation per row of unclamped FFT-beam intensities (bf_localize).
+
+    Returns (sin_theta float64, peak float32), shaped like the intensities
+    without their last (N-S beam) axis."""
+    torch = _torch()
+    _need(fft_intensity, torch.float32, "fft_intensity")
+    shape = ((plan.n_chan, plan.m_ew, plan.m_ns) if plan.pol_sum
+             else (plan.n_chan, plan.n_pol, plan.m_ew, plan.m_ns))
+    if tuple(fft_intensity.shape[1:]) != shape:
+        raise ValueError(f"fft_intensity must be [n_blk]{list(shape)}")
+    n_blk = fft_intensity.shape[0]
+    out_shape = (n_blk,) + shape[:-1]
+    st = torch.empty(out_shape, dtype=torch.float64, device=fft_intensity.device)
+    pk = torch.empty(out_shape, dtype=torch.float32, device=fft_intensity.device)
+    check(lib().bf_localize(plan.handle, _ptr(fft_intensity), n_blk, int(n_window), int(n_iter), _ptr(st),
+                            _ptr(pk), _stream_handle(stream)), "bf_localize")
+    return st, pk
 
 
 class Regrid:

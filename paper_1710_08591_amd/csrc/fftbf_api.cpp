@@ -473,6 +473,42 @@ bf_status bf_regrid_intensity(const bf_regrid* rg, const float* fft_intensity, i
   return BF_OK;
 }
 
+bf_status bf_localize(const bf_plan* plan, const float* fft_intensity, int64_t n_blk, int32_t n_window,
+                      int32_t n_iter, double* sin_theta, float* peak, void* stream) {
+  if (!plan) return fail(BF_ERR_INVALID_ARGUMENT, "localize: NULL plan");
+  const bf_plan_desc& d = plan->d;
+  if (plan->sel || keep_of(d) != d.m_ns)
+    return fail(BF_ERR_INVALID_ARGUMENT, "localize: needs a plan without a clamp (all m_ns beams)");
+  if (d.m_ns < 2 * d.n_ns - 1)
+    return fail(BF_ERR_UNSUPPORTED, "localize: the estimator needs m_ns >= 2 n_ns - 1");
+  if (n_blk < 0) return fail(BF_ERR_INVALID_ARGUMENT, "localize: negative n_blk");
+  if (n_window < 1 || n_window > 64 || n_window > d.m_ns)
+    return fail(BF_ERR_INVALID_ARGUMENT, "localize: n_window out of [1, min(64, m_ns)]");
+  if (n_iter < 0 || n_iter > 64) return fail(BF_ERR_INVALID_ARGUMENT, "localize: n_iter out of [0, 64]");
+  if (n_blk == 0) return BF_OK;
+  if (!fft_intensity || !sin_theta) return fail(BF_ERR_INVALID_ARGUMENT, "localize: NULL intensity or sin_theta");
+  if (!aligned(fft_intensity, 4) || !aligned(sin_theta, 8) || (peak && !aligned(peak, 4)))
+    return fail(BF_ERR_INVALID_ARGUMENT, "localize: misaligned buffer");
+  fftbf::LocArgs a{};
+  a.in = fft_intensity;
+  a.dl = plan->dl;
+  a.sin_out = sin_theta;
+  a.peak_out = peak;
+  a.rows_per_chan_blk = (int64_t)(d.pol_sum ? 1 : d.n_pol) * d.m_ew;
+  a.n_rows = n_blk * d.n_chan * a.rows_per_chan_blk;
+  a.n_chan = d.n_chan;
+  a.n = d.n_ns;
+  a.m = d.m_ns;
+  a.n_window = n_window;
+  a.n_iter = n_iter;
+  int64_t moi = 0;
+  for (int64_t k = 1; k < d.n_ns; ++k) moi += 2 * k * k * (d.n_ns - k);
+  a.moi = (double)moi;
+  hipError_t e = fftbf::launch_localize(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return dev_fail(e, "localize: launch");
+  return BF_OK;
+}
+
 bf_status bf_accumulate_intensity(const void* z, int64_t n_time, int64_t n_series, int32_t block, int32_t add,
                                   float* out, void* stream) {
   if (n_time < 0 || n_series < 0) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: negative size");

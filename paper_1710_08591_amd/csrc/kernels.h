@@ -85,6 +85,19 @@ hipError_t launch_regrid_tap_table(int* first, float* tw, const double* dl, cons
                                    int n_chan, int n_target, int k, int n, int m, hipStream_t s);
 hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);
 
+// Newton localisation over rows of FFT-beam intensities
+struct LocArgs {
+  const float* in;         // [n_rows][m] (rows = (blk, chan, pol group, E-W beam))
+  const double* dl;        // [n_chan][2] d/lambda (ew, ns)
+  double* sin_out;         // [n_rows]
+  float* peak_out;         // [n_rows] or nullptr
+  int64_t n_rows;
+  int64_t rows_per_chan_blk;   // rows per (blk, chan) = n_pg * m_ew
+  int n_chan, n, m, n_window, n_iter;
+  double moi;              // sum over lags of delta^2 (n - |delta|)
+};
+hipError_t launch_localize(const LocArgs& a, hipStream_t s);
+
 // mixed-precision (MFMA) beamformer
 struct MixArgs {
   const uint32_t* volts;
