@@ -50,6 +50,14 @@ __all__ = [
 
 # ---------------------------------------------------------------- decode ---
 
+def _weights(h) -> np.ndarray:
+    """Per-antenna weights as given: real windows (Sec. "Controlling beam
+    shape with windowing") stay real, complex per-antenna gains
+    e^{gamma + i psi} (eq. e:vis_pert, Sec. "Non-redundancy") stay complex."""
+    h = np.asarray(h)
+    return h.astype(np.complex128) if np.iscomplexobj(h) else h.astype(np.float64)
+
+
 def decode_int4(volts: np.ndarray) -> np.ndarray:
     """uint8 voltages -> complex128 (two's complement nibbles, re high).
 
@@ -90,7 +98,7 @@ def fft_beams(eta: np.ndarray, m_ew: int, m_ns: int, taper: Optional[np.ndarray]
     n_ns, n_ew = eta.shape[-2], eta.shape[-1]
     if m_ew < n_ew or m_ns < n_ns:
         raise ValueError("transform shorter than the array needs cyclic co-adding")
-    x = eta if taper is None else eta * np.asarray(taper, dtype=np.float64)
+    x = eta if taper is None else eta * _weights(taper)
     w_ew = dft_matrix(n_ew, m_ew)            # [m_ew][n_ew]
     w_ns = dft_matrix(n_ns, m_ns)            # [m_ns][n_ns]
     # B[..., A_ew, A_ns] = sum_{a_ns, a_ew} w_ew[A_ew, a_ew] w_ns[A_ns, a_ns] x[..., a_ns, a_ew]
@@ -153,7 +161,7 @@ def tied_beams(volts: np.ndarray, dircos: np.ndarray, d_over_lambda: np.ndarray,
     """
     eta = decode_int4(volts)
     if taper is not None:
-        eta = eta * np.asarray(taper, dtype=np.float64)
+        eta = eta * _weights(taper)
     n_t, n_c, n_p, n_ns, n_ew = eta.shape
     chans = np.arange(n_c) if chans is None else np.asarray(chans)
     dircos = np.asarray(dircos, dtype=np.float64)
