@@ -121,6 +121,18 @@ bf_status bf_beamform_fft(const bf_plan *plan, const uint8_t *volts, int64_t n_t
                           const float *taper, int32_t kind, void *out, void *stream);
 
 /*
+ * bf_beamform_fft with complex per-antenna gains in place of the real
+ * window: eta_a -> g_a eta_a before the transform, g_a = e^{gamma_a + i psi_a}
+ * the per-antenna amplitude and phase response of eq. e:vis_pert (Sec.
+ * "Non-redundancy"), or the inverse of estimated gains (calibration).
+ *   gains  device float [n_ns][n_ew][2] (re, im), 16-byte aligned, not NULL.
+ * FP32 plans only (BF_ERR_UNSUPPORTED otherwise); every other argument,
+ * layout and error as bf_beamform_fft.
+ */
+bf_status bf_beamform_fft_gains(const bf_plan *plan, const uint8_t *volts, int64_t n_time,
+                                const float *gains, int32_t kind, void *out, void *stream);
+
+/*
  * Tied-array (pointed) beams at arbitrary directions, formed by
  * interpolating complex FFT beams.  The weights follow from substituting
  * the zero-padded inverse transform into the pointed-beam weights of eq.

@@ -129,17 +129,27 @@ def plan_destroy(plan: Plan) -> None:
     plan.close()
 
 
-def beamform_fft(plan: Plan, volts, taper=None, kind: int = BF_OUT_INTENSITY, out=None, stream=None):
-    """FFT beams of ``volts`` (uint8 [t][chan][pol][n_ns][n_ew]) -> intensities or complex beams."""
+def beamform_fft(plan: Plan, volts, taper=None, kind: int = BF_OUT_INTENSITY, out=None, stream=None,
+                 gains=None):
+    """FFT beams of ``volts`` (uint8 [t][chan][pol][n_ns][n_ew]) -> intensities or complex beams.
+
+    taper: real float32 [n_ns][n_ew] weights (bf_beamform_fft); gains: complex64
+    [n_ns][n_ew] per-antenna gains (bf_beamform_fft_gains).  At most one."""
     torch = _torch()
     _need(volts, torch.uint8, "volts")
     n_time = volts.shape[0]
     if tuple(volts.shape) != plan.volts_shape(n_time):
         raise ValueError(f"volts shape {tuple(volts.shape)} != {plan.volts_shape(n_time)}")
+    if taper is not None and gains is not None:
+        raise ValueError("pass a real taper or complex gains, not both")
     if taper is not None:
         _need(taper, torch.float32, "taper")
         if tuple(taper.shape) != (plan.n_ns, plan.n_ew):
             raise ValueError("taper must be [n_ns][n_ew]")
+    if gains is not None:
+        _need(gains, torch.complex64, "gains")
+        if tuple(gains.shape) != (plan.n_ns, plan.n_ew):
+            raise ValueError("gains must be [n_ns][n_ew]")
     shape = plan.out_shape(n_time, kind)
     dt = torch.complex64 if kind == BF_OUT_COMPLEX else torch.float32
     if out is None:
@@ -148,8 +158,12 @@ def beamform_fft(plan: Plan, volts, taper=None, kind: int = BF_OUT_INTENSITY, ou
         _need(out, dt, "out")
         if tuple(out.shape) != shape:
             raise ValueError(f"out shape {tuple(out.shape)} != {shape}")
-    check(lib().bf_beamform_fft(plan.handle, _ptr(volts), n_time, _ptr(taper), kind, _ptr(out),
-                                _stream_handle(stream)), "bf_beamform_fft")
+    if gains is not None:
+        check(lib().bf_beamform_fft_gains(plan.handle, _ptr(volts), n_time, _ptr(gains), kind, _ptr(out),
+                                          _stream_handle(stream)), "bf_beamform_fft_gains")
+    else:
+        check(lib().bf_beamform_fft(plan.handle, _ptr(volts), n_time, _ptr(taper), kind, _ptr(out),
+                                    _stream_handle(stream)), "bf_beamform_fft")
     return out
 
 

@@ -55,6 +55,7 @@ _SIGS = {
     "bf_plan_destroy": (C.c_int32, [_P]),
     "bf_plan_get_desc": (C.c_int32, [_P, C.POINTER(bf_plan_desc)]),
     "bf_beamform_fft": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P]),
+    "bf_beamform_fft_gains": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P]),
     "bf_form_tied_beams": (C.c_int32, [_P, _P, C.c_int64, C.c_int32, C.c_int32, _P, C.c_int32,
                                        C.c_int32, _P, _P]),
     "bf_form_tied_beams_v": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, C.c_int32, _P, C.c_int32,

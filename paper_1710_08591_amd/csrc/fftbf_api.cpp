@@ -175,8 +175,11 @@ bf_status bf_plan_get_desc(const bf_plan* plan, bf_plan_desc* desc) {
   return BF_OK;
 }
 
-bf_status bf_beamform_fft(const bf_plan* plan, const uint8_t* volts, int64_t n_time,
-                          const float* taper, int32_t kind, void* out, void* stream) {
+}  // extern "C"
+
+// taper_kind: 1 real weights [n_ns][n_ew], 2 complex gains [n_ns][n_ew][2]
+static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
+                                   int taper_kind, int32_t kind, void* out, void* stream) {
   if (!plan) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: NULL plan");
   const bf_plan_desc& d = plan->d;
   if (kind != BF_OUT_INTENSITY && kind != BF_OUT_COMPLEX)
@@ -219,7 +222,7 @@ bf_status bf_beamform_fft(const bf_plan* plan, const uint8_t* volts, int64_t n_t
     a.out = out;
     const float inv_n = 1.0f / float(d.n_ew * d.n_ns);
     a.norm = (kind == BF_OUT_COMPLEX) ? 1.0f / std::sqrt(float(d.n_ew * d.n_ns)) : inv_n;
-    e = fftbf::launch_fft32(a, d.n_ns, taper != nullptr, kind == BF_OUT_COMPLEX, n_wg, s);
+    e = fftbf::launch_fft32(a, d.n_ns, taper ? taper_kind : 0, kind == BF_OUT_COMPLEX, n_wg, s);
   } else {
     fftbf::MixArgs a{};
     a.volts = reinterpret_cast<const uint32_t*>(volts);
@@ -239,6 +242,21 @@ bf_status bf_beamform_fft(const bf_plan* plan, const uint8_t* volts, int64_t n_t
   }
   if (e != hipSuccess) return dev_fail(e, "beamform_fft: launch");
   return BF_OK;
+}
+
+extern "C" {
+
+bf_status bf_beamform_fft(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper, int32_t kind,
+                          void* out, void* stream) {
+  return beamform_fft_impl(plan, volts, n_time, taper, 1, kind, out, stream);
+}
+
+bf_status bf_beamform_fft_gains(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* gains,
+                                int32_t kind, void* out, void* stream) {
+  if (!gains) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft_gains: NULL gains");
+  if (plan && plan->d.precision != BF_PREC_FP32)
+    return fail(BF_ERR_UNSUPPORTED, "beamform_fft_gains: complex gains need an FP32 plan");
+  return beamform_fft_impl(plan, volts, n_time, gains, 2, kind, out, stream);
 }
 
 static bf_status tied_common(const bf_plan* plan, int64_t n_time, int32_t chan_lo, int32_t n_chan_sub,

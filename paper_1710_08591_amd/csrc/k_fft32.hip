@@ -70,7 +70,10 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
   return (float)(int)__builtin_amdgcn_sbfe((int)d, shift, 4);
 }
 
-template <int N, int G, bool TAPER, bool CPLX>
+// TAPER: 0 none (E-W DFT as signed 4-bit dot products), 1 real per-antenna
+// weights h_a, 2 complex per-antenna gains g_a (float2), applied before the
+// E-W DFT.
+template <int N, int G, int TAPER, bool CPLX>
 __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
   constexpr int F = 64 / (4 * G);      // frames handled side by side
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   static_assert(F * 4 * M * 4 <= F * 4 * G * YS * 8, "block-end sums must fit the LDS");
 
   __shared__ cf lds_y[F * 4 * G * YS];
-  __shared__ float lds_h[TAPER ? N * 4 : 1];
+  __shared__ float lds_h[TAPER == 2 ? N * 8 : TAPER ? N * 4 : 1];
 
   const int lane = threadIdx.x;
   const int f1 = lane / (4 * G), e1 = (lane / G) & 3, a1 = lane % G;
@@ -92,8 +95,8 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   const int chan = wg % p.n_chan;
   const int blk = wg / p.n_chan;
 
-  if constexpr (TAPER) {
-    for (int i = lane; i < N * 4; i += 64) lds_h[i] = p.taper[i];
+  if constexpr (TAPER != 0) {
+    for (int i = lane; i < N * 4 * TAPER; i += 64) lds_h[i] = p.taper[i];
     __syncthreads();
   }
 
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 
   int wre = 0, wim = 0;
   TaperLane tl{};
-  if constexpr (TAPER) tl = taper_lane(e1); else ew_weights(e1, wre, wim);
+  if constexpr (TAPER != 0) tl = taper_lane(e1); else ew_weights(e1, wre, wim);
 
   float acc[R2][G];
 #pragma unroll
@@ -146,7 +149,22 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 #pragma unroll
       for (int j = 0; j < L; ++j) {
         const uint32_t d = cur[j];
-        if constexpr (TAPER) {
+        if constexpr (TAPER == 2) {
+          // z_q = g_q x_q, then the E-W twiddle (-i)^{e q} as a swap and signs
+          const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
+          const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
+          const float gr[4] = {g01.x, g01.z, g23.x, g23.z}, gi[4] = {g01.y, g01.w, g23.y, g23.w};
+          float re = 0.f, im = 0.f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
+            const float zr = fmaf(xr, gr[q], -(xi * gi[q]));
+            const float zi = fmaf(xr, gi[q], xi * gr[q]);
+            re = fmaf(tl.sre[q], tl.swap[q] ? zi : zr, re);
+            im = fmaf(tl.sim[q], tl.swap[q] ? zr : zi, im);
+          }
+          x[j] = cf{re, im};
+        } else if constexpr (TAPER == 1) {
           const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 4]);
           const float hq[4] = {h.x, h.y, h.z, h.w};
           float re = 0.f, im = 0.f;
@@ -231,16 +249,18 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   }
 }
 
+template <int N, int G, int T>
+void launch_nt(const Fft32Args& a, bool cplx, dim3 grid, hipStream_t s) {
+  if (cplx) hipLaunchKernelGGL((k_fft32<N, G, T, true>), grid, dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_fft32<N, G, T, false>), grid, dim3(64), 0, s, a);
+}
+
 template <int N, int G>
-hipError_t launch_n(const Fft32Args& a, bool taper, bool cplx, int64_t n_wg, hipStream_t s) {
-  dim3 grid((unsigned)n_wg), blockd(64);
-  if (taper) {
-    if (cplx) hipLaunchKernelGGL((k_fft32<N, G, true, true>), grid, blockd, 0, s, a);
-    else hipLaunchKernelGGL((k_fft32<N, G, true, false>), grid, blockd, 0, s, a);
-  } else {
-    if (cplx) hipLaunchKernelGGL((k_fft32<N, G, false, true>), grid, blockd, 0, s, a);
-    else hipLaunchKernelGGL((k_fft32<N, G, false, false>), grid, blockd, 0, s, a);
-  }
+hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, int64_t n_wg, hipStream_t s) {
+  const dim3 grid((unsigned)n_wg);
+  if (taper == 2) launch_nt<N, G, 2>(a, cplx, grid, s);
+  else if (taper == 1) launch_nt<N, G, 1>(a, cplx, grid, s);
+  else launch_nt<N, G, 0>(a, cplx, grid, s);
   return hipGetLastError();
 }
 
@@ -268,7 +288,7 @@ int fft32_group(int n_ns) {
   }
 }
 
-hipError_t launch_fft32(const Fft32Args& a, int n_ns, bool taper, bool cplx, int64_t n_wg,
+hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s) {
   switch (n_ns) {
     case 16: return launch_n<16, 4>(a, taper, cplx, n_wg, s);

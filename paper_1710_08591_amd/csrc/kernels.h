@@ -15,7 +15,7 @@ struct Fft32Args {
   int pol_iter;            // polarisations folded into one workgroup (1 or n_pol)
   int block;               // samples per intensity block (chunk for complex output)
   const float2* tw;        // [G][2L] W_M^{a1 k2}
-  const float* taper;      // [n_ns][4] or null
+  const float* taper;      // [n_ns][4] real weights, [n_ns][4][2] complex gains, or null
   const int32_t* sel;      // [n_chan][n_keep] or null (identity)
   int n_keep;
   void* out;
@@ -24,7 +24,8 @@ struct Fft32Args {
 
 int fft32_frames_per_pass(int n_ns);
 int fft32_group(int n_ns);
-hipError_t launch_fft32(const Fft32Args& a, int n_ns, bool taper, bool cplx, int64_t n_wg,
+// taper: 0 none, 1 real weights, 2 complex gains
+hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s);
 
 // FP64 table generation on the device
