@@ -132,6 +132,23 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float) -> dict:
         ref = orc.beamform_fft(vs, w.m_ew, w.m_ns, 16)[0, 0, 0][:, sel[c]]
         err = max(err, float(np.max(np.abs(out[blk, c, p].cpu().numpy() - ref) / ref)))
     alg = w.n_time * w.n_chan * w.n_pol * w.frame_bytes + out.numel() * 4
+    # complex per-antenna gains (bf_beamform_fft_gains) on the same voltages, FP32 plan
+    plan32 = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=w.m_ew, m_ns=w.m_ns, n_pol=w.n_pol, n_chan=w.n_chan,
+                     block=w.block, ns_select=w.ns_select(), d_over_lambda=w.d_over_lambda())
+    grng = np.random.default_rng(17)
+    gains = np.exp(0.1 * grng.normal(size=(w.n_ns, w.n_ew)) + 0.1j * grng.normal(size=(w.n_ns, w.n_ew)))
+    g_dev = torch.from_numpy(gains.astype(np.complex64)).to(dev)
+    g_ms = _time_launches(lambda: bf.beamform_fft(plan32, volts, out=out, gains=g_dev), 5)
+    g_err = 0.0
+    for _ in range(2):
+        blk, c, p = int(rng.integers(1024)), int(rng.integers(256)), int(rng.integers(2))
+        vs = sg.volts(w, blk * 16, 16, chans=[c], pols=[p])
+        ref = orc.beamform_fft(vs, w.m_ew, w.m_ns, 16, taper=gains.astype(np.complex64).astype(np.complex128))
+        g_err = max(g_err, float(np.max(np.abs(out[blk, c, p].cpu().numpy() - ref[0, 0, 0][:, sel[c]])
+                                        / ref[0, 0, 0][:, sel[c]])))
+    plan32.close()
+    gains_rec = {"kernel_ms": g_ms, "antenna_samples_per_s": w.antenna_samples / (g_ms / 1e3),
+                 "slowdown_vs_no_gains": g_ms / fp32_ms, "max_rel_power_err_sampled": g_err}
     # MFMA work issued per sample frame: 4 E-W beams x (stage 1: 2 terms x [64 x 32] over 16 a1
     # + stage 2: 3 products of [32 x 32] over 32 k2), 2 flop per multiply-add
     frames = w.n_time * w.n_chan * w.n_pol
@@ -144,7 +161,8 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float) -> dict:
             "hbm_alg_gbs": alg / (ms / 1e3) / 1e9, "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "mfma_tflops": mfma_flops / (ms / 1e3) / 1e12,
             "mfma_frac_of_fp16_peak": mfma_flops / (ms / 1e3) / 1e12 / FP16_MFMA_PEAK_TFLOPS,
-            "max_rel_power_err_sampled": err}
+            "max_rel_power_err_sampled": err,
+            "fp32_with_complex_gains": gains_rec}
 
 
 def run_chime_regrid(dev, w, volts, n_target: int = 256) -> dict:

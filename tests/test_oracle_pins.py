@@ -488,6 +488,32 @@ def test_phase_ramp_gains_steer_the_beams():
         assert abs(b.max() - _gain_beams(None, eta, 4, m)[0].max()) < 1e-9
 
 
+def test_inverse_receiver_temperature_weighting_is_optimal():
+    """Sec. "Noise correlated between antennas": with feed-dependent receiver
+    noise T_a (uncorrelated, noise-dominated), weighting the voltages by 1/T_a
+    before FFT beamforming gives the highest point-source SNR of any
+    per-antenna weighting.  Measured through the oracle's beams: signal = the
+    on-grid source's beam power, noise = the mean beam power of unit-modulus
+    noise scaled by sqrt(T_a) (exact by Parseval)."""
+    rng = np.random.default_rng(21)
+    n_ns, n_ew = 16, 4
+    t_r = rng.uniform(0.5, 2.0, (n_ns, n_ew))
+    a_ns, a_ew = np.arange(n_ns)[:, None], np.arange(n_ew)[None, :]
+    eta_s = np.exp(2j * np.pi * (a_ew * 3 / 4 + a_ns * 9 / 32))[None]
+    eta_n = np.exp(2j * np.pi * rng.random((8, n_ns, n_ew))) * np.sqrt(t_r)
+
+    def snr(h):
+        sig = _gain_beams(h, eta_s, 4, 32)[0, 3, 9]
+        return sig / _gain_beams(h, eta_n, 4, 32).mean()
+
+    best = snr(1.0 / t_r)
+    assert best > snr(np.ones((n_ns, n_ew))) * 1.01
+    for _ in range(20):
+        assert snr((1.0 / t_r) * (1 + 0.2 * rng.normal(size=(n_ns, n_ew)))) < best
+    # the optimum in closed form (Cauchy-Schwarz): n_ant * mean(1/T)
+    assert abs(best - 64 * np.mean(1.0 / t_r)) < 1e-9 * best
+
+
 def test_gain_variations_printed_example():
     """The printed example: 10% RMS amplitude variations raise point-source
     sensitivity by 1%, 0.1 rad RMS phase variations lower it by 1%; as
