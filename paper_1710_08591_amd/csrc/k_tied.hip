@@ -258,11 +258,15 @@ __device__ __forceinline__ float tied_block_mfma(const float* lds_b, const TiedB
 }
 
 // Voltage variant on the matrix cores: workgroup = 4 wavefronts = 64
-// pointings; wavefront 0 forms the FFT beams of 16 samples in LDS, then each
-// wavefront interpolates its 16 pointings.
+// pointings.  Samples go in quads of 16-sample groups: wavefront w forms the
+// FFT beams of group w of the quad in its own LDS buffer, then every
+// wavefront interpolates its 16 pointings over all four groups, so no
+// wavefront waits while another forms beams.
+constexpr int kV16Buf = kV16TS * 4 * kV16M * 2;     // floats per group buffer (16 KB)
+
 template <bool TAPER>
 __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
-  __shared__ float lds_b[kV16TS * 4 * kV16M * 2];
+  __shared__ float lds_b[4 * kV16Buf];
   __shared__ float lds_h[TAPER ? kV16N * 4 : 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n_ptile = (a.n_point + 63) / 64;
@@ -291,23 +295,36 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
   const int64_t t1 = t0 + span < a.n_time ? t0 + span : a.n_time;
   const int64_t frame_dw = (int64_t)a.n_chan * a.n_pol * kV16N;   // dwords per sample
 
-  for (int64_t tb = t0; tb < t1; tb += a.block) {
-    float acc = 0.f;
-    for (int tg = 0; tg < a.block; tg += kV16TS) {
-      for (int pol = pol_lo; pol < pol_hi; ++pol) {
-        if (wave == 0) {
-          const uint32_t* src = a.volts + (tb + tg + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * kV16N;
-          v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b);
-        }
-        __syncthreads();
-        if (wave_live) acc += tied_block_mfma(lds_b, w, lane);
-        __syncthreads();
+  float acc = 0.f;
+  for (int64_t tq = t0; tq < t1; tq += 4 * kV16TS) {
+    float accg[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int pol = pol_lo; pol < pol_hi; ++pol) {
+      const int64_t tw = tq + kV16TS * wave;
+      if (tw < t1) {
+        const uint32_t* src = a.volts + (tw + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * kV16N;
+        v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b + wave * kV16Buf);
       }
+      __syncthreads();
+      if (wave_live) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          if (tq + kV16TS * g < t1) accg[g] += tied_block_mfma(lds_b + g * kV16Buf, w, lane);
+      }
+      __syncthreads();
     }
-    if (live && lane < 16) {
-      const int64_t blk = tb / a.block;
-      float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
-      *o = acc;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t tg = tq + kV16TS * g;
+      if (tg >= t1) break;
+      acc += accg[g];
+      if ((tg + kV16TS) % a.block == 0) {
+        if (live && lane < 16) {
+          const int64_t blk = tg / a.block;
+          float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
+          *o = acc;
+        }
+        acc = 0.f;
+      }
     }
   }
 }
@@ -315,12 +332,13 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
 // Persistent tile worker of the tied-beam server: each workgroup takes tiles
 // (request, channel, 64 pointings, run of 16-sample blocks) from the batch,
 // reading voltages from the device ring (absolute sample s lives in slot
-// s mod ring_samples).  A tile's arithmetic is the same as k_tied_v16's and
-// does not depend on which other tiles share the launch.
+// s mod ring_samples).  A tile's arithmetic is the same as k_tied_v16's (the
+// same quads of 16-sample groups) and does not depend on which other tiles
+// share the launch.
 __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ tiles, int n_tiles,
                                                const uint32_t* __restrict__ ring, int64_t ring_samples,
                                                int n_chan, int n_pol, const double* __restrict__ dl) {
-  __shared__ float lds_b[kV16TS * 4 * kV16M * 2];
+  __shared__ float lds_b[4 * kV16Buf];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const V16Lane l = v16_lane(lane);
   const int64_t frame_dw = (int64_t)n_chan * n_pol * kV16N;
@@ -333,21 +351,29 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
     TiedB w;
     if (wave_live)
       tied_weights(dl[2 * t.chan] * t.dircos[2 * pp], dl[2 * t.chan + 1] * t.dircos[2 * pp + 1], lane >> 4, w);
-    for (int b = 0; b < t.n_blk; ++b) {
-      const int64_t s0 = t.t_start + (int64_t)(t.blk0 + b) * kV16TS;
-      for (int pol = 0; pol < n_pol; ++pol) {
-        if (wave == 0) {
+    for (int pol = 0; pol < n_pol; ++pol) {
+      for (int b0 = 0; b0 < t.n_blk; b0 += 4) {
+        if (b0 + wave < t.n_blk) {
+          const int64_t s0 = t.t_start + (int64_t)(t.blk0 + b0 + wave) * kV16TS;
           const int64_t slot = (s0 + l.ts) % ring_samples;
           const uint32_t* src = ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * kV16N;
-          v16_fft_to_lds<false>(src, l, nullptr, lds_b);
+          v16_fft_to_lds<false>(src, l, nullptr, lds_b + wave * kV16Buf);
         }
         __syncthreads();
-        float acc = 0.f;
-        if (wave_live) acc = tied_block_mfma(lds_b, w, lane);
+        float accg[4] = {0.f, 0.f, 0.f, 0.f};
+        if (wave_live) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+            if (b0 + g < t.n_blk) accg[g] = tied_block_mfma(lds_b + g * kV16Buf, w, lane);
+        }
         __syncthreads();
         if (live && lane < 16) {
-          const int64_t ob = t.blk0 + b;
-          t.out[((ob * t.n_chan_req + (t.chan - t.chan_lo)) * n_pol + pol) * (int64_t)t.n_point + p] = acc;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            if (b0 + g >= t.n_blk) break;
+            const int64_t ob = t.blk0 + b0 + g;
+            t.out[((ob * t.n_chan_req + (t.chan - t.chan_lo)) * n_pol + pol) * (int64_t)t.n_point + p] = accg[g];
+          }
         }
       }
     }
