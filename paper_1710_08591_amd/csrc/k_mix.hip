@@ -22,13 +22,13 @@
 // sample), B column = l % 16 (one beam), both holding k in
 // [8 (l/16), 8 (l/16) + 8); C holds column l % 16, rows 4 (l/16) + i.
 #include "dev_common.h"
+#include "dev_f16.h"
 #include "kernels.h"
 
 namespace fftbf {
 
 namespace {
 
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPrecFp16 = 1;
@@ -294,19 +294,6 @@ __global__ void k_mix256_tables(void* tab) {
     float2* w = reinterpret_cast<float2*>(static_cast<char*>(tab) + kMix256TwOff);
     w[i] = make_float2((float)cs, (float)sn);
   }
-}
-
-// Two floats into FP16 high and low terms: hi = fp16(v) (round to nearest
-// even), lo = fp16(v - hi); the residual v - hi is exact in FP32 and comes
-// from one mixed-precision fused multiply-add per value.
-__device__ __forceinline__ void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
-  uint32_t h;
-  float r0, r1;
-  asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(h) : "v"(v0), "v"(v1));
-  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r0) : "v"(h), "v"(v0));
-  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r1) : "v"(h), "v"(v1));
-  asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(lo) : "v"(r0), "v"(r1));
-  hi = h;
 }
 
 __device__ __forceinline__ __attribute__((unused)) half8 pack8(const float* v) {

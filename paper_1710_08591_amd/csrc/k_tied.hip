@@ -16,6 +16,7 @@
 // FFT beam at the same time, so beam reads are wave-uniform (scalar loads
 // from the complex-beam array, LDS broadcasts in the voltage variant).
 #include "dev_common.h"
+#include "dev_f16.h"
 #include "kernels.h"
 
 namespace fftbf {
@@ -148,13 +149,40 @@ __device__ __forceinline__ V16Lane v16_lane(int lane) {
   return l;
 }
 
+// The interpolation of a group of 16 samples runs on the FP16 matrix cores
+// (v_mfma_f32_16x16x32_f16) with two-term operands:
+//   Out[s][p] = sum_k A[s][k] W[k][p] ~ sum_k (A_hi W_hi + A_lo W_hi + A_hi W_lo),
+// A = hi + lo and W = hi + lo split in FP16, so each term carries ~22
+// significant bits and only the lo x lo product (~2^-22 relative) is
+// dropped; products are exact and accumulate in FP32.  k = 2 beam + (re|im)
+// over the 128 FFT beams (beam = 32 e + A_ns); the Re and Im parts of Out
+// are two products with the same A operand:
+//   W_re[2b][p] = Re c_b, W_re[2b+1][p] = -Im c_b,  W_im[2b][p] = Im c_b,
+//   W_im[2b+1][p] = Re c_b.
+// The FFT beams are scaled by 2^ds and the weights by 2^10 before the split
+// (powers of two, exact), so that the low terms stay in FP16's normal range;
+// the block sum of |Out|^2 is scaled back by 2^-2(ds+10).
+//
+// LDS operand layout of one group (FP16, 16 KB): [hi|lo][kb 8][g 4][s 16][j 8]
+// with k = 32 kb + 8 g + j, so lane (s, g) of the A operand reads its eight
+// values of k-block kb as one 16-byte load.
+constexpr int kV16Wscale = 10;
+
+// |FFT beam| <= (1/8) * 64 antennas * |h|max * 8 sqrt(2) on the 4 x 16 lattice;
+// the largest power of two keeping the scaled beams below 2^15.
+__device__ __forceinline__ int v16_data_scale(float hmax) {
+  if (!(hmax > 0.f)) return 8;
+  int e;
+  frexpf(32768.f / (90.51f * hmax), &e);
+  return e - 1;
+}
+
 // FFT beams of the 16 samples whose frames the lanes point at (lane = sample
-// l.ts, E-W beam l.e) into LDS as floats, sample fastest:
-//   lds_b[((beam * 2) + comp) * 16 + sample],  beam = e * 32 + A_ns,
-// normalised by 1/sqrt(64).
+// l.ts, E-W beam l.e), normalised by 1/sqrt(64), scaled by 2^ds and split
+// into the FP16 operand layout above.
 template <bool TAPER>
 __device__ __forceinline__ void v16_fft_to_lds(const uint32_t* __restrict__ src, const V16Lane& l,
-                                               const float* lds_h, float* lds_b) {
+                                               const float* lds_h, _Float16* lds_g, int ds) {
   constexpr int N = kV16N, MNS = kV16M;
   cf x[N];
 #pragma unroll
@@ -181,12 +209,15 @@ __device__ __forceinline__ void v16_fft_to_lds(const uint32_t* __restrict__ src,
   }
   cf y[MNS];
   padded_dft<N>(x, y);
-  const float nrm = 0.125f;   // 1/sqrt(4 * 16)
-  float* col = lds_b + (l.e * MNS * 2) * 16 + l.ts;
+  const float nrm = ldexpf(0.125f, ds);   // 2^ds / sqrt(4 * 16)
 #pragma unroll
-  for (int k = 0; k < MNS; ++k) {
-    col[(2 * k) * 16] = y[k].r * nrm;
-    col[(2 * k + 1) * 16] = y[k].i * nrm;
+  for (int c = 0; c < MNS / 4; ++c) {     // four beams A = 4c .. 4c+3 per 16-byte vector
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) split2(y[4 * c + q].r * nrm, y[4 * c + q].i * nrm, hw[q], lw[q]);
+    const int kb = 2 * l.e + c / 4, g = c % 4;
+    *reinterpret_cast<half8*>(lds_g + (((0 * 8 + kb) * 4 + g) * 16 + l.ts) * 8) = __builtin_bit_cast(half8, hw);
+    *reinterpret_cast<half8*>(lds_g + (((1 * 8 + kb) * 4 + g) * 16 + l.ts) * 8) = __builtin_bit_cast(half8, lw);
   }
 }
 
@@ -208,46 +239,56 @@ __device__ __forceinline__ void interp_weight_d(int A, int m, int n, double y, d
   *wi_out = ai / m;
 }
 
-// Matrix-core interpolation of one pointing tile.  The complex product
-//   Out[s][p] = sum_beam B[s][beam] C[p][beam],   C = c_ew[e] c_ns[A_ns]
-// runs as real 16 x 16 x 4 FP32 MFMAs: rows = 16 samples, columns = 16
-// pointings (one per lane column), k = (beam, re|im) with beam = 2 kstep +
-// (l/16 >> 1) and re|im = (l/16) & 1; one product gives Re(Out), the other
-// Im(Out) from the same A operand.  The weight operands (64 + 64 floats per
-// lane) are generated once per tile in FP64 and stay in registers.
-struct TiedB {
-  float re[64], im[64];
+// B operands of one pointing (lane column p = l % 16, k rows 8 g .. 8 g + 7 of
+// every k-block, g = l / 16): Re and Im parts, high and low FP16 terms.
+struct TiedW {
+  half8 rh[8], rl[8], ih[8], il[8];
 };
 
-__device__ __forceinline__ void tied_weights(double y_ew, double y_ns, int g, TiedB& w) {
-  const int par = g >> 1, comp = g & 1;
+__device__ __forceinline__ void tied_weights(double y_ew, double y_ns, int g, TiedW& w) {
   double ewr[4], ewi[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) interp_weight_d(e, 4, 4, y_ew, &ewr[e], &ewi[e]);
+  // this lane's k rows hold beams 16 kb + 4 g + jj (jj < 4): N-S beams 16 h + 4 g + jj
+  double nsr[2][4], nsi[2][4];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    double nr, ni;
-    interp_weight_d(2 * j + par, kV16M, kV16N, y_ns, &nr, &ni);
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double cr = ewr[e] * nr - ewi[e] * ni, ci = ewr[e] * ni + ewi[e] * nr;
-      const int ks = e * 16 + j;               // beam e*32 + 2j + par = 2 ks + par
-      w.re[ks] = comp == 0 ? (float)cr : (float)(-ci);
-      w.im[ks] = comp == 0 ? (float)ci : (float)cr;
+    for (int jj = 0; jj < 4; ++jj) interp_weight_d(16 * h + 4 * g + jj, kV16M, kV16N, y_ns, &nsr[h][jj], &nsi[h][jj]);
+  const double sc = (double)(1 << kV16Wscale);
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    const int e = kb >> 1, h = kb & 1;
+    uint32_t rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const double cr = (ewr[e] * nsr[h][jj] - ewi[e] * nsi[h][jj]) * sc;
+      const double ci = (ewr[e] * nsi[h][jj] + ewi[e] * nsr[h][jj]) * sc;
+      split2((float)cr, (float)(-ci), rh[jj], rl[jj]);     // W_re rows 2b, 2b+1
+      split2((float)ci, (float)cr, ih[jj], il[jj]);        // W_im rows 2b, 2b+1
     }
+    w.rh[kb] = __builtin_bit_cast(half8, rh);
+    w.rl[kb] = __builtin_bit_cast(half8, rl);
+    w.ih[kb] = __builtin_bit_cast(half8, ih);
+    w.il[kb] = __builtin_bit_cast(half8, il);
   }
 }
 
-// sum over the block's 16 samples of |Out|^2 for this lane's pointing (valid
-// in lanes with l / 16 == 0 after the call)
-__device__ __forceinline__ float tied_block_mfma(const float* lds_b, const TiedB& w, int lane) {
-  const int s = lane & 15, g = lane >> 4, par = g >> 1, comp = g & 1;
+// sum over the group's 16 samples of |Out|^2 for this lane's pointing,
+// scaled by 2^2(ds+10) (the same value in every lane of a column)
+__device__ __forceinline__ float tied_block_mfma(const _Float16* lds_g, const TiedW& w, int lane) {
+  const int s = lane & 15, g = lane >> 4;
   f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int ks = 0; ks < 64; ++ks) {
-    const float a = lds_b[((2 * ks + par) * 2 + comp) * 16 + s];
-    cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w.re[ks], cre, 0, 0, 0);
-    cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a, w.im[ks], cim, 0, 0, 0);
+  for (int kb = 0; kb < 8; ++kb) {
+    const half8 ah = *reinterpret_cast<const half8*>(lds_g + (((0 * 8 + kb) * 4 + g) * 16 + s) * 8);
+    const half8 al = *reinterpret_cast<const half8*>(lds_g + (((1 * 8 + kb) * 4 + g) * 16 + s) * 8);
+    cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.rh[kb], cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.ih[kb], cim, 0, 0, 0);
+    cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, w.rh[kb], cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, w.ih[kb], cim, 0, 0, 0);
+    cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.rl[kb], cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.il[kb], cim, 0, 0, 0);
   }
   float v = 0.f;
 #pragma unroll
@@ -262,11 +303,11 @@ __device__ __forceinline__ float tied_block_mfma(const float* lds_b, const TiedB
 // FFT beams of group w of the quad in its own LDS buffer, then every
 // wavefront interpolates its 16 pointings over all four groups, so no
 // wavefront waits while another forms beams.
-constexpr int kV16Buf = kV16TS * 4 * kV16M * 2;     // floats per group buffer (16 KB)
+constexpr int kV16Buf = 2 * 8 * 4 * 16 * 8;          // FP16 values per group buffer (16 KB)
 
 template <bool TAPER>
 __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
-  __shared__ float lds_b[4 * kV16Buf];
+  __shared__ __attribute__((aligned(16))) _Float16 lds_b[4 * kV16Buf];
   __shared__ float lds_h[TAPER ? kV16N * 4 : 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n_ptile = (a.n_point + 63) / 64;
@@ -284,10 +325,17 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
   if constexpr (TAPER) {
     for (int i = tid; i < kV16N * 4; i += 256) lds_h[i] = a.taper[i];
   }
-  TiedB w;
+  TiedW w;
   if (wave_live) tied_weights(a.dl[2 * chan] * a.dircos[2 * pp], a.dl[2 * chan + 1] * a.dircos[2 * pp + 1], lane >> 4, w);
   const V16Lane l = v16_lane(lane);
   __syncthreads();
+  int ds = 8;
+  if constexpr (TAPER) {
+    float hmax = 0.f;
+    for (int i = 0; i < kV16N * 4; ++i) hmax = fmaxf(hmax, fabsf(lds_h[i]));
+    ds = v16_data_scale(hmax);
+  }
+  const float out_scale = ldexpf(1.f, -2 * (ds + kV16Wscale));
 
   const int pol_lo = a.pol_sum ? 0 : pg, pol_hi = a.pol_sum ? a.n_pol : pg + 1;
   const int64_t span = (int64_t)a.block * kTiedBlocksPerWg;
@@ -302,13 +350,13 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
       const int64_t tw = tq + kV16TS * wave;
       if (tw < t1) {
         const uint32_t* src = a.volts + (tw + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * kV16N;
-        v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b + wave * kV16Buf);
+        v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b + wave * kV16Buf, ds);
       }
       __syncthreads();
       if (wave_live) {
 #pragma unroll
         for (int g = 0; g < 4; ++g)
-          if (tq + kV16TS * g < t1) accg[g] += tied_block_mfma(lds_b + g * kV16Buf, w, lane);
+          if (tq + kV16TS * g < t1) accg[g] += tied_block_mfma(lds_b + g * kV16Buf, w, lane) * out_scale;
       }
       __syncthreads();
     }
@@ -338,9 +386,10 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
 __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ tiles, int n_tiles,
                                                const uint32_t* __restrict__ ring, int64_t ring_samples,
                                                int n_chan, int n_pol, const double* __restrict__ dl) {
-  __shared__ float lds_b[4 * kV16Buf];
+  __shared__ __attribute__((aligned(16))) _Float16 lds_b[4 * kV16Buf];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const V16Lane l = v16_lane(lane);
+  const float out_scale = ldexpf(1.f, -2 * (8 + kV16Wscale));
   const int64_t frame_dw = (int64_t)n_chan * n_pol * kV16N;
   for (int ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const ServeTile t = tiles[ti];
@@ -348,7 +397,7 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
     const bool live = p < t.n_point;
     const bool wave_live = t.ptile * 64 + wave * 16 < t.n_point;
     const int pp = live ? p : t.n_point - 1;
-    TiedB w;
+    TiedW w;
     if (wave_live)
       tied_weights(dl[2 * t.chan] * t.dircos[2 * pp], dl[2 * t.chan + 1] * t.dircos[2 * pp + 1], lane >> 4, w);
     for (int pol = 0; pol < n_pol; ++pol) {
@@ -357,14 +406,14 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
           const int64_t s0 = t.t_start + (int64_t)(t.blk0 + b0 + wave) * kV16TS;
           const int64_t slot = (s0 + l.ts) % ring_samples;
           const uint32_t* src = ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * kV16N;
-          v16_fft_to_lds<false>(src, l, nullptr, lds_b + wave * kV16Buf);
+          v16_fft_to_lds<false>(src, l, nullptr, lds_b + wave * kV16Buf, 8);
         }
         __syncthreads();
         float accg[4] = {0.f, 0.f, 0.f, 0.f};
         if (wave_live) {
 #pragma unroll
           for (int g = 0; g < 4; ++g)
-            if (b0 + g < t.n_blk) accg[g] = tied_block_mfma(lds_b + g * kV16Buf, w, lane);
+            if (b0 + g < t.n_blk) accg[g] = tied_block_mfma(lds_b + g * kV16Buf, w, lane) * out_scale;
         }
         __syncthreads();
         if (live && lane < 16) {

@@ -71,6 +71,30 @@ def test_c3_tied_beams_from_voltages(taper):
     plan.close()
 
 
+@pytest.mark.parametrize("scale", [3.5, 1e-3, 40.0])
+def test_tied_from_voltages_window_scaling(scale):
+    """The matrix-core interpolation scales the FFT beams by a power of two
+    chosen from the window's largest weight (so its FP16 high and low terms
+    neither overflow nor fall below the normal range): windows far above and
+    below 1, extreme voltages, both polarisations summed."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=3, n_pol=2, n_time=160, seed=23, n_src=2, snr=30.0,
+                           dl=(0.4, 0.8))
+    v = sg.volts(w)
+    rng = np.random.default_rng(1)
+    v[:16] = rng.choice(np.array([0x88, 0x77, 0x78, 0x87], dtype=np.uint8), size=v[:16].shape)   # |re|, |im| >= 7
+    h = (sg.gaussian_taper(4, 16) * scale).astype(np.float32)
+    plan = plan_for(w, clamp=False, pol_sum=True)
+    dirs = np.concatenate([sg.pointings(40, 3), [[0.0, 0.0]]], axis=0)
+    got = bf.form_tied_beams_v(plan, torch.from_numpy(v).cuda(), 0, 3, torch.from_numpy(dirs).cuda(),
+                               taper=torch.from_numpy(h).cuda()).cpu().numpy()
+    ref = orc.tied_intensity(v, dirs, w.d_over_lambda(), 16, taper=h).sum(axis=2)
+    assert got.shape == ref.shape
+    assert rel_err(got, ref) < TOL_FP32
+    plan.close()
+
+
 def test_tied_on_grid_and_odd_counts():
     """On-grid pointings reproduce the FFT beams; ragged pointing tiles; channel subsets."""
     torch = _torch()
