@@ -45,6 +45,7 @@ __all__ = [
     "window_autocorr", "optimal_window_norm", "optimal_window_lag_weights",
     "optimal_window_weights", "compact_taps", "regrid_intensity",
     "baseline_moi", "pointed_power_and_slope", "localize_row", "localize",
+    "regrid_intensity_2d",
 ]
 
 
@@ -430,6 +431,19 @@ def localize(intensity: np.ndarray, n: int, d_over_lambda_ns: np.ndarray, n_wind
     for idx in np.ndindex(*x.shape[:-1]):
         st[idx], pk[idx] = localize_row(x[idx], n, float(d_over_lambda_ns[chans[idx[1]]]), n_window, n_iter)
     return st, pk
+
+
+def regrid_intensity_2d(b: np.ndarray, y_ew: np.ndarray, y_ns: np.ndarray, n_ew: int, n_ns: int) -> np.ndarray:
+    """Pointed-beam intensities at 2-D pointings from FFT-beam intensities
+    b [..., M_ew, M_ns]: eq. e:bp_max_arbitrary on each axis (the lattice is
+    separable), b_p = sum_{A_ew, A_ns} w^{A_ew}(y_ew) w^{A_ns}(y_ns) b_A.
+    Exact when M >= 2n - 1 on both axes.  Returns [..., P]."""
+    m_ew, m_ns = b.shape[-2], b.shape[-1]
+    out = np.empty(b.shape[:-2] + (len(y_ew),))
+    for p in range(len(y_ew)):
+        w = np.outer(regrid_weights_paper(n_ew, m_ew, float(y_ew[p])), regrid_weights_paper(n_ns, m_ns, float(y_ns[p])))
+        out[..., p] = np.tensordot(np.asarray(b, dtype=np.float64), w, axes=([-2, -1], [0, 1]))
+    return out
 
 
 def interp_weights(n: int, m: int, y: np.ndarray) -> np.ndarray:

@@ -189,6 +189,30 @@ def test_paper_regridding_matches_phased_sum_intensity(m):
         assert np.allclose(got, ref, rtol=1e-10)
 
 
+def test_2d_regridding_exact_with_padded_ew_axis():
+    """eq. e:bp_max_arbitrary on both axes of the 4 x 16 lattice: with the E-W
+    axis padded to M_ew = 8 >= 2 n_ew - 1 (and M_ns = 32) the regridded
+    intensities equal the direct phased beams at arbitrary 2-D pointings;
+    with the unpadded M_ew = 4 they do not."""
+    rng = np.random.default_rng(31)
+    n_ns, n_ew = 16, 4
+    eta = rng.normal(size=(32, 1, 1, n_ns, n_ew)) + 1j * rng.normal(size=(32, 1, 1, n_ns, n_ew))
+    dl = np.array([[0.6, 0.7]])
+    dirs = rng.uniform(-1, 1, (25, 2))
+    # the phased beams, straight from eq. e:c_pointed
+    w_ew = orc.pointed_weights(n_ew, dl[0, 0] * dirs[:, 0])
+    w_ns = orc.pointed_weights(n_ns, dl[0, 1] * dirs[:, 1])
+    ref = (np.abs(np.einsum("pn,pe,tqcne->tqcp", w_ns, w_ew, eta)) ** 2).sum(axis=0)[0, 0]
+    for m_ew, exact in ((8, True), (4, False)):
+        b = (np.abs(orc.fft_beams(eta, m_ew, 32)) ** 2).sum(axis=0)[0, 0]          # [m_ew][32]
+        got = orc.regrid_intensity_2d(b, dl[0, 0] * dirs[:, 0], dl[0, 1] * dirs[:, 1], n_ew, n_ns)
+        err = np.max(np.abs(got - ref) / ref)
+        if exact:
+            assert err < 1e-12
+        else:
+            assert err > 1e-2
+
+
 def test_paper_regridding_fails_below_2n_minus_1():
     n, m = 16, 30
     w, v = _small_array(16, 1, n, nt=64)
