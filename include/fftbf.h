@@ -62,7 +62,11 @@ typedef enum {
 typedef struct bf_plan bf_plan;
 
 /*
- * Plan geometry.  Supported: n_ew = m_ew = 4 (unpadded E-W axis);
+ * Plan geometry.  Supported: n_ew = 4 with m_ew = 4 (unpadded E-W axis)
+ * or, for FP32 plans, m_ew = 8 (E-W zero-padded to M_ew >= 2 n_ew - 1, so
+ * that intensity regridding is exact on both axes; the odd E-W beams are
+ * the 4-point DFT of x_a W_8^{a_ew}, formed by a second pass over the
+ * voltages; tied beams and the server need m_ew = 4);
  * n_ns a power of two in [16, 256] with m_ns = 2 n_ns (zero padding by two,
  * the smallest power of two with M >= 2n - 1, eq. e:b2n-1); block a
  * multiple of 16 (mixed precision) or of 4 (FP32); 1 <= n_pol <= 2.
@@ -217,6 +221,18 @@ typedef struct bf_regrid bf_regrid;
  * BF_ERR_OUT_OF_MEMORY / BF_ERR_DEVICE. */
 bf_status bf_regrid_create(const bf_plan *plan, const double *sin_theta, int32_t n_target,
                            const double *window, int32_t n_taps, bf_regrid **rg);
+/* 2-D pointings: each pointing (direction cosines ew, ns) is regridded along
+ * N-S as above and then along E-W with the same pointed kernel of eq.
+ * e:bp_max_arbitrary, w^{A_ew} = (1/M_ew) sin((2n_ew-1) pi y)/sin(pi y),
+ * y = (d/lambda)_ew dircos_ew - A_ew/M_ew; exact for a plan with m_ew = 8
+ * (>= 2 n_ew - 1) and m_ns = 2 n_ns.  The result is the intensity of the
+ * pointed beam at each pointing in every channel.
+ *   dircos  host double [n_point][2] (ew, ns), copied; n_point in [1, 65536].
+ * Errors as bf_regrid_create; BF_ERR_UNSUPPORTED unless m_ew >= 2 n_ew - 1.
+ * bf_regrid_intensity then writes out: device float
+ * [n_blk][n_chan][n_pol][n_point] ([n_blk][n_chan][n_point] when the plan sums
+ * polarisations). */
+bf_status bf_regrid_create_2d(const bf_plan *plan, const double *dircos, int32_t n_point, bf_regrid **rg);
 bf_status bf_regrid_destroy(bf_regrid *rg);
 /* fft_intensity: device float [n_blk][n_chan][n_pol][m_ew][m_ns] as written by
  * bf_beamform_fft with the plan ([n_blk][n_chan][m_ew][m_ns] when it sums

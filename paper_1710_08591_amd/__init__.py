@@ -20,7 +20,7 @@ from ._lib import (bf_server_stats, BF_OK, BF_ERR_INVALID_ARGUMENT, BF_ERR_UNSUP
 
 __all__ = [
     "Plan", "plan_create", "plan_destroy", "beamform_fft", "form_tied_beams", "form_tied_beams_v",
-    "accumulate_intensity", "Regrid", "localize", "Server", "lib", "BFError", "LibraryMissing",
+    "accumulate_intensity", "Regrid", "Regrid2D", "localize", "Server", "lib", "BFError", "LibraryMissing",
     "BF_PREC_FP32", "BF_PREC_FP16_MFMA", "BF_PREC_FP8_MFMA", "BF_OUT_INTENSITY", "BF_OUT_COMPLEX",
 ]
 
@@ -309,6 +309,41 @@ class Regrid:
         if tuple(fft_intensity.shape[1:]) != self.plan_shape:
             raise ValueError(f"fft_intensity must be [n_blk]{list(self.plan_shape)}")
         shape = (n_blk,) + self.plan_shape[:-1] + (self.n_target,)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=fft_intensity.device)
+        else:
+            _need(out, torch.float32, "out")
+            if tuple(out.shape) != shape:
+                raise ValueError(f"out shape {tuple(out.shape)} != {shape}")
+        check(lib().bf_regrid_intensity(self.handle, _ptr(fft_intensity), n_blk, _ptr(out),
+                                        _stream_handle(stream)), "bf_regrid_intensity")
+        return out
+
+
+class Regrid2D(Regrid):
+    """Pointed beams at 2-D pointings from FFT-beam intensities of a plan with
+    an E-W axis padded to 8 beams (bf_regrid_create_2d)."""
+
+    def __init__(self, plan: Plan, dircos: np.ndarray):
+        d = np.ascontiguousarray(dircos, dtype=np.float64)
+        if d.ndim != 2 or d.shape[1] != 2:
+            raise ValueError("dircos must be [n_point][2]")
+        h = C.c_void_p()
+        check(lib().bf_regrid_create_2d(plan.handle, d.ctypes.data_as(C.c_void_p), d.shape[0], C.byref(h)),
+              "bf_regrid_create_2d")
+        self.handle = h
+        self.n_target = d.shape[0]
+        self.plan_shape = ((plan.n_chan, plan.m_ew, plan.m_ns) if plan.pol_sum
+                           else (plan.n_chan, plan.n_pol, plan.m_ew, plan.m_ns))
+
+    def __call__(self, fft_intensity, out=None, stream=None):
+        """Regrid [n_blk][n_chan]([n_pol])[8][m_ns] intensities to [n_blk][n_chan]([n_pol])[n_point]."""
+        torch = _torch()
+        _need(fft_intensity, torch.float32, "fft_intensity")
+        n_blk = fft_intensity.shape[0]
+        if tuple(fft_intensity.shape[1:]) != self.plan_shape:
+            raise ValueError(f"fft_intensity must be [n_blk]{list(self.plan_shape)}")
+        shape = (n_blk,) + self.plan_shape[:-2] + (self.n_target,)
         if out is None:
             out = torch.empty(shape, dtype=torch.float32, device=fft_intensity.device)
         else:

@@ -62,6 +62,7 @@ _SIGS = {
                                          _P, _P]),
     "bf_accumulate_intensity": (C.c_int32, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P, _P]),
     "bf_regrid_create": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, C.POINTER(_P)]),
+    "bf_regrid_create_2d": (C.c_int32, [_P, _P, C.c_int32, C.POINTER(_P)]),
     "bf_regrid_destroy": (C.c_int32, [_P]),
     "bf_localize": (C.c_int32, [_P, _P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P]),
     "bf_regrid_intensity": (C.c_int32, [_P, _P, C.c_int64, _P, _P]),

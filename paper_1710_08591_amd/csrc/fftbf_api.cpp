@@ -90,8 +90,10 @@ bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
     return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: sizes must be positive");
   if (d.m_ew < d.n_ew || d.m_ns < d.n_ns)
     return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: transform shorter than the array");
-  if (d.n_ew != 4 || d.m_ew != 4)
-    return fail(BF_ERR_UNSUPPORTED, "plan_create: only n_ew = m_ew = 4 is supported");
+  if (d.n_ew != 4 || (d.m_ew != 4 && d.m_ew != 8))
+    return fail(BF_ERR_UNSUPPORTED, "plan_create: n_ew = 4 with m_ew = 4 or 8 is supported");
+  if (d.m_ew == 8 && d.precision != BF_PREC_FP32)
+    return fail(BF_ERR_UNSUPPORTED, "plan_create: the padded E-W axis (m_ew = 8) needs an FP32 plan");
   if (!is_pow2(d.n_ns) || d.n_ns < 16 || d.n_ns > 256 || d.m_ns != 2 * d.n_ns)
     return fail(BF_ERR_UNSUPPORTED,
                 "plan_create: n_ns must be a power of two in [16, 256] with m_ns = 2 n_ns");
@@ -222,7 +224,19 @@ static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, in
     a.out = out;
     const float inv_n = 1.0f / float(d.n_ew * d.n_ns);
     a.norm = (kind == BF_OUT_COMPLEX) ? 1.0f / std::sqrt(float(d.n_ew * d.n_ns)) : inv_n;
+    a.ew_rows = d.m_ew;
+    a.ew_mul = d.m_ew / 4;
+    a.ew_off = 0;
+    a.gain_src = taper ? taper_kind : 0;
+    a.twist = 0;
     e = fftbf::launch_fft32(a, d.n_ns, taper ? taper_kind : 0, kind == BF_OUT_COMPLEX, n_wg, s);
+    if (e == hipSuccess && d.m_ew == 8) {
+      // odd E-W beams of the zero-padded 8-point E-W transform: the 4-point
+      // DFT of x_a W_8^{a_ew} (with the window or gains, if any)
+      a.ew_off = 1;
+      a.twist = 1;
+      e = fftbf::launch_fft32(a, d.n_ns, 2, kind == BF_OUT_COMPLEX, n_wg, s);
+    }
   } else {
     fftbf::MixArgs a{};
     a.volts = reinterpret_cast<const uint32_t*>(volts);
@@ -291,8 +305,8 @@ bf_status bf_form_tied_beams(const bf_plan* plan, const void* fft_beams, int64_t
     return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: n_time not a multiple of block");
   if (kind == BF_OUT_COMPLEX && d.pol_sum)
     return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: complex output cannot sum polarisations");
-  if (d.m_ns != 32 && d.m_ns != 64)
-    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams: m_ns must be 32 or 64");
+  if ((d.m_ns != 32 && d.m_ns != 64) || d.m_ew != 4)
+    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams: m_ns must be 32 or 64 and m_ew 4");
   fftbf::TiedArgs a{};
   a.beams = static_cast<const float2*>(fft_beams);
   a.n_time = n_time;
@@ -326,8 +340,8 @@ bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_
   if (!volts || !aligned(volts, 4)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v: NULL or misaligned volts");
   if (taper && !aligned(taper, 16)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v: taper misaligned");
   if (n_time % d.block) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v: n_time not a multiple of block");
-  if (d.n_ns != 16 || d.block % 16)
-    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams_v: needs the 4 x 16 lattice and block a multiple of 16");
+  if (d.n_ns != 16 || d.m_ew != 4 || d.block % 16)
+    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams_v: needs the 4 x 16 lattice (m_ew 4) and block a multiple of 16");
   fftbf::TiedArgs a{};
   a.volts = reinterpret_cast<const uint32_t*>(volts);
   a.taper = taper;
@@ -359,6 +373,7 @@ struct bf_regrid {
   float* w = nullptr;       // dense weights [n_chan][pad][m_ns]
   int* first = nullptr;     // compact kernels [n_chan][n_target]
   float* tw = nullptr;      //                 [n_chan][n_taps][n_target]
+  float* wew = nullptr;     // 2-D pointings: E-W weights [n_chan][pad][8]
 };
 
 namespace {
@@ -386,6 +401,7 @@ void regrid_free(bf_regrid* r) {
   if (r->w) (void)hipFree(r->w);
   if (r->first) (void)hipFree(r->first);
   if (r->tw) (void)hipFree(r->tw);
+  if (r->wew) (void)hipFree(r->wew);
   delete r;
 }
 
@@ -456,6 +472,52 @@ bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t
   return BF_OK;
 }
 
+bf_status bf_regrid_create_2d(const bf_plan* plan, const double* dircos, int32_t n_point, bf_regrid** rg) {
+  if (!rg) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create_2d: NULL rg");
+  *rg = nullptr;
+  if (!plan || !dircos) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create_2d: NULL plan or dircos");
+  const bf_plan_desc& d = plan->d;
+  if (plan->sel || keep_of(d) != d.m_ns)
+    return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create_2d: needs a plan without a clamp (all m_ns beams)");
+  if (d.m_ns < 2 * d.n_ns - 1 || d.m_ew < 2 * d.n_ew - 1)
+    return fail(BF_ERR_UNSUPPORTED, "regrid_create_2d: exact 2-D regridding needs m >= 2 n - 1 on both axes (m_ew = 8)");
+  if (n_point < 1 || n_point > 65536) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create_2d: n_point out of [1, 65536]");
+  std::vector<double> dew(n_point), dns(n_point);
+  for (int j = 0; j < n_point; ++j) {
+    dew[j] = dircos[2 * j];
+    dns[j] = dircos[2 * j + 1];
+    if (!(dew[j] >= -1e6 && dew[j] <= 1e6 && dns[j] >= -1e6 && dns[j] <= 1e6))
+      return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create_2d: dircos[%d] not finite", j);
+  }
+  bf_regrid* r = new (std::nothrow) bf_regrid();
+  if (!r) return fail(BF_ERR_OUT_OF_MEMORY, "regrid_create_2d: host allocation");
+  r->n_chan = d.n_chan;
+  r->n_pg = d.pol_sum ? 1 : d.n_pol;
+  r->m_ew = d.m_ew;
+  r->m_ns = d.m_ns;
+  r->n_ns = d.n_ns;
+  r->n_target = n_point;
+  r->pad = fftbf::regrid_target_pad(n_point);
+  double *dd = nullptr;
+  hipError_t e = hipMalloc(&dd, sizeof(double) * 2 * n_point);
+  if (e == hipSuccess) e = hipMemcpy(dd, dns.data(), sizeof(double) * n_point, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dd + n_point, dew.data(), sizeof(double) * n_point, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&r->w, sizeof(float) * (size_t)r->n_chan * r->pad * r->m_ns);
+  if (e == hipSuccess) e = hipMalloc(&r->wew, sizeof(float) * (size_t)r->n_chan * r->pad * 8);
+  if (e == hipSuccess)
+    e = fftbf::launch_regrid_weights(r->w, plan->dl, dd, nullptr, r->n_chan, n_point, r->n_ns, r->m_ns, nullptr);
+  if (e == hipSuccess)
+    e = fftbf::launch_regrid_ew_weights(r->wew, plan->dl, dd + n_point, r->n_chan, n_point, d.n_ew, d.m_ew, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (dd) (void)hipFree(dd);
+  if (e != hipSuccess) {
+    regrid_free(r);
+    return dev_fail(e, "regrid_create_2d: weights");
+  }
+  *rg = r;
+  return BF_OK;
+}
+
 bf_status bf_regrid_destroy(bf_regrid* rg) {
   if (!rg) return BF_OK;
   hipError_t e = hipDeviceSynchronize();
@@ -486,6 +548,7 @@ bf_status bf_regrid_intensity(const bf_regrid* rg, const float* fft_intensity, i
   a.n_taps = rg->n_taps;
   a.first = rg->first;
   a.tw = rg->tw;
+  a.wew = rg->wew;
   hipError_t e = fftbf::launch_regrid(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return dev_fail(e, "regrid_intensity: launch");
   return BF_OK;

@@ -95,8 +95,31 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   const int chan = wg % p.n_chan;
   const int blk = wg / p.n_chan;
 
-  if constexpr (TAPER != 0) {
-    for (int i = lane; i < N * 4 * TAPER; i += 64) lds_h[i] = p.taper[i];
+  if constexpr (TAPER == 1) {
+    for (int i = lane; i < N * 4; i += 64) lds_h[i] = p.taper[i];
+    __syncthreads();
+  } else if constexpr (TAPER == 2) {
+    // per antenna (a_ns, q): g = 1, h or the complex gain, times W_8^q when twisting
+    constexpr float kS = 0.70710678118654752f;
+    for (int i = lane; i < N * 4; i += 64) {
+      float gr = 1.f, gi = 0.f;
+      if (p.gain_src == 2) {
+        gr = p.taper[2 * i];
+        gi = p.taper[2 * i + 1];
+      } else if (p.gain_src == 1) {
+        gr = p.taper[i];
+      }
+      if (p.twist) {
+        const int q = i & 3;
+        const float wr = q == 0 ? 1.f : q == 1 ? kS : q == 2 ? 0.f : -kS;
+        const float wi = q == 0 ? 0.f : q == 1 ? -kS : q == 2 ? -1.f : -kS;
+        const float tr = gr * wr - gi * wi;
+        gi = gr * wi + gi * wr;
+        gr = tr;
+      }
+      lds_h[2 * i] = gr;
+      lds_h[2 * i + 1] = gi;
+    }
     __syncthreads();
   }
 
@@ -205,7 +228,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
           const int64_t tt = t_base + (int64_t)it * F + f;
           if (tt < p.n_time) {
             float2* o = static_cast<float2*>(p.out) +
-                        (((tt * p.n_chan + chan) * p.n_pol + pg) * 4 + e) * M + k2;
+                        (((tt * p.n_chan + chan) * p.n_pol + pg) * p.ew_rows + e * p.ew_mul + p.ew_off) * M + k2;
 #pragma unroll
             for (int k1 = 0; k1 < G; ++k1) {
               const cf b = z[k1];
@@ -237,14 +260,14 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
     __syncthreads();
     const int keep = p.n_keep;
     const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
-    float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * 4 * keep;
+    float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
     for (int idx = lane; idx < 4 * keep; idx += 64) {
       const int e = idx / keep, j = idx - e * keep;
       const int A = sel ? sel[j] : j;
       float v = 0.f;
 #pragma unroll
       for (int f = 0; f < F; ++f) v += lds_i[(f * 4 + e) * M + A];
-      o[idx] = v * p.norm;
+      o[(e * p.ew_mul + p.ew_off) * keep + j] = v * p.norm;
     }
   }
 }

@@ -73,6 +73,20 @@ __global__ void k_regrid_weights(float* w, const double* dl, const double* sin_t
   w[i] = (float)regrid_weight(A, dl[2 * c + 1] * sin_t[j], n, m, coef);
 }
 
+// E-W weights of 2-D pointings: w[chan][target][e], e < m (= 8), zero rows
+// for padded targets; the pointed kernel of eq. e:bp_max_arbitrary on the
+// (padded) E-W axis.
+__global__ void k_regrid_ew_weights(float* w, const double* dl, const double* dircos_ew, int n_chan, int n_target,
+                                    int n_target_pad, int n, int m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n_chan * n_target_pad * m;
+  if (i >= total) return;
+  const int e = (int)(i % m);
+  const int j = (int)((i / m) % n_target_pad);
+  const int c = (int)(i / ((int64_t)m * n_target_pad));
+  w[i] = j < n_target ? (float)regrid_weight(e, dl[2 * c] * dircos_ew[j], n, m, nullptr) : 0.f;
+}
+
 // Compact kernels: the k FFT beams nearest the steering on the circular beam
 // grid, first = rint(y M) - (k-1)/2 (mod M), with their full-kernel weights.
 // Layout: first[chan][target], tw[chan][tap][target].
@@ -92,8 +106,10 @@ __global__ void k_regrid_tap_table(int* first, float* tw, const double* dl, cons
 }
 
 // KC: beams per chunk (32 when M = 32, else 64).  NT: 16-target MFMA tiles
-// per wave (TT = 16 NT targets per workgroup).
-template <int KC, int NT>
+// per wave (TT = 16 NT targets per workgroup).  EW2D: 2-D pointings on an
+// E-W axis padded to 8 beams -- the 8 E-W rows of each (block, pol group)
+// are combined with the E-W weights in the epilogue.
+template <int KC, int NT, bool EW2D>
 __global__ __launch_bounds__(256, 2) void k_regrid(RegridArgs a) {
   constexpr int TT = 16 * NT;
   constexpr int KS = KC / 4;              // MFMA steps per chunk = beams per lane per chunk
@@ -161,6 +177,28 @@ __global__ __launch_bounds__(256, 2) void k_regrid(RegridArgs a) {
   }
 
   // acc[nt][i]: row 16 wave + 4 g + i, target t0 + 16 nt + lane % 16
+  if constexpr (EW2D) {
+    // rows 16 wave + [0, 8) and + [8, 16) are two (block, pol group) groups of
+    // 8 E-W beams: lane group g holds E-W beams 4 (g & 1) .. +3 of group g >> 1
+    const int grp_row = blockIdx.x * 64 + wave * 16 + 8 * (g >> 1);
+    const bool ok = grp_row < rows && (g & 1) == 0;
+    const int gi = grp_row >> 3;
+    const int blk = gi / a.n_pg, pg = gi - blk * a.n_pg;
+    float* o = a.out + (((int64_t)blk * a.n_chan + chan) * a.n_pg + pg) * a.n_target;
+    const float* wew = a.wew + ((int64_t)chan * a.n_target_pad + t0) * 8 + 4 * (g & 1);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int t = t0 + 16 * nt + m;
+      const f32x4 we = *reinterpret_cast<const f32x4*>(wew + (16 * nt + m) * 8);
+      float part = we[0] * acc[nt][0];
+      part = fmaf(we[1], acc[nt][1], part);
+      part = fmaf(we[2], acc[nt][2], part);
+      part = fmaf(we[3], acc[nt][3], part);
+      part += __shfl_xor(part, 16);
+      if (ok && t < a.n_target) o[t] = part;
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int ro = blockIdx.x * 64 + wave * 16 + 4 * g + i;
@@ -216,12 +254,12 @@ __global__ __launch_bounds__(256) void k_regrid_taps(RegridArgs a) {
   }
 }
 
-template <int KC>
+template <int KC, bool EW2D>
 hipError_t launch_kc(const RegridArgs& a, dim3 grid, bool wide, hipStream_t s) {
   if (wide)
-    hipLaunchKernelGGL((k_regrid<KC, 16>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_regrid<KC, 16, EW2D>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_regrid<KC, 4>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_regrid<KC, 4, EW2D>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -238,6 +276,15 @@ hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t
   const int pad = regrid_target_pad(n_target);
   const int64_t total = (int64_t)n_chan * pad * m;
   hipLaunchKernelGGL(k_regrid_weights, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, dl, sin_t, coef,
+                     n_chan, n_target, pad, n, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_regrid_ew_weights(float* w, const double* dl, const double* dircos_ew, int n_chan, int n_target,
+                                    int n, int m, hipStream_t s) {
+  const int pad = regrid_target_pad(n_target);
+  const int64_t total = (int64_t)n_chan * pad * m;
+  hipLaunchKernelGGL(k_regrid_ew_weights, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, w, dl, dircos_ew,
                      n_chan, n_target, pad, n, m);
   return hipGetLastError();
 }
@@ -279,7 +326,11 @@ hipError_t launch_regrid(const RegridArgs& a_in, hipStream_t s) {
   const bool wide = a.n_target_pad > 64;
   const int tt = wide ? a.n_target_pad / 256 : 1;
   const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)tt, (unsigned)a.n_chan);
-  return a.m_ns == 32 ? launch_kc<32>(a, grid, wide, s) : launch_kc<64>(a, grid, wide, s);
+  if (a.wew) {
+    if (a.m_ew != 8) return hipErrorNotSupported;
+    return a.m_ns == 32 ? launch_kc<32, true>(a, grid, wide, s) : launch_kc<64, true>(a, grid, wide, s);
+  }
+  return a.m_ns == 32 ? launch_kc<32, false>(a, grid, wide, s) : launch_kc<64, false>(a, grid, wide, s);
 }
 
 }  // namespace fftbf

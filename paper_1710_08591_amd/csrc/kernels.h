@@ -20,6 +20,14 @@ struct Fft32Args {
   int n_keep;
   void* out;
   float norm;              // 1/(n_ew n_ns) for intensities, its square root for complex beams
+  // E-W rows: the output holds ew_rows E-W beams per (sample or block, chan,
+  // pol group); this launch's E-W beam e goes to row e * ew_mul + ew_off.
+  int ew_rows, ew_mul, ew_off;
+  // complex-gain variant only: where the per-antenna factors come from (0 unit,
+  // 1 real weights in `taper`, 2 complex gains in `taper`), and whether they
+  // are multiplied by W_8^{a_ew} (the odd E-W beams of an 8-point padded E-W
+  // transform are the 4-point DFT of x_a W_8^{a_ew})
+  int gain_src, twist;
 };
 
 int fft32_frames_per_pass(int n_ns);
@@ -75,6 +83,8 @@ struct RegridArgs {
   int64_t n_blk;
   int n_chan, n_pg, m_ew, m_ns, n_target, n_target_pad;
   int n_taps;              // 0: dense weights w; 1..kRegridMaxTaps: compact kernels
+  const float* wew;        // 2-D pointings: [n_chan][n_target_pad][8] E-W weights, else null;
+                           // out is then [n_blk][n_chan][n_pg][n_target]
   int rows_per_chan, log2_r;   // set by launch_regrid
 };
 constexpr int kRegridMaxTaps = 8;
@@ -82,6 +92,9 @@ int regrid_target_pad(int n_target);
 // coef: device double [n] window lag coefficients, or nullptr for the pointed kernel
 hipError_t launch_regrid_weights(float* w, const double* dl, const double* sin_t, const double* coef, int n_chan,
                                  int n_target, int n, int m, hipStream_t s);
+// E-W regridding weights of 2-D pointings, w[chan][target_pad][m_ew = 8]
+hipError_t launch_regrid_ew_weights(float* w, const double* dl, const double* dircos_ew, int n_chan, int n_target,
+                                    int n, int m, hipStream_t s);
 hipError_t launch_regrid_tap_table(int* first, float* tw, const double* dl, const double* sin_t, const double* coef,
                                    int n_chan, int n_target, int k, int n, int m, hipStream_t s);
 hipError_t launch_regrid(const RegridArgs& a, hipStream_t s);

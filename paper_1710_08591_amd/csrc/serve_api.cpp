@@ -173,7 +173,8 @@ bf_status bf_server_create(const bf_plan* plan, int64_t ring_samples, int64_t hb
   if (!plan) return sfail(BF_ERR_INVALID_ARGUMENT, "server_create: NULL plan");
   bf_plan_desc d;
   const double* dl = bf_internal_plan_dl(plan, &d);
-  if (d.n_ew != 4 || d.n_ns != 16 || d.m_ns != 32 || d.block != 16 || d.precision != BF_PREC_FP32 || d.pol_sum)
+  if (d.n_ew != 4 || d.m_ew != 4 || d.n_ns != 16 || d.m_ns != 32 || d.block != 16 || d.precision != BF_PREC_FP32 ||
+      d.pol_sum)
     return sfail(BF_ERR_UNSUPPORTED, "server_create: needs an FP32 4 x 16 lattice plan, block 16, per-pol output");
   if (ring_samples < 16 || ring_samples % 16)
     return sfail(BF_ERR_INVALID_ARGUMENT, "server_create: ring_samples must be a positive multiple of 16");
