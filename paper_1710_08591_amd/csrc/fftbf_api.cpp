@@ -235,7 +235,7 @@ static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, in
       // DFT of x_a W_8^{a_ew} (with the window or gains, if any)
       a.ew_off = 1;
       a.twist = 1;
-      e = fftbf::launch_fft32(a, d.n_ns, 2, kind == BF_OUT_COMPLEX, n_wg, s);
+      e = fftbf::launch_fft32(a, d.n_ns, taper ? 2 : 3, kind == BF_OUT_COMPLEX, n_wg, s);
     }
   } else {
     fftbf::MixArgs a{};

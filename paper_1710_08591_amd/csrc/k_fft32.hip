@@ -48,6 +48,36 @@ __device__ __forceinline__ void ew_weights(int e, int& wre, int& wim) {
   }
 }
 
+// dot8 weight words for sum_q c_q x_q over the four E-W samples of a dword,
+// c_q = cr[q] + i ci[q] with components in {-1, 0, 1}: Re = cr xr - ci xi,
+// Im = ci xr + cr xi, one signed nibble per term.
+__device__ __forceinline__ void cweights(const int* cr, const int* ci, int& wre, int& wim) {
+  wre = 0;
+  wim = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
+    wre |= ((cr[q] & 0xF) << sr) | (((-ci[q]) & 0xF) << si);
+    wim |= ((ci[q] & 0xF) << sr) | ((cr[q] & 0xF) << si);
+  }
+}
+
+// Odd beam 2e+1 of the zero-padded 8-point E-W transform of x_0..x_3:
+//   sum_q x_q W_8^{q (2e+1)} = P + Q / sqrt(2),
+//   P = x_0 + (-1)^e (-i) x_2,   Q = (-i)^e (1 - i) x_1 + i^e (-1 - i) x_3,
+// both integer combinations with coefficients in {-1, 0, 1}.
+__device__ __forceinline__ void ew8_odd_weights(int e, int& wpr, int& wpi, int& wqr, int& wqi) {
+  const int mr[4] = {1, 0, -1, 0}, mi[4] = {0, -1, 0, 1};          // (-i)^e
+  int pcr[4] = {1, 0, 0, 0}, pci[4] = {0, 0, (e & 1) ? 1 : -1, 0};
+  int qcr[4] = {0, 0, 0, 0}, qci[4] = {0, 0, 0, 0};
+  qcr[1] = mr[e] + mi[e];                  // (-i)^e (1 - i)
+  qci[1] = mi[e] - mr[e];
+  qcr[3] = -mr[e] - mi[e];                 // i^e (-1 - i), i^e = conj((-i)^e)
+  qci[3] = mi[e] - mr[e];
+  cweights(pcr, pci, wpr, wpi);
+  cweights(qcr, qci, wqr, wqi);
+}
+
 struct TaperLane {
   bool swap[4];
   float sre[4], sim[4];
@@ -72,7 +102,8 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
 
 // TAPER: 0 none (E-W DFT as signed 4-bit dot products), 1 real per-antenna
 // weights h_a, 2 complex per-antenna gains g_a (float2), applied before the
-// E-W DFT.
+// E-W DFT, 3 none and the odd beams of the zero-padded 8-point E-W transform
+// (signed 4-bit dot products again).
 template <int N, int G, int TAPER, bool CPLX>
 __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
@@ -84,7 +115,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   static_assert(F * 4 * M * 4 <= F * 4 * G * YS * 8, "block-end sums must fit the LDS");
 
   __shared__ cf lds_y[F * 4 * G * YS];
-  __shared__ float lds_h[TAPER == 2 ? N * 8 : TAPER ? N * 4 : 1];
+  __shared__ float lds_h[TAPER == 2 ? N * 8 : TAPER == 1 ? N * 4 : 1];
 
   const int lane = threadIdx.x;
   const int f1 = lane / (4 * G), e1 = (lane / G) & 3, a1 = lane % G;
@@ -131,9 +162,11 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
     tw1[k] = cf{w.x, w.y};
   }
 
-  int wre = 0, wim = 0;
+  int wre = 0, wim = 0, wqr = 0, wqi = 0;
   TaperLane tl{};
-  if constexpr (TAPER != 0) tl = taper_lane(e1); else ew_weights(e1, wre, wim);
+  if constexpr (TAPER == 3) ew8_odd_weights(e1, wre, wim, wqr, wqi);
+  else if constexpr (TAPER != 0) tl = taper_lane(e1);
+  else ew_weights(e1, wre, wim);
 
   float acc[R2][G];
 #pragma unroll
@@ -172,7 +205,12 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 #pragma unroll
       for (int j = 0; j < L; ++j) {
         const uint32_t d = cur[j];
-        if constexpr (TAPER == 2) {
+        if constexpr (TAPER == 3) {
+          constexpr float kS = 0.70710678118654752f;
+          const float pr = (float)sdot8((int)d, wre), pi = (float)sdot8((int)d, wim);
+          const float qr = (float)sdot8((int)d, wqr), qi = (float)sdot8((int)d, wqi);
+          x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pi)};
+        } else if constexpr (TAPER == 2) {
           // z_q = g_q x_q, then the E-W twiddle (-i)^{e q} as a swap and signs
           const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
           const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
@@ -281,7 +319,8 @@ void launch_nt(const Fft32Args& a, bool cplx, dim3 grid, hipStream_t s) {
 template <int N, int G>
 hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, int64_t n_wg, hipStream_t s) {
   const dim3 grid((unsigned)n_wg);
-  if (taper == 2) launch_nt<N, G, 2>(a, cplx, grid, s);
+  if (taper == 3) launch_nt<N, G, 3>(a, cplx, grid, s);
+  else if (taper == 2) launch_nt<N, G, 2>(a, cplx, grid, s);
   else if (taper == 1) launch_nt<N, G, 1>(a, cplx, grid, s);
   else launch_nt<N, G, 0>(a, cplx, grid, s);
   return hipGetLastError();

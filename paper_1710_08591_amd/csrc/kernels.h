@@ -32,7 +32,8 @@ struct Fft32Args {
 
 int fft32_frames_per_pass(int n_ns);
 int fft32_group(int n_ns);
-// taper: 0 none, 1 real weights, 2 complex gains
+// taper: 0 none, 1 real weights, 2 complex gains, 3 none with the odd E-W
+// beams of the zero-padded 8-point E-W transform
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s);
 
