@@ -250,6 +250,35 @@ def run_chime_regrid(dev, w, volts, n_target: int = 256) -> dict:
                     "hbm_frac": loc_bytes / (loc_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                     "max_abs_sin_theta_diff_sampled_vs_oracle_chain": loc_err}
     plan.close()
+    # E-W axis padded to 8 beams and exact 2-D regridding to 256 pointings
+    del out
+    plan8 = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=8, m_ns=w.m_ns, n_pol=w.n_pol, n_chan=w.n_chan,
+                    block=w.block, d_over_lambda=dl)
+    dirs = sg.pointings(n_target, 12)
+    rg2 = bf.Regrid2D(plan8, dirs)
+    fft8 = torch.empty(plan8.out_shape(w.n_time), dtype=torch.float32, device=dev)
+    del fft_i
+    torch.cuda.empty_cache()
+    fft8_ms = _time_launches(lambda: bf.beamform_fft(plan8, volts, out=fft8), 3, warmup=1)
+    out2 = torch.empty((n_blk, w.n_chan, w.n_pol, n_target), dtype=torch.float32, device=dev)
+    r2_ms = _time_launches(lambda: rg2(fft8, out=out2), 10)
+    e2 = 0.0
+    for _ in range(2):
+        blk, c = int(rng.integers(n_blk)), int(rng.integers(w.n_chan))
+        vs = sg.volts(w, blk * 16, 16, chans=[c])
+        ref = orc.tied_intensity(vs, dirs, dl, 16, chans=[c])[0, 0]
+        e2 = max(e2, float(np.max(np.abs(out2[blk, c].cpu().numpy() - ref) / ref)))
+    rows8 = n_blk * w.n_chan * w.n_pol * 8
+    flops2 = 2.0 * rows8 * w.m_ns * n_target
+    regrid_2d = {"workload": "same voltages, E-W zero-padded to 8 beams (8 x 512 FFT beams), exact 2-D regridding "
+                             f"to {n_target} pointings per channel, pol and block",
+                 "fft_m_ew8_ms": fft8_ms, "kernel_ms": r2_ms,
+                 "mfma_fp32_tflops": flops2 / (r2_ms / 1e3) / 1e12,
+                 "mfma_fp32_frac": flops2 / (r2_ms / 1e3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+                 "max_rel_power_err_sampled_vs_phased_beams": e2}
+    rg2.close()
+    plan8.close()
+    del fft8, out2
     return {"workload": "same voltages as the headline, no clamp (512 N-S beams), regridded to "
                         f"{n_target} sin(theta) targets per E-W beam, channel and block",
             "fft_unclamped_ms": fft_ms, "kernel_ms": ms,
@@ -259,7 +288,8 @@ def run_chime_regrid(dev, w, volts, n_target: int = 256) -> dict:
             "max_rel_power_err_sampled": err,
             "max_err_over_sum_abs_w_b_sampled": err_prop,
             "optimal_window_half_sine": windowed,
-            "localisation": localisation}
+            "localisation": localisation,
+            "regrid_2d_m_ew8": regrid_2d}
 
 
 def run_extras(dev) -> dict:
