@@ -95,10 +95,11 @@ def fft_beams(eta: np.ndarray, m_ew: int, m_ns: int, taper: Optional[np.ndarray]
     lattice (separable phase, normalisation 1/sqrt(n_ew n_ns)), after the
     per-antenna window h (Sec. "Controlling beam shape with windowing").
     Zero padding to m > n is implicit: antennas beyond n contribute zero.
+    For m < n the same weights over all n antennas are the cyclic
+    co-adding of the same section (antennas with equal a mod m share a
+    phase); the normalisation stays n^-1/2.
     """
     n_ns, n_ew = eta.shape[-2], eta.shape[-1]
-    if m_ew < n_ew or m_ns < n_ns:
-        raise ValueError("transform shorter than the array needs cyclic co-adding")
     x = eta if taper is None else eta * _weights(taper)
     w_ew = dft_matrix(n_ew, m_ew)            # [m_ew][n_ew]
     w_ns = dft_matrix(n_ns, m_ns)            # [m_ns][n_ns]

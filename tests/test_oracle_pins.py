@@ -213,6 +213,28 @@ def test_2d_regridding_exact_with_padded_ew_axis():
             assert err > 1e-2
 
 
+@pytest.mark.parametrize("n,m", [(32, 16), (64, 16), (256, 128), (48, 16)])
+def test_cyclic_coadding_when_fewer_beams_than_antennas(n, m):
+    """Sec. "Redundant arrays and Fourier transform beamforming": for M < n the
+    array to transform is the antennas co-added by a mod M.  The oracle's
+    beams with weights n^-1/2 e^{-i 2 pi A a / M} over all n antennas (eq.
+    e:w_A^a, e:fftbeamform) equal that recipe: fold, then an M-point DFT
+    written out as a sum, normalised by n^-1/2."""
+    rng = np.random.default_rng(n + m)
+    eta = rng.normal(size=(3, n, 4)) + 1j * rng.normal(size=(3, n, 4))
+    got = orc.fft_beams(eta, 4, m)                                  # [3][4][m]
+    folded = np.zeros((3, m, 4), dtype=np.complex128)
+    for a in range(n):
+        folded[:, a % m] += eta[:, a]
+    A = np.arange(m)
+    ref = np.empty_like(got)
+    for k in range(m):
+        ew = np.exp(-2j * np.pi * np.outer(np.arange(4), np.arange(4)) / 4)           # [A_ew][a_ew]
+        ns = np.exp(-2j * np.pi * k * A / m)                                            # [a_ns]
+        ref[:, :, k] = np.einsum("tne,n,fe->tf", folded, ns, ew) / np.sqrt(n * 4)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
 def test_paper_regridding_fails_below_2n_minus_1():
     n, m = 16, 30
     w, v = _small_array(16, 1, n, nt=64)
