@@ -68,7 +68,13 @@ typedef struct bf_plan bf_plan;
  * the 4-point DFT of x_a W_8^{a_ew}, formed by a second pass over the
  * voltages; tied beams and the server need m_ew = 4);
  * n_ns a power of two in [16, 256] with m_ns = 2 n_ns (zero padding by two,
- * the smallest power of two with M >= 2n - 1, eq. e:b2n-1); block a
+ * the smallest power of two with M >= 2n - 1, eq. e:b2n-1), or, for FP32
+ * plans with m_ew = 4 and no clamp, m_ns a power of two in [16, 128] below
+ * n_ns: cyclic co-adding (Sec. "Redundant arrays and Fourier transform
+ * beamforming"), the N-S antennas summed by a_ns mod m_ns before an m_ns-point
+ * transform, i.e. the weights n^-1/2 e^{-i 2 pi A a / M} of eq. e:w_A^a with
+ * M < n (a real window is allowed up to n_ns = 8 m_ns, complex gains are
+ * not); block a
  * multiple of 16 (mixed precision) or of 4 (FP32); 1 <= n_pol <= 2.
  * Other shapes return BF_ERR_UNSUPPORTED.
  */

@@ -19,6 +19,8 @@ struct bf_plan {
   int g = 0, l2 = 0;       // FP32 N-S split: m_ns = l2 * g
   float2* tw = nullptr;    // [g][l2] FP32 twiddles W_M^{a1 k2}
   int32_t* sel = nullptr;  // [n_chan][n_ns_keep] or null (identity)
+  int fold = 1;            // cyclic co-adding: n_ns / m_ns when m_ns < n_ns
+  int32_t* even = nullptr; // cyclic co-adding: [n_chan][m_ns] = 2 A (the even padded outputs)
   double* dl = nullptr;    // [n_chan][2]
   void* mix = nullptr;     // mixed-precision operand tables
 };
@@ -50,6 +52,7 @@ void free_plan(bf_plan* p) {
   if (!p) return;
   if (p->tw) (void)hipFree(p->tw);
   if (p->sel) (void)hipFree(p->sel);
+  if (p->even) (void)hipFree(p->even);
   if (p->dl) (void)hipFree(p->dl);
   if (p->mix) (void)hipFree(p->mix);
   delete p;
@@ -88,15 +91,19 @@ bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
   if (d.n_ew <= 0 || d.n_ns <= 0 || d.m_ew <= 0 || d.m_ns <= 0 || d.n_pol <= 0 || d.n_chan <= 0 ||
       d.block <= 0 || d.n_ns_keep < 0)
     return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: sizes must be positive");
-  if (d.m_ew < d.n_ew || d.m_ns < d.n_ns)
-    return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: transform shorter than the array");
+  if (d.m_ew < d.n_ew) return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: E-W transform shorter than the array");
+  const bool folded = d.m_ns < d.n_ns;    // cyclic co-adding (e:fftbeamform with M < n)
   if (d.n_ew != 4 || (d.m_ew != 4 && d.m_ew != 8))
     return fail(BF_ERR_UNSUPPORTED, "plan_create: n_ew = 4 with m_ew = 4 or 8 is supported");
   if (d.m_ew == 8 && d.precision != BF_PREC_FP32)
     return fail(BF_ERR_UNSUPPORTED, "plan_create: the padded E-W axis (m_ew = 8) needs an FP32 plan");
-  if (!is_pow2(d.n_ns) || d.n_ns < 16 || d.n_ns > 256 || d.m_ns != 2 * d.n_ns)
+  if (!is_pow2(d.n_ns) || d.n_ns < 16 || d.n_ns > 256 ||
+      (folded ? (!is_pow2(d.m_ns) || d.m_ns < 16 || d.m_ns > 128) : d.m_ns != 2 * d.n_ns))
     return fail(BF_ERR_UNSUPPORTED,
-                "plan_create: n_ns must be a power of two in [16, 256] with m_ns = 2 n_ns");
+                "plan_create: n_ns must be a power of two in [16, 256] with m_ns = 2 n_ns, or (cyclic "
+                "co-adding) m_ns a power of two in [16, 128] below n_ns");
+  if (folded && (d.precision != BF_PREC_FP32 || d.m_ew != 4 || (d.n_ns_keep && d.n_ns_keep != d.m_ns)))
+    return fail(BF_ERR_UNSUPPORTED, "plan_create: cyclic co-adding needs an FP32 plan, m_ew = 4 and no clamp");
   if (d.n_pol > 2) return fail(BF_ERR_UNSUPPORTED, "plan_create: at most 2 polarisations");
   if (d.pol_sum != 0 && d.pol_sum != 1) return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: pol_sum is 0 or 1");
   if (d.precision < BF_PREC_FP32 || d.precision > BF_PREC_FP8_MFMA)
@@ -129,11 +136,20 @@ bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { free_plan(p); return dev_fail(e, "plan_create: hipGetDevice"); }
 
-  p->g = fftbf::fft32_group(d.n_ns);
-  p->l2 = d.m_ns / p->g;
+  // the transform's N: n_ns, or m_ns when folding (its padded outputs 2A are the beams)
+  const int kn = folded ? d.m_ns : d.n_ns;
+  p->fold = d.n_ns / kn;
+  p->g = fftbf::fft32_group(kn);
+  p->l2 = 2 * kn / p->g;
   hipStream_t s = nullptr;
   e = hipMalloc(&p->tw, sizeof(float2) * p->g * p->l2);
-  if (e == hipSuccess) e = fftbf::launch_twiddle_table(p->tw, p->g, p->l2, d.m_ns, s);
+  if (e == hipSuccess) e = fftbf::launch_twiddle_table(p->tw, p->g, p->l2, 2 * kn, s);
+  if (e == hipSuccess && folded) {
+    std::vector<int32_t> ev((size_t)d.n_chan * d.m_ns);
+    for (size_t i = 0; i < ev.size(); ++i) ev[i] = 2 * (int32_t)(i % d.m_ns);
+    e = hipMalloc(&p->even, sizeof(int32_t) * ev.size());
+    if (e == hipSuccess) e = hipMemcpy(p->even, ev.data(), sizeof(int32_t) * ev.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess && d.ns_select) {
     e = hipMalloc(&p->sel, sizeof(int32_t) * d.n_chan * keep);
     if (e == hipSuccess)
@@ -219,8 +235,9 @@ static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, in
     a.block = d.block;
     a.tw = plan->tw;
     a.taper = taper;
-    a.sel = plan->sel;
+    a.sel = plan->fold > 1 ? plan->even : plan->sel;
     a.n_keep = keep_of(d);
+    a.fold = plan->fold;
     a.out = out;
     const float inv_n = 1.0f / float(d.n_ew * d.n_ns);
     a.norm = (kind == BF_OUT_COMPLEX) ? 1.0f / std::sqrt(float(d.n_ew * d.n_ns)) : inv_n;
@@ -229,7 +246,9 @@ static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, in
     a.ew_off = 0;
     a.gain_src = taper ? taper_kind : 0;
     a.twist = 0;
-    e = fftbf::launch_fft32(a, d.n_ns, taper ? taper_kind : 0, kind == BF_OUT_COMPLEX, n_wg, s);
+    if (plan->fold > 1 && taper && (taper_kind != 1 || plan->fold > 8))
+      return fail(BF_ERR_UNSUPPORTED, "beamform_fft: cyclic co-adding takes a real window only, up to 8-fold");
+    e = fftbf::launch_fft32(a, d.n_ns / plan->fold, taper ? taper_kind : 0, kind == BF_OUT_COMPLEX, n_wg, s);
     if (e == hipSuccess && d.m_ew == 8) {
       // odd E-W beams of the zero-padded 8-point E-W transform: the 4-point
       // DFT of x_a W_8^{a_ew} (with the window or gains, if any)
@@ -305,8 +324,8 @@ bf_status bf_form_tied_beams(const bf_plan* plan, const void* fft_beams, int64_t
     return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: n_time not a multiple of block");
   if (kind == BF_OUT_COMPLEX && d.pol_sum)
     return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: complex output cannot sum polarisations");
-  if ((d.m_ns != 32 && d.m_ns != 64) || d.m_ew != 4)
-    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams: m_ns must be 32 or 64 and m_ew 4");
+  if ((d.m_ns != 32 && d.m_ns != 64) || d.m_ew != 4 || d.m_ns < d.n_ns)
+    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams: m_ns must be 32 or 64 (and >= n_ns) and m_ew 4");
   fftbf::TiedArgs a{};
   a.beams = static_cast<const float2*>(fft_beams);
   a.n_time = n_time;

@@ -104,9 +104,14 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
 // weights h_a, 2 complex per-antenna gains g_a (float2), applied before the
 // E-W DFT, 3 none and the odd beams of the zero-padded 8-point E-W transform
 // (signed 4-bit dot products again).
-template <int N, int G, int TAPER, bool CPLX>
+// FOLD > 1: cyclic co-adding (fewer beams than antennas, e:fftbeamform with
+// M < n): the N * FOLD antennas along N-S are summed onto N positions by
+// a mod N before an N-point transform, whose outputs are the even outputs
+// of the zero-padded 2N-point transform computed here.
+template <int N, int G, int TAPER, bool CPLX, int FOLD = 1>
 __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
+  constexpr int NA = N * FOLD, LA = L * FOLD;   // antennas along N-S; dwords per lane per frame
   constexpr int F = 64 / (4 * G);      // frames handled side by side
   constexpr int R2 = (F * 4 * L2) / 64; // pass-2 tasks per lane
   constexpr int YS = L2 + 1;           // padded LDS row, complex elements
@@ -115,7 +120,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   static_assert(F * 4 * M * 4 <= F * 4 * G * YS * 8, "block-end sums must fit the LDS");
 
   __shared__ cf lds_y[F * 4 * G * YS];
-  __shared__ float lds_h[TAPER == 2 ? N * 8 : TAPER == 1 ? N * 4 : 1];
+  __shared__ float lds_h[TAPER == 2 ? NA * 8 : TAPER == 1 ? NA * 4 : 1];
 
   const int lane = threadIdx.x;
   const int f1 = lane / (4 * G), e1 = (lane / G) & 3, a1 = lane % G;
@@ -127,12 +132,12 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   const int blk = wg / p.n_chan;
 
   if constexpr (TAPER == 1) {
-    for (int i = lane; i < N * 4; i += 64) lds_h[i] = p.taper[i];
+    for (int i = lane; i < NA * 4; i += 64) lds_h[i] = p.taper[i];
     __syncthreads();
   } else if constexpr (TAPER == 2) {
     // per antenna (a_ns, q): g = 1, h or the complex gain, times W_8^q when twisting
     constexpr float kS = 0.70710678118654752f;
-    for (int i = lane; i < N * 4; i += 64) {
+    for (int i = lane; i < NA * 4; i += 64) {
       float gr = 1.f, gi = 0.f;
       if (p.gain_src == 2) {
         gr = p.taper[2 * i];
@@ -176,18 +181,18 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 
   const int64_t t_base = (int64_t)blk * p.block;
   const int n_it = p.block / F;
-  const int64_t frame_stride = (int64_t)p.n_chan * p.n_pol * N;  // dwords per sample
+  const int64_t frame_stride = (int64_t)p.n_chan * p.n_pol * NA;  // dwords per sample
 
   for (int pi = 0; pi < p.pol_iter; ++pi) {
     const int pol = (p.pol_iter == 1) ? pg : pi;
-    const uint32_t* src = p.volts + ((int64_t)chan * p.n_pol + pol) * N + a1;
+    const uint32_t* src = p.volts + ((int64_t)chan * p.n_pol + pol) * NA + a1;
 
-    uint32_t cur[L], nxt[L];
+    uint32_t cur[LA], nxt[LA];
     {
       const int64_t t = t_base + f1;
       const bool ok = t < p.n_time;
 #pragma unroll
-      for (int j = 0; j < L; ++j) cur[j] = ok ? __builtin_nontemporal_load(src + t * frame_stride + G * j) : 0u;
+      for (int j = 0; j < LA; ++j) cur[j] = ok ? __builtin_nontemporal_load(src + t * frame_stride + G * j) : 0u;
     }
 
     for (int it = 0; it < n_it; ++it) {
@@ -197,21 +202,31 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
         const int64_t tn = t + F;
         const bool okn = tn < p.n_time;
 #pragma unroll
-        for (int j = 0; j < L; ++j) nxt[j] = okn ? __builtin_nontemporal_load(src + tn * frame_stride + G * j) : 0u;
+        for (int j = 0; j < LA; ++j) nxt[j] = okn ? __builtin_nontemporal_load(src + tn * frame_stride + G * j) : 0u;
       }
 
       // ---- E-W DFT for this lane's beam e1 at N-S positions a1 + G j ----
+      // (with FOLD > 1, summed over the antennas a1 + G j + N f, f < FOLD)
       cf x[L];
 #pragma unroll
       for (int j = 0; j < L; ++j) {
-        const uint32_t d = cur[j];
-        if constexpr (TAPER == 3) {
+        if constexpr (TAPER == 0) {
+          int sr = 0, si = 0;
+#pragma unroll
+          for (int f = 0; f < FOLD; ++f) {
+            sr += sdot8((int)cur[j + L * f], wre);
+            si += sdot8((int)cur[j + L * f], wim);
+          }
+          x[j] = cf{(float)sr, (float)si};
+        } else if constexpr (TAPER == 3) {
           constexpr float kS = 0.70710678118654752f;
+          const uint32_t d = cur[j];
           const float pr = (float)sdot8((int)d, wre), pi = (float)sdot8((int)d, wim);
           const float qr = (float)sdot8((int)d, wqr), qi = (float)sdot8((int)d, wqi);
           x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pi)};
         } else if constexpr (TAPER == 2) {
           // z_q = g_q x_q, then the E-W twiddle (-i)^{e q} as a swap and signs
+          const uint32_t d = cur[j];
           const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
           const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
           const float gr[4] = {g01.x, g01.z, g23.x, g23.z}, gi[4] = {g01.y, g01.w, g23.y, g23.w};
@@ -225,21 +240,23 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
             im = fmaf(tl.sim[q], tl.swap[q] ? zr : zi, im);
           }
           x[j] = cf{re, im};
-        } else if constexpr (TAPER == 1) {
-          const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 4]);
-          const float hq[4] = {h.x, h.y, h.z, h.w};
+        } else {
           float re = 0.f, im = 0.f;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
-            const float u = tl.swap[q] ? xi : xr;
-            const float v = tl.swap[q] ? xr : xi;
-            re = fmaf(tl.sre[q] * hq[q], u, re);
-            im = fmaf(tl.sim[q] * hq[q], v, im);
+          for (int f = 0; f < FOLD; ++f) {
+            const uint32_t d = cur[j + L * f];
+            const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * (j + L * f)) * 4]);
+            const float hq[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
+              const float u = tl.swap[q] ? xi : xr;
+              const float v = tl.swap[q] ? xr : xi;
+              re = fmaf(tl.sre[q] * hq[q], u, re);
+              im = fmaf(tl.sim[q] * hq[q], v, im);
+            }
           }
           x[j] = cf{re, im};
-        } else {
-          x[j] = cf{(float)sdot8((int)d, wre), (float)sdot8((int)d, wim)};
         }
       }
 
@@ -263,14 +280,16 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
         for (int j = 0; j < G; ++j) z[j] = col[j * YS];
         dit<G>(z);
         if constexpr (CPLX) {
+          // with FOLD > 1 only the even padded outputs 2A are beams (A < N)
+          constexpr int MO = FOLD > 1 ? N : M, SO = FOLD > 1 ? 2 : 1;
           const int64_t tt = t_base + (int64_t)it * F + f;
-          if (tt < p.n_time) {
+          if (tt < p.n_time && (k2 % SO) == 0) {
             float2* o = static_cast<float2*>(p.out) +
-                        (((tt * p.n_chan + chan) * p.n_pol + pg) * p.ew_rows + e * p.ew_mul + p.ew_off) * M + k2;
+                        (((tt * p.n_chan + chan) * p.n_pol + pg) * p.ew_rows + e * p.ew_mul + p.ew_off) * MO + k2 / SO;
 #pragma unroll
             for (int k1 = 0; k1 < G; ++k1) {
               const cf b = z[k1];
-              o[L2 * k1] = make_float2(b.r * p.norm, b.i * p.norm);
+              o[(L2 / SO) * k1] = make_float2(b.r * p.norm, b.i * p.norm);
             }
           }
         } else {
@@ -281,7 +300,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
       __syncthreads();
 
 #pragma unroll
-      for (int j = 0; j < L; ++j) cur[j] = nxt[j];
+      for (int j = 0; j < LA; ++j) cur[j] = nxt[j];
     }
   }
 
@@ -310,10 +329,26 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   }
 }
 
-template <int N, int G, int T>
+template <int N, int G, int T, int FOLD = 1>
 void launch_nt(const Fft32Args& a, bool cplx, dim3 grid, hipStream_t s) {
-  if (cplx) hipLaunchKernelGGL((k_fft32<N, G, T, true>), grid, dim3(64), 0, s, a);
-  else hipLaunchKernelGGL((k_fft32<N, G, T, false>), grid, dim3(64), 0, s, a);
+  if (cplx) hipLaunchKernelGGL((k_fft32<N, G, T, true, FOLD>), grid, dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_fft32<N, G, T, false, FOLD>), grid, dim3(64), 0, s, a);
+}
+
+// cyclic co-adding: no window, or a real window for folds up to 8 (the
+// 16-fold windowed variant would not fit its registers)
+template <int N, int G, int FOLD>
+hipError_t launch_fold(const Fft32Args& a, int taper, bool cplx, int64_t n_wg, hipStream_t s) {
+  const dim3 grid((unsigned)n_wg);
+  if (taper == 0) {
+    launch_nt<N, G, 0, FOLD>(a, cplx, grid, s);
+  } else if (taper == 1) {
+    if constexpr (FOLD <= 8) launch_nt<N, G, 1, FOLD>(a, cplx, grid, s);
+    else return hipErrorNotSupported;
+  } else {
+    return hipErrorNotSupported;
+  }
+  return hipGetLastError();
 }
 
 template <int N, int G>
@@ -352,6 +387,22 @@ int fft32_group(int n_ns) {
 
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s) {
+  if (a.fold > 1) {
+    const int key = n_ns * 1000 + a.fold;
+    switch (key) {
+      case 16002: return launch_fold<16, 4, 2>(a, taper, cplx, n_wg, s);
+      case 16004: return launch_fold<16, 4, 4>(a, taper, cplx, n_wg, s);
+      case 16008: return launch_fold<16, 4, 8>(a, taper, cplx, n_wg, s);
+      case 16016: return launch_fold<16, 4, 16>(a, taper, cplx, n_wg, s);
+      case 32002: return launch_fold<32, 8, 2>(a, taper, cplx, n_wg, s);
+      case 32004: return launch_fold<32, 8, 4>(a, taper, cplx, n_wg, s);
+      case 32008: return launch_fold<32, 8, 8>(a, taper, cplx, n_wg, s);
+      case 64002: return launch_fold<64, 8, 2>(a, taper, cplx, n_wg, s);
+      case 64004: return launch_fold<64, 8, 4>(a, taper, cplx, n_wg, s);
+      case 128002: return launch_fold<128, 16, 2>(a, taper, cplx, n_wg, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (n_ns) {
     case 16: return launch_n<16, 4>(a, taper, cplx, n_wg, s);
     case 32: return launch_n<32, 8>(a, taper, cplx, n_wg, s);

@@ -28,12 +28,16 @@ struct Fft32Args {
   // are multiplied by W_8^{a_ew} (the odd E-W beams of an 8-point padded E-W
   // transform are the 4-point DFT of x_a W_8^{a_ew})
   int gain_src, twist;
+  // cyclic co-adding: the n_ns = fold * N antennas along N-S are summed by
+  // a mod N onto the N positions of the transform (1: none)
+  int fold;
 };
 
 int fft32_frames_per_pass(int n_ns);
 int fft32_group(int n_ns);
-// taper: 0 none, 1 real weights, 2 complex gains, 3 none with the odd E-W
-// beams of the zero-padded 8-point E-W transform
+// n_ns: the transform's N (m_ns / 2, or m_ns when folding); taper: 0 none,
+// 1 real weights, 2 complex gains, 3 none with the odd E-W beams of the
+// zero-padded 8-point E-W transform
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s);
 

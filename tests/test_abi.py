@@ -38,7 +38,13 @@ def _desc(**kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(n_ns=0), L.BF_ERR_INVALID_ARGUMENT),
     (dict(block=0), L.BF_ERR_INVALID_ARGUMENT),
-    (dict(m_ns=8), L.BF_ERR_INVALID_ARGUMENT),
+    (dict(m_ns=8), L.BF_ERR_UNSUPPORTED),                 # cyclic co-adding below 16 beams
+    (dict(m_ew=2), L.BF_ERR_INVALID_ARGUMENT),            # E-W transform shorter than the array
+    (dict(n_ns=64, m_ns=48), L.BF_ERR_UNSUPPORTED),
+    (dict(n_ns=64, m_ns=32, precision=1), L.BF_ERR_UNSUPPORTED),
+    (dict(n_ns=64, m_ns=32, m_ew=8), L.BF_ERR_UNSUPPORTED),
+    (dict(n_ns=64, m_ns=32, n_ns_keep=16), L.BF_ERR_UNSUPPORTED),
+    (dict(m_ew=8, precision=1), L.BF_ERR_UNSUPPORTED),
     (dict(n_ew=2, m_ew=2), L.BF_ERR_UNSUPPORTED),
     (dict(n_ns=24, m_ns=48), L.BF_ERR_UNSUPPORTED),
     (dict(n_ns=512, m_ns=1024), L.BF_ERR_UNSUPPORTED),
