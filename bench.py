@@ -26,6 +26,9 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+# FP32 VALU issue ceiling without packed FP32 instructions (which this build
+# does not emit): 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_UNPACKED_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def flops_per_frame(n_ns: int, m_ns: int, keep: int, m_ew: int = 4) -> float:
@@ -513,6 +516,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
                      "kernel": "k_fft32<256,16>", "kernel_ms": ms_avg,
+                     "unpacked_fp32_issue_peak": FP32_UNPACKED_ISSUE_TFLOPS,
+                     "frac_of_unpacked_issue_peak": achieved_tflops / FP32_UNPACKED_ISSUE_TFLOPS,
                      "flop_per_antenna_sample": flops / ant_samples,
                      "hbm_alg_bytes": alg_bytes,
                      "hbm_alg_gbs": alg_bytes / (ms_avg / 1000.0) / 1e9,

@@ -3,7 +3,8 @@
     python -m paper_1710_08591_amd.build        (or __graft_entry__.build())
 
 Each source under csrc/ is compiled to an object in _build/ (in parallel),
-then linked into paper_1710_08591_amd/libfftbf.so.  Packed FP32 VALU ops
+then linked into paper_1710_08591_amd/libfftbf.so; csrc/bench_main.cpp
+becomes the C-ABI driver paper_1710_08591_amd/fftbf_bench.  Packed FP32 VALU ops
 are disabled for all device code.
 """
 from __future__ import annotations
@@ -30,8 +31,13 @@ CFLAGS = [
 ]
 
 
+BENCH_SRC = os.path.join(CSRC, "bench_main.cpp")
+BENCH = os.path.join(HERE, "fftbf_bench")
+
+
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                  if f.endswith((".hip", ".cpp")) and os.path.join(CSRC, f) != BENCH_SRC)
 
 
 def _compile(src: str) -> str:
@@ -59,8 +65,15 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    # the C-ABI driver (no Python), linked against the library next to it
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), BENCH_SRC, "-o", BENCH + ".tmp",
+           f"-L{HERE}", "-lfftbf", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("fftbf_bench build failed:\n" + r.stdout + r.stderr)
+    os.replace(BENCH + ".tmp", BENCH)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {BENCH}")
     return LIB
 
 
