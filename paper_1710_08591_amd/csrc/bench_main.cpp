@@ -2,7 +2,7 @@
 // for timing and hardware-counter runs on a chosen lattice.
 //
 //   fftbf_bench [--n-ns N] [--n-chan C] [--n-pol P] [--n-time T] [--keep K]
-//               [--steps S] [--warmup W]
+//               [--precision 0|1|2] [--steps S] [--warmup W]
 //
 // Voltages are device-resident and filled with a fixed byte pattern (the
 // kernel's memory traffic and arithmetic do not depend on the values); the
@@ -47,6 +47,7 @@ int main(int argc, char** argv) {
   const int keep = arg_int(argc, argv, "--keep", n_ns);
   const int steps = arg_int(argc, argv, "--steps", 10);
   const int warmup = arg_int(argc, argv, "--warmup", 2);
+  const int precision = arg_int(argc, argv, "--precision", BF_PREC_FP32);
   if (n_ns <= 0 || n_chan <= 0 || n_pol <= 0 || n_time <= 0 || keep < 0 || keep > 2 * n_ns || steps <= 0 ||
       warmup < 0) {
     std::fprintf(stderr, "invalid arguments\n");
@@ -62,7 +63,7 @@ int main(int argc, char** argv) {
   d.n_pol = n_pol;
   d.n_chan = n_chan;
   d.block = 16;
-  d.precision = BF_PREC_FP32;
+  d.precision = (bf_precision)precision;
   if (keep && keep < 2 * n_ns) {
     sel.resize((size_t)n_chan * keep);
     for (size_t i = 0; i < sel.size(); ++i) sel[i] = (int32_t)(2 * (i % keep));
@@ -97,9 +98,9 @@ int main(int argc, char** argv) {
   if (!ok_hip(hipEventRecord(e1, s), "hipEventRecord") || !ok_hip(hipEventSynchronize(e1), "hipEventSynchronize"))
     goto done;
   if (!ok_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) goto done;
-  std::printf("fftbf_bench: 4x%d lattice, %d chan, %d pol, %d samples, %d N-S beams kept: %.4f ms per launch, "
-              "%.4g antenna-samples/s\n",
-              n_ns, n_chan, n_pol, n_time, kept, ms / steps,
+  std::printf("fftbf_bench: 4x%d lattice, %d chan, %d pol, %d samples, %d N-S beams kept, precision %d: "
+              "%.4f ms per launch, %.4g antenna-samples/s\n",
+              n_ns, n_chan, n_pol, n_time, kept, precision, ms / steps,
               (double)n_time * n_chan * n_pol * 4 * n_ns / (ms / steps * 1e-3));
   rc = 0;
 done:
