@@ -21,8 +21,9 @@
  *     e:bf and e:fftbeamform without the 1/n_samp and unit factors).
  *   - Every device pointer is caller-owned device memory (the library never
  *     allocates or frees caller memory).  The plan owns its device tables.
- *   - `stream` is a hipStream_t (NULL = the null stream).  Every call other
- *     than plan creation and destruction is asynchronous on that stream.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  The creators and
+ *     destroyers (plans, regrid objects, servers) are synchronous; every
+ *     other call that takes a stream is asynchronous on it.
  *   - Arguments are validated before any launch; on a validation error
  *     nothing is written and nothing is launched.  No call aborts or throws.
  *     Device faults surface as BF_ERR_DEVICE.  bf_last_error() gives a
