@@ -355,6 +355,14 @@ def run_extras(dev) -> dict:
     ms = _time_launches(lambda: bf.form_tied_beams_v(plan, vt, 0, 256, d), 5, warmup=1)
     ex["tied_beams_v"] = {"workload": "4x16 lattice, 256 chan, 16384 samples, 64 pointings, |B|^2 over 16",
                           "kernel_ms": ms, "beam_samples_per_s": 64 * 256 * 16384 / (ms / 1e3)}
+    # the same tied beams interpolated from stored complex FFT beams (k_tied, FP32 vector ALUs)
+    beams = bf.beamform_fft(plan, vt, kind=bf.BF_OUT_COMPLEX)
+    ms_b = _time_launches(lambda: bf.form_tied_beams(plan, beams, 0, 256, d), 5, warmup=1)
+    ex["tied_beams_from_fft_beams"] = {"workload": "same, from the stored complex 4 x 32 FFT beams "
+                                                   f"({beams.numel() * 8 / 2**30:.0f} GiB)",
+                                       "kernel_ms": ms_b, "beam_samples_per_s": 64 * 256 * 16384 / (ms_b / 1e3),
+                                       "hbm_alg_gbs": beams.numel() * 8 / (ms_b / 1e3) / 1e9}
+    del beams
     plan.close()
     del vt
     torch.cuda.empty_cache()

@@ -93,3 +93,16 @@ def test_null_arguments():
 def test_accumulate_validation(args, status):
     lib = L.lib()
     assert lib.bf_accumulate_intensity(*args) == status
+
+
+def test_native_driver_rejects_bad_arguments():
+    """The C-ABI driver is built beside the library and validates its
+    arguments before touching the device."""
+    import os
+    import subprocess
+    exe = os.path.join(os.path.dirname(L.__file__), "fftbf_bench")
+    assert os.path.exists(exe)
+    r = subprocess.run([exe, "--n-ns", "-4"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "invalid arguments" in r.stderr
+    r = subprocess.run([exe, "--keep", "9999"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
