@@ -298,6 +298,124 @@ __device__ __forceinline__ float tied_block_mfma(const _Float16* lds_g, const Ti
   return v;
 }
 
+// As tied_block_mfma, with a power-of-two scale 2^ds[row] per sample row
+// (stored FFT beams have no fixed bound): the row's |Out|^2 is scaled back
+// by 2^-2(ds + 10) before the sum over the group's samples.
+__device__ __forceinline__ float tied_block_mfma_rows(const _Float16* lds_g, const TiedW& w, int lane,
+                                                      const int* ds) {
+  const int s = lane & 15, g = lane >> 4;
+  f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    const half8 ah = *reinterpret_cast<const half8*>(lds_g + (((0 * 8 + kb) * 4 + g) * 16 + s) * 8);
+    const half8 al = *reinterpret_cast<const half8*>(lds_g + (((1 * 8 + kb) * 4 + g) * 16 + s) * 8);
+    cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.rh[kb], cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.ih[kb], cim, 0, 0, 0);
+    cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, w.rh[kb], cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, w.ih[kb], cim, 0, 0, 0);
+    cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.rl[kb], cre, 0, 0, 0);
+    cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.il[kb], cim, 0, 0, 0);
+  }
+  float v = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    v = fmaf(fmaf(cre[i], cre[i], cim[i] * cim[i]), ldexpf(1.f, -2 * (ds[4 * g + i] + kV16Wscale)), v);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Tied beams from stored complex FFT beams of the 4 x 16 lattice (M_ns = 32)
+// on the matrix cores: the k_tied_v16 tile structure, with each wavefront
+// loading one group of 16 samples' beams instead of forming them.  A
+// sample's 128 complex beams (beam 32 e + A_ns, re|im) are exactly its k
+// vector; each lane loads 8 consecutive floats (k = 8 c .. 8 c + 7) with two
+// 16-byte loads, consecutive lanes consecutive chunks.  Each sample gets the
+// largest power-of-two scale keeping its beams below 2^15 (a max over the 32
+// lanes holding it).
+__global__ __launch_bounds__(256) void k_tied_b16(TiedArgs a) {
+  __shared__ __attribute__((aligned(16))) _Float16 lds_b[4 * 2 * 8 * 4 * 16 * 8];
+  __shared__ int lds_ds[4][16];
+  constexpr int kBuf = 2 * 8 * 4 * 16 * 8;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int n_ptile = (a.n_point + 63) / 64;
+  const int n_pg = a.pol_sum ? 1 : a.n_pol;
+  int wg = blockIdx.x;
+  const int ptile = wg % n_ptile;
+  const int trun = wg / n_ptile;
+  const int cs = blockIdx.y, pg = blockIdx.z;
+  const int chan = a.chan_lo + cs;
+  const int p = ptile * 64 + wave * 16 + (lane & 15);
+  const bool live = p < a.n_point;
+  const bool wave_live = ptile * 64 + wave * 16 < a.n_point;
+  const int pp = live ? p : a.n_point - 1;
+
+  TiedW w;
+  if (wave_live) tied_weights(a.dl[2 * chan] * a.dircos[2 * pp], a.dl[2 * chan + 1] * a.dircos[2 * pp + 1], lane >> 4, w);
+
+  const int pol_lo = a.pol_sum ? 0 : pg, pol_hi = a.pol_sum ? a.n_pol : pg + 1;
+  const int64_t span = (int64_t)a.block * kTiedBlocksPerWg;
+  const int64_t t0 = (int64_t)trun * span;
+  const int64_t t1 = t0 + span < a.n_time ? t0 + span : a.n_time;
+  const float* beams = reinterpret_cast<const float*>(a.beams);
+  const int kbg = lane & 31, kb = kbg >> 2, gq = kbg & 3;
+
+  float acc = 0.f;
+  for (int64_t tq = t0; tq < t1; tq += 4 * kV16TS) {
+    float accg[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int pol = pol_lo; pol < pol_hi; ++pol) {
+      const int64_t tw = tq + kV16TS * wave;
+      if (tw < t1) {
+        _Float16* lds_g = lds_b + wave * kBuf;
+#pragma unroll 2
+        for (int it = 0; it < 8; ++it) {
+          const int s = 2 * it + (lane >> 5);
+          const float* src = beams + (((tw + s) * a.n_chan + chan) * a.n_pol + pol) * 256 + 8 * kbg;
+          const f32x4 v0 = *reinterpret_cast<const f32x4*>(src);
+          const f32x4 v1 = *reinterpret_cast<const f32x4*>(src + 4);
+          float m = fmaxf(fmaxf(fmaxf(fabsf(v0[0]), fabsf(v0[1])), fmaxf(fabsf(v0[2]), fabsf(v0[3]))),
+                          fmaxf(fmaxf(fabsf(v1[0]), fabsf(v1[1])), fmaxf(fabsf(v1[2]), fabsf(v1[3]))));
+#pragma unroll
+          for (int off = 1; off < 32; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+          int e = 0;
+          if (m > 0.f) frexpf(32768.f / m, &e);
+          const int ds = m > 0.f ? e - 1 : 0;
+          if (kbg == 0) lds_ds[wave][s] = ds;
+          const float sc = ldexpf(1.f, ds);
+          uint32_t hw[4], lw[4];
+          split2(v0[0] * sc, v0[1] * sc, hw[0], lw[0]);
+          split2(v0[2] * sc, v0[3] * sc, hw[1], lw[1]);
+          split2(v1[0] * sc, v1[1] * sc, hw[2], lw[2]);
+          split2(v1[2] * sc, v1[3] * sc, hw[3], lw[3]);
+          *reinterpret_cast<half8*>(lds_g + (((0 * 8 + kb) * 4 + gq) * 16 + s) * 8) = __builtin_bit_cast(half8, hw);
+          *reinterpret_cast<half8*>(lds_g + (((1 * 8 + kb) * 4 + gq) * 16 + s) * 8) = __builtin_bit_cast(half8, lw);
+        }
+      }
+      __syncthreads();
+      if (wave_live) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          if (tq + kV16TS * g < t1) accg[g] += tied_block_mfma_rows(lds_b + g * kBuf, w, lane, lds_ds[g]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t tg = tq + kV16TS * g;
+      if (tg >= t1) break;
+      acc += accg[g];
+      if ((tg + kV16TS) % a.block == 0) {
+        if (live && lane < 16) {
+          const int64_t blk = tg / a.block;
+          float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
+          *o = acc;
+        }
+        acc = 0.f;
+      }
+    }
+  }
+}
+
 // Voltage variant on the matrix cores: workgroup = 4 wavefronts = 64
 // pointings.  Samples go in quads of 16-sample groups: wavefront w forms the
 // FFT beams of group w of the quad in its own LDS buffer, then every
@@ -433,6 +551,17 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
 
 hipError_t launch_tied(const TiedArgs& a, hipStream_t s) {
   const int n_ptile = (a.n_point + 63) / 64;
+  // the 4 x 16 lattice, intensities in blocks of 16k samples, 16-byte aligned beams: matrix cores
+  if (a.m_ns == 32 && a.n_ns == 16 && !a.complex_out && a.block % 16 == 0 &&
+      (reinterpret_cast<uintptr_t>(a.beams) & 15) == 0) {
+    const int64_t span_m = (int64_t)a.block * kTiedBlocksPerWg;
+    const int64_t n_run_m = (a.n_time + span_m - 1) / span_m;
+    const int n_pg_m = a.pol_sum ? 1 : a.n_pol;
+    if ((int64_t)n_ptile * n_run_m > 0x7FFFFFFF || a.n_chan_sub > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_tied_b16, dim3((unsigned)(n_ptile * n_run_m), (unsigned)a.n_chan_sub, (unsigned)n_pg_m),
+                       dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   const int64_t span = (int64_t)(a.complex_out ? 16 : a.block) * kTiedBlocksPerWg;
   const int64_t n_run = (a.n_time + span - 1) / span;
   const int n_pg = (a.pol_sum && !a.complex_out) ? 1 : a.n_pol;

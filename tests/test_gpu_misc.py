@@ -95,6 +95,37 @@ def test_tied_from_voltages_window_scaling(scale):
     plan.close()
 
 
+@pytest.mark.parametrize("scale", [1e4, 1e-4])
+def test_tied_from_fft_beams_scaling_and_fallback(scale):
+    """Tied beams from stored complex FFT beams on the matrix cores scale each
+    sample by its own power of two (stored beams have no fixed bound): beams
+    formed with a window far above or below 1 must still match the oracle;
+    an unaligned view of the beams takes the FP32 vector kernel and must give
+    the same beams to the FP32 bar."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=3, n_pol=2, n_time=96, seed=41, n_src=2, snr=20.0,
+                           dl=(0.4, 0.8))
+    v = sg.volts(w)
+    h = (sg.gaussian_taper(4, 16) * scale).astype(np.float32)
+    plan = plan_for(w, clamp=False)
+    beams = bf.beamform_fft(plan, torch.from_numpy(v).cuda(), taper=torch.from_numpy(h).cuda(),
+                            kind=bf.BF_OUT_COMPLEX)
+    dirs = np.concatenate([sg.pointings(70, 9), [[0.0, 0.0]]], axis=0)
+    d = torch.from_numpy(dirs).cuda()
+    got = bf.form_tied_beams(plan, beams, 0, 3, d).cpu().numpy()
+    ref = orc.tied_intensity(v, dirs, w.d_over_lambda(), 16, taper=h)
+    assert rel_err(got, ref) < TOL_FP32
+    # an 8-byte-aligned (not 16) copy of the beams: the vector-ALU path
+    buf = torch.empty(beams.numel() + 1, dtype=torch.complex64, device="cuda")
+    shifted = buf[1:].view(beams.shape)
+    shifted.copy_(beams)
+    assert shifted.data_ptr() % 16 == 8
+    got2 = bf.form_tied_beams(plan, shifted, 0, 3, d).cpu().numpy()
+    assert rel_err(got2, ref) < TOL_FP32
+    plan.close()
+
+
 def test_tied_on_grid_and_odd_counts():
     """On-grid pointings reproduce the FFT beams; ragged pointing tiles; channel subsets."""
     torch = _torch()
