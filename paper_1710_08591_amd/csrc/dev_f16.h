@@ -7,6 +7,14 @@
 namespace fftbf {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2 __attribute__((ext_vector_type(2)));
+
+// Signed 4-bit dot product of eight nibble pairs, added to the integer c.
+__device__ __forceinline__ int sdot8_acc(int a, int b, int c) {
+  int r;
+  asm("v_dot8_i32_i4 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
 
 // Two floats into FP16 high and low terms: hi = fp16(v) (round to nearest
 // even), lo = fp16(v - hi); the residual v - hi is exact in FP32 and comes

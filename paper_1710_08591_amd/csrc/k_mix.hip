@@ -367,19 +367,35 @@ __global__ __launch_bounds__(64) void k_mix256(MixArgs a) {
   for (int pol = pol_lo; pol < pol_hi; ++pol) {
     const uint32_t* src = a.volts + ((int64_t)chan * a.n_pol + pol) * N + pos0;
     const int64_t t0 = (int64_t)blk * a.block;
-    uint32_t cur[8], nxt[8];
+    // samples s, s + 1 and s + 2 in flight (two loads ahead of the arithmetic)
+    uint32_t buf[3][8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) cur[j] = __builtin_nontemporal_load(src + t0 * frame_stride + 16 * j);
+    for (int b = 0; b < 2; ++b)
+      if (b < a.block) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) buf[b][j] = __builtin_nontemporal_load(src + (t0 + b) * frame_stride + 16 * j);
+      }
     for (int s = 0; s < a.block; ++s) {
-      if (s + 1 < a.block) {
+      if (s + 2 < a.block) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) nxt[j] = __builtin_nontemporal_load(src + (t0 + s + 1) * frame_stride + 16 * j);
+        for (int j = 0; j < 8; ++j) buf[2][j] = __builtin_nontemporal_load(src + (t0 + s + 2) * frame_stride + 16 * j);
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
+        // E-W sum x (|x| <= 32) straight to FP16: the dot product starts from
+        // 0x6600, the FP16 pattern of 1536, whose unit step is 1, so the low
+        // half of 0x6600 + x is exactly FP16(1536 + x); two of them are packed
+        // and 1536 comes off in one packed FP16 subtraction (exact).
         half8 A1;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) A1[j] = (_Float16)(float)sdot8((int)cur[j], wts[e]);
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t lo = (uint32_t)sdot8_acc((int)buf[0][2 * j], wts[e], 0x6600);
+          const uint32_t hi = (uint32_t)sdot8_acc((int)buf[0][2 * j + 1], wts[e], 0x6600);
+          const half2 v = __builtin_bit_cast(half2, __builtin_amdgcn_perm(hi, lo, 0x05040100u)) -
+                          half2{(_Float16)1536.0f, (_Float16)1536.0f};
+          A1[2 * j] = v[0];
+          A1[2 * j + 1] = v[1];
+        }
         f32x4 y[2][2];
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt)
@@ -421,7 +437,9 @@ __global__ __launch_bounds__(64) void k_mix256(MixArgs a) {
         }
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) cur[j] = nxt[j];
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) buf[b][j] = buf[b + 1][j];
     }
   }
 
