@@ -66,7 +66,10 @@ def build(verbose: bool = True) -> str:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
     # the C-ABI driver (no Python), linked against the library next to it
-    cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), BENCH_SRC, "-o", BENCH + ".tmp",
+    # compiled as HIP for gfx950: the driver has a small kernel of its own (the voltage fill)
+    cmd = [HIPCC, "-x", "hip", f"--offload-arch={ARCH}", "-O2", "-std=c++17", "-Wno-unused-command-line-argument",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), BENCH_SRC, "-o", BENCH + ".tmp",
            f"-L{HERE}", "-lfftbf", "-Wl,-rpath,$ORIGIN"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -2,11 +2,13 @@
 // for timing and hardware-counter runs on a chosen lattice.
 //
 //   fftbf_bench [--n-ns N] [--n-chan C] [--n-pol P] [--n-time T] [--keep K]
-//               [--precision 0|1|2] [--steps S] [--warmup W]
+//               [--precision 0|1|2] [--steps S] [--warmup W] [--random 0|1]
 //
-// Voltages are device-resident and filled with a fixed byte pattern (the
-// kernel's memory traffic and arithmetic do not depend on the values); the
-// N-S clamp keeps K beams per channel (every other beam, 0 = no clamp).
+// Voltages are device-resident, filled with a fixed byte pattern (0x5A) or,
+// with --random 1, with hashed bytes: the memory traffic and the instruction
+// stream do not depend on the values, but the chip's power draw, and with it
+// the clock it holds, does.  The N-S clamp keeps K beams per channel (every
+// other beam, 0 = no clamp).
 // Prints the average time per launch from HIP events on the launch stream.
 #include <hip/hip_runtime.h>
 
@@ -31,6 +33,19 @@ bool ok_hip(hipError_t e, const char* what) {
   return false;
 }
 
+// bytes from a 32-bit integer hash of the dword index (deterministic)
+__global__ void k_fill_hash(uint32_t* v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t x = (uint32_t)i * 0x9E3779B1u + 0x7F4A7C15u;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    v[i] = x;
+  }
+}
+
 bool ok_bf(bf_status s, const char* what) {
   if (s == BF_OK) return true;
   std::fprintf(stderr, "%s: %s: %s\n", what, bf_status_string(s), bf_last_error());
@@ -48,8 +63,9 @@ int main(int argc, char** argv) {
   const int steps = arg_int(argc, argv, "--steps", 10);
   const int warmup = arg_int(argc, argv, "--warmup", 2);
   const int precision = arg_int(argc, argv, "--precision", BF_PREC_FP32);
+  const int random = arg_int(argc, argv, "--random", 0);
   if (n_ns <= 0 || n_chan <= 0 || n_pol <= 0 || n_time <= 0 || keep < 0 || keep > 2 * n_ns || steps <= 0 ||
-      warmup < 0) {
+      warmup < 0 || (random != 0 && random != 1)) {
     std::fprintf(stderr, "invalid arguments\n");
     return 2;
   }
@@ -83,7 +99,12 @@ int main(int argc, char** argv) {
   float ms = 0.f;
   if (!ok_hip(hipMalloc(&volts, in_bytes), "hipMalloc volts")) goto done;
   if (!ok_hip(hipMalloc(&out, out_bytes), "hipMalloc out")) goto done;
-  if (!ok_hip(hipMemset(volts, 0x5A, in_bytes), "hipMemset")) goto done;
+  if (random) {
+    hipLaunchKernelGGL(k_fill_hash, dim3(4096), dim3(256), 0, 0, static_cast<uint32_t*>(volts), in_bytes / 4);
+    if (!ok_hip(hipGetLastError(), "k_fill_hash") || !ok_hip(hipDeviceSynchronize(), "k_fill_hash")) goto done;
+  } else if (!ok_hip(hipMemset(volts, 0x5A, in_bytes), "hipMemset")) {
+    goto done;
+  }
   if (!ok_hip(hipStreamCreate(&s), "hipStreamCreate")) goto done;
   if (!ok_hip(hipEventCreate(&e0), "hipEventCreate") || !ok_hip(hipEventCreate(&e1), "hipEventCreate")) goto done;
   for (int i = 0; i < warmup; ++i)
@@ -99,9 +120,9 @@ int main(int argc, char** argv) {
     goto done;
   if (!ok_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) goto done;
   std::printf("fftbf_bench: 4x%d lattice, %d chan, %d pol, %d samples, %d N-S beams kept, precision %d: "
-              "%.4f ms per launch, %.4g antenna-samples/s\n",
+              "%.4f ms per launch, %.4g antenna-samples/s (%s voltages)\n",
               n_ns, n_chan, n_pol, n_time, kept, precision, ms / steps,
-              (double)n_time * n_chan * n_pol * 4 * n_ns / (ms / steps * 1e-3));
+              (double)n_time * n_chan * n_pol * 4 * n_ns / (ms / steps * 1e-3), random ? "hashed" : "constant");
   rc = 0;
 done:
   if (e0) (void)hipEventDestroy(e0);

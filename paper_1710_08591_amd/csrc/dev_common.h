@@ -217,6 +217,153 @@ __device__ __forceinline__ void padded_dft(cf* x /* in: [L], */, cf* y /* out: [
   }
 }
 
+// ---- scaled radix-2 decimation in time -----------------------------------
+// A twiddle in tangent form, W = f (1 + i t) or W = f (u + i), costs two fused
+// multiply-adds when its real factor f is left on the value: the value held
+// is then the true value divided by its scale f.  A DIT butterfly whose
+// operands carry scales s_top and s_bot costs no more than the plain one
+// (4 operations, or 6 with a non-trivial twiddle of its own) when the bottom
+// operand is multiplied by mu = f_W s_bot / s_top, f_W being the outer factor
+// of the butterfly's own tangent-form twiddle (1 for W = 1 or -i): both
+// outputs then carry s_top.  Every value of a group [S, S + SIZE) leaves a
+// stage with the scale of the group's first input, so after the last stage
+// all outputs carry the scale of input 0, which is 1 for every use here.
+constexpr bool tan_re_form(int k, int m) { return cx_abs(tw_re(k, m)) >= cx_abs(tw_im(k, m)); }
+constexpr double tan_outer(int k, int m) { return tan_re_form(k, m) ? tw_re(k, m) : tw_im(k, m); }
+constexpr bool dit_trivial(int j, int size) { return j == 0 || 4 * j == size; }
+
+// multipliers of a scaled G-point DIT: one per (stage, group) for its
+// trivial-twiddle butterflies, one more per non-trivial twiddle
+constexpr int dit_group_slots(int size) {
+  int n = 1;
+  for (int j = 0; j < size / 2; ++j) n += dit_trivial(j, size) ? 0 : 1;
+  return n;
+}
+constexpr int dit_slots(int g) {
+  int n = 0;
+  for (int z = 2; z <= g; z *= 2) n += (g / z) * dit_group_slots(z);
+  return n;
+}
+constexpr int dit_slot(int g, int size, int s, int j) {
+  int base = 0;
+  for (int z = 2; z < size; z *= 2) base += (g / z) * dit_group_slots(z);
+  base += (s / size) * dit_group_slots(size);
+  if (dit_trivial(j, size)) return base;
+  int n = 1;
+  for (int i = 0; i < j; ++i) n += dit_trivial(i, size) ? 0 : 1;
+  return base + n;
+}
+
+template <int J, int SIZE>
+__device__ __forceinline__ void bfly_mu(cf& a, cf& b, float mu) {
+  const cf t0 = a;
+  if constexpr (J == 0) {
+    a = cf{fmaf(mu, b.r, t0.r), fmaf(mu, b.i, t0.i)};
+    b = cf{fmaf(-mu, b.r, t0.r), fmaf(-mu, b.i, t0.i)};
+  } else if constexpr (4 * J == SIZE) {       // W = -i: W b = (b.i, -b.r)
+    a = cf{fmaf(mu, b.i, t0.r), fmaf(-mu, b.r, t0.i)};
+    b = cf{fmaf(-mu, b.i, t0.r), fmaf(mu, b.r, t0.i)};
+  } else {
+    cf bp;
+    if constexpr (tan_re_form(J, SIZE)) {
+      constexpr float t = float(tw_im(J, SIZE) / tw_re(J, SIZE));
+      bp = cf{fmaf(-t, b.i, b.r), fmaf(t, b.r, b.i)};
+    } else {
+      constexpr float u = float(tw_re(J, SIZE) / tw_im(J, SIZE));
+      bp = cf{fmaf(u, b.r, -b.i), fmaf(u, b.i, b.r)};
+    }
+    a = cf{fmaf(mu, bp.r, t0.r), fmaf(mu, bp.i, t0.i)};
+    b = cf{fmaf(-mu, bp.r, t0.r), fmaf(-mu, bp.i, t0.i)};
+  }
+}
+
+// scaled G-point DIT with run-time multipliers mu[dit_slot(...)]
+template <int G, int SIZE, int S, int J>
+struct DitRs {
+  static __device__ __forceinline__ void run(cf* y, const float* mu) {
+    bfly_mu<J, SIZE>(y[S + J], y[S + J + SIZE / 2], mu[dit_slot(G, SIZE, S, J)]);
+    if constexpr (J + 1 < SIZE / 2) DitRs<G, SIZE, S, J + 1>::run(y, mu);
+    else if constexpr (S + SIZE < G) DitRs<G, SIZE, S + SIZE, 0>::run(y, mu);
+    else if constexpr (SIZE < G) DitRs<G, 2 * SIZE, 0, 0>::run(y, mu);
+  }
+};
+template <int G>
+__device__ __forceinline__ void dit_rs(cf* x, const float* mu) {
+  cf y[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) y[i] = x[bitrev(i, G)];
+  DitRs<G, 2, 0, 0>::run(y, mu);
+#pragma unroll
+  for (int i = 0; i < G; ++i) x[i] = y[i];
+}
+
+// Zero-padded DFT as padded_dft, with the pre-twiddles x_j W_{2L}^j in
+// tangent form and their factors carried through the odd half's DIT as
+// compile-time multipliers (the outputs carry no scale).
+constexpr double pad_scale(int j, int l) { return (j == 0 || 2 * j == l) ? 1.0 : tan_outer(j, 2 * l); }
+constexpr double pad_mu(int l, int size, int s, int j) {
+  const double rho = pad_scale(bitrev(s + size / 2, l), l) / pad_scale(bitrev(s, l), l);
+  return dit_trivial(j, size) ? rho : rho * tan_outer(j, size);
+}
+template <int L, int SIZE, int S, int J>
+struct DitPad {
+  static __device__ __forceinline__ void run(cf* y) {
+    constexpr float mu = float(pad_mu(L, SIZE, S, J));
+    bfly_mu<J, SIZE>(y[S + J], y[S + J + SIZE / 2], mu);
+    if constexpr (J + 1 < SIZE / 2) DitPad<L, SIZE, S, J + 1>::run(y);
+    else if constexpr (S + SIZE < L) DitPad<L, SIZE, S + SIZE, 0>::run(y);
+    else if constexpr (SIZE < L) DitPad<L, 2 * SIZE, 0, 0>::run(y);
+  }
+};
+template <int L, int J>
+struct PadPreT {
+  static __device__ __forceinline__ void run(const cf* x, cf* xo) {
+    constexpr int M = 2 * L;
+    if constexpr (J == 0) {
+      xo[0] = x[0];
+    } else if constexpr (4 * J == M) {        // -i
+      xo[J] = cf{x[J].i, -x[J].r};
+    } else if constexpr (tan_re_form(J, M)) {
+      constexpr float t = float(tw_im(J, M) / tw_re(J, M));
+      xo[J] = cf{fmaf(-t, x[J].i, x[J].r), fmaf(t, x[J].r, x[J].i)};
+    } else {
+      constexpr float u = float(tw_re(J, M) / tw_im(J, M));
+      xo[J] = cf{fmaf(u, x[J].r, -x[J].i), fmaf(u, x[J].i, x[J].r)};
+    }
+    if constexpr (J + 1 < L) PadPreT<L, J + 1>::run(x, xo);
+  }
+};
+template <int L>
+__device__ __forceinline__ void padded_dft_t(cf* x /* in: [L], */, cf* y /* out: [2L] */) {
+  cf xo[L];
+  PadPreT<L, 0>::run(x, xo);
+  dit<L>(x);
+  if constexpr (L > 1) {
+    cf z[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) z[i] = xo[bitrev(i, L)];
+    DitPad<L, 2, 0, 0>::run(z);
+#pragma unroll
+    for (int i = 0; i < L; ++i) xo[i] = z[i];
+  }
+#pragma unroll
+  for (int m = 0; m < L; ++m) {
+    y[2 * m] = x[m];
+    y[2 * m + 1] = xo[m];
+  }
+}
+
+// Pass-1 columns k of the M = 2L x G transform that keep the whole twiddle
+// W_M^{a1 k}: those where some a1 < G has Re W = 0, which the tangent form
+// cannot hold.
+constexpr bool cmul_col(int k, int g, int m) {
+  for (int a1 = 0; a1 < g; ++a1) {
+    const int r = (a1 * k) % m;
+    if (4 * r == m || 4 * r == 3 * m) return true;
+  }
+  return false;
+}
+
 // Signed 4-bit dot product of the eight nibbles of a and b, accumulator 0
 // (the three-operand VOP3P form, so no register has to be zeroed first).
 __device__ __forceinline__ int sdot8(int a, int b) {

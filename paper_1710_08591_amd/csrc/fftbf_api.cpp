@@ -17,7 +17,8 @@ struct bf_plan {
   bf_plan_desc d;          // copy; pointer members are NULL
   int device = 0;
   int g = 0, l2 = 0;       // FP32 N-S split: m_ns = l2 * g
-  float2* tw = nullptr;    // [g][l2] FP32 twiddles W_M^{a1 k2}
+  float2* tw = nullptr;    // [g][l2] FP32 pass-1 twiddles W_M^{a1 k2} (tangent form)
+  float* mult = nullptr;   // [l2][slots] pass-2 multipliers
   int32_t* sel = nullptr;  // [n_chan][n_ns_keep] or null (identity)
   int fold = 1;            // cyclic co-adding: n_ns / m_ns when m_ns < n_ns
   int32_t* even = nullptr; // cyclic co-adding: [n_chan][m_ns] = 2 A (the even padded outputs)
@@ -51,6 +52,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 void free_plan(bf_plan* p) {
   if (!p) return;
   if (p->tw) (void)hipFree(p->tw);
+  if (p->mult) (void)hipFree(p->mult);
   if (p->sel) (void)hipFree(p->sel);
   if (p->even) (void)hipFree(p->even);
   if (p->dl) (void)hipFree(p->dl);
@@ -143,7 +145,8 @@ bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
   p->l2 = 2 * kn / p->g;
   hipStream_t s = nullptr;
   e = hipMalloc(&p->tw, sizeof(float2) * p->g * p->l2);
-  if (e == hipSuccess) e = fftbf::launch_twiddle_table(p->tw, p->g, p->l2, 2 * kn, s);
+  if (e == hipSuccess) e = hipMalloc(&p->mult, sizeof(float) * fftbf::twiddle_mult_count(p->g, p->l2));
+  if (e == hipSuccess) e = fftbf::launch_twiddle_table(p->tw, p->mult, p->g, p->l2, 2 * kn, s);
   if (e == hipSuccess && folded) {
     std::vector<int32_t> ev((size_t)d.n_chan * d.m_ns);
     for (size_t i = 0; i < ev.size(); ++i) ev[i] = 2 * (int32_t)(i % d.m_ns);
@@ -234,6 +237,7 @@ static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, in
     a.pol_iter = (n_pg == 1) ? d.n_pol : 1;
     a.block = d.block;
     a.tw = plan->tw;
+    a.mult = plan->mult;
     a.taper = taper;
     a.sel = plan->fold > 1 ? plan->even : plan->sel;
     a.n_keep = keep_of(d);

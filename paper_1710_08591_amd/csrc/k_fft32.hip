@@ -100,6 +100,17 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
   return (float)(int)__builtin_amdgcn_sbfe((int)d, shift, 4);
 }
 
+// row[k] = y[k] W_M^{a1 k} / Re W (tangent form, two fused multiply-adds), or
+// y[k] W_M^{a1 k} in the columns that keep whole twiddles
+template <int G, int M, int L2, int K>
+struct Pass1Tw {
+  static __device__ __forceinline__ void run(const cf* y, const float* t1, const cf* c1, cf* row) {
+    if constexpr (cmul_col(K, G, M)) row[K] = cmul(y[K], c1[K]);
+    else row[K] = cf{fmaf(-t1[K], y[K].i, y[K].r), fmaf(t1[K], y[K].r, y[K].i)};
+    if constexpr (K + 1 < L2) Pass1Tw<G, M, L2, K + 1>::run(y, t1, c1, row);
+  }
+};
+
 // TAPER: 0 none (E-W DFT as signed 4-bit dot products), 1 real per-antenna
 // weights h_a, 2 complex per-antenna gains g_a (float2), applied before the
 // E-W DFT, 3 none and the odd beams of the zero-padded 8-point E-W transform
@@ -159,13 +170,23 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
     __syncthreads();
   }
 
-  // pass-1 twiddles W_M^{a1 k2}, generated in FP64 at plan creation
-  cf tw1[L2];
+  // pass-1 twiddles W_M^{a1 k2}, generated in FP64 at plan creation, in
+  // tangent form W = Re W (1 + i t): only t is applied here, the factor
+  // Re W travels into pass 2's multipliers (columns where some lane has
+  // Re W = 0 keep whole twiddles)
+  constexpr int NSL = dit_slots(G);
+  float t1[L2];
+  cf c1[L2];
 #pragma unroll
   for (int k = 0; k < L2; ++k) {
     const float2 w = p.tw[a1 * L2 + k];
-    tw1[k] = cf{w.x, w.y};
+    t1[k] = w.x;
+    c1[k] = cf{w.x, w.y};
   }
+  // pass-2 multipliers of this lane's column k2 (the same for all its tasks)
+  float mu[NSL];
+#pragma unroll
+  for (int i = 0; i < NSL; ++i) mu[i] = p.mult[(lane % L2) * NSL + i];
 
   int wre = 0, wim = 0, wqr = 0, wqi = 0;
   TaperLane tl{};
@@ -262,11 +283,10 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 
       // ---- pass 1: zero-padded 2L-point DFT over a2, twiddle, to LDS ----
       cf y[L2];
-      padded_dft<L>(x, y);
+      padded_dft_t<L>(x, y);
       cf* row = &lds_y[((f1 * 4 + e1) * G + a1) * YS];
       row[0] = y[0];
-#pragma unroll
-      for (int k = 1; k < L2; ++k) row[k] = cmul(y[k], tw1[k]);
+      Pass1Tw<G, M, L2, 1>::run(y, t1, c1, row);
       __syncthreads();
 
       // ---- pass 2: G-point DFT over a1 ----
@@ -278,7 +298,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
         const cf* col = &lds_y[(f * 4 + e) * G * YS + k2];
 #pragma unroll
         for (int j = 0; j < G; ++j) z[j] = col[j * YS];
-        dit<G>(z);
+        dit_rs<G>(z, mu);
         if constexpr (CPLX) {
           // with FOLD > 1 only the even padded outputs 2A are beams (A < N)
           constexpr int MO = FOLD > 1 ? N : M, SO = FOLD > 1 ? 2 : 1;

@@ -7,16 +7,47 @@ namespace fftbf {
 
 namespace {
 
-// tw[a1][k2] = W_M^{a1 k2} = exp(-i 2 pi (a1 k2 mod M) / M): the index is
-// reduced in integers, the phase evaluated in FP64, then rounded to FP32.
-__global__ void k_twiddle(float2* tw, int g, int l2, int m) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g * l2) return;
-  const int a1 = i / l2, k2 = i % l2;
+// W_M^{a1 k2} = exp(-i 2 pi (a1 k2 mod M) / M): the index is reduced in
+// integers, the phase evaluated in FP64.
+__device__ void twiddle64(int a1, int k2, int m, double& c, double& s) {
   const long r = ((long)a1 * k2) % m;
-  double s, c;
   sincospi(-2.0 * (double)r / (double)m, &s, &c);
-  tw[i] = make_float2((float)c, (float)s);
+}
+
+// The factor that the tangent form of pass-1 twiddle (a1, k2) leaves on its
+// value: Re W, or 1 where the column keeps whole twiddles (and for k2 = 0).
+__device__ double pass1_scale(int a1, int k2, int g, int m) {
+  if (k2 == 0 || cmul_col(k2, g, m)) return 1.0;
+  double c, s;
+  twiddle64(a1, k2, m, c, s);
+  return c;
+}
+
+// Pass-1 table tw[a1][k2]: (t, 0) with W = Re W (1 + i t), or the whole
+// twiddle (Re W, Im W) in the columns that keep it.  Pass-2 table
+// mult[k2][slot]: the multipliers of the scaled G-point DIT over a1 whose
+// input a1 carries pass1_scale(a1, k2).  FP64 throughout, rounded to FP32.
+__global__ void k_twiddle(float2* tw, float* mult, int g, int l2, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g * l2) {
+    const int a1 = i / l2, k2 = i % l2;
+    double c, s;
+    twiddle64(a1, k2, m, c, s);
+    tw[i] = cmul_col(k2, g, m) ? make_float2((float)c, (float)s) : make_float2((float)(s / c), 0.f);
+  }
+  const int ns = dit_slots(g);
+  if (i < l2 * ns) {
+    const int k2 = i / ns, slot = i % ns;
+    for (int size = 2; size <= g; size *= 2)
+      for (int s0 = 0; s0 < g; s0 += size)
+        for (int j = 0; j < size / 2; ++j) {
+          if (dit_slot(g, size, s0, j) != slot) continue;
+          double mu = pass1_scale(bitrev(s0 + size / 2, g), k2, g, m) / pass1_scale(bitrev(s0, g), k2, g, m);
+          // the butterfly's own twiddle factor, from the same definition as its tangent
+          if (!dit_trivial(j, size)) mu *= tan_outer(j, size);
+          mult[i] = (float)mu;
+        }
+  }
 }
 
 // out[b][s] (+)= sum_{t in block b} |z[t][s]|^2 -- the block sum of the
@@ -48,9 +79,11 @@ __global__ __launch_bounds__(256) void k_accumulate(const float2* __restrict__ z
 
 }  // namespace
 
-hipError_t launch_twiddle_table(float2* tw, int g, int l2, int m, hipStream_t s) {
-  const int n = g * l2;
-  hipLaunchKernelGGL(k_twiddle, dim3((n + 255) / 256), dim3(256), 0, s, tw, g, l2, m);
+int twiddle_mult_count(int g, int l2) { return l2 * dit_slots(g); }
+
+hipError_t launch_twiddle_table(float2* tw, float* mult, int g, int l2, int m, hipStream_t s) {
+  const int n = g * l2 > l2 * dit_slots(g) ? g * l2 : l2 * dit_slots(g);
+  hipLaunchKernelGGL(k_twiddle, dim3((n + 255) / 256), dim3(256), 0, s, tw, mult, g, l2, m);
   return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@ struct Fft32Args {
   int n_pg;                // polarisation groups in the output (n_pol, or 1 when summed)
   int pol_iter;            // polarisations folded into one workgroup (1 or n_pol)
   int block;               // samples per intensity block (chunk for complex output)
-  const float2* tw;        // [G][2L] W_M^{a1 k2}
+  const float2* tw;        // [G][2L] pass-1 twiddles W_M^{a1 k2}: (t, 0) of W = Re W (1 + i t), or whole
+  const float* mult;       // [2L][dit_slots(G)] pass-2 multipliers (the factors Re W moved there)
   const float* taper;      // [n_ns][4] real weights, [n_ns][4][2] complex gains, or null
   const int32_t* sel;      // [n_chan][n_keep] or null (identity)
   int n_keep;
@@ -42,7 +43,8 @@ hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int6
                         hipStream_t s);
 
 // FP64 table generation on the device
-hipError_t launch_twiddle_table(float2* tw, int g, int l2, int m, hipStream_t s);
+int twiddle_mult_count(int g, int l2);
+hipError_t launch_twiddle_table(float2* tw, float* mult, int g, int l2, int m, hipStream_t s);
 
 // standalone |z|^2 block sums
 hipError_t launch_accumulate(const float2* z, int64_t n_time, int64_t n_series, int block,
