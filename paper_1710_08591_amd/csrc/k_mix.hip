@@ -6,17 +6,19 @@
 //
 //   C[sample][beam] += A[sample][k] * B[k][beam],   k = (re|im, a_ns)
 //
-// A holds the raw int4 voltages of one E-W column (exact in FP16 and in FP8
-// e4m3); B holds the realified DFT coefficients, split into terms of the
-// working precision that accumulate into the same FP32 accumulators:
+// A holds exact integers: in FP16 the E-W sums of one E-W beam (the 4-point
+// E-W DFT has twiddles +-1, +-i, so the sums are integers of magnitude at
+// most 32, formed by signed 4-bit dot products on the packed bytes); in FP8
+// the raw int4 voltages of one E-W column, because e4m3 does not hold every
+// E-W sum (17, for one).  B holds the realified DFT coefficients, split into
+// terms of the working precision that accumulate into the same FP32
+// accumulators:
 //   FP16:  W = hi + lo                               (two passes)
 //   FP8:   W = hi + 2^-5 lo1 + 2^-9 lo2              (three passes; the
 //          power-of-two factor moves onto the exact data operand so that
 //          every coefficient term sits in the normal range of e4m3)
-// The N-S transform goes first so that the data operand stays exact (E-W
-// sums reach +-32, not all of which e4m3 holds); the E-W 4-point DFT
-// (twiddles +-1, +-i) then runs in FP32 on the accumulators, in-lane,
-// followed by |B|^2 and the block sum.
+// FP16 then needs only |B|^2 and the block sum; FP8 runs the E-W 4-point
+// DFT in FP32 on the accumulators, in-lane, before them.
 //
 // v_mfma_f32_16x16x32_{f16,fp8_fp8} operands (lane l): A row = l % 16 (one
 // sample), B column = l % 16 (one beam), both holding k in
@@ -116,19 +118,47 @@ __device__ __forceinline__ f32x4 mfma(typename Mix<PREC>::op_t a, typename Mix<P
   else return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ half8 to_f16(const int* v) {
-  half8 h;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) h[j] = (_Float16)(float)v[j];
-  return h;
-}
-
 __device__ __forceinline__ long to_fp8(const int* v, float scale) {
   int w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0] * scale, (float)v[1] * scale, 0, false);
   w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2] * scale, (float)v[3] * scale, w0, true);
   int w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[4] * scale, (float)v[5] * scale, 0, false);
   w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[6] * scale, (float)v[7] * scale, w1, true);
   return (long)(unsigned)w0 | ((long)(unsigned)w1 << 32);
+}
+
+// dot8 weights for component comp (0 Re, 1 Im) of E-W beam e:
+// sum_q x_q (-i)^{e q}; nibble 2q+1 is Re(x_q), nibble 2q is Im(x_q)
+__device__ __forceinline__ int ew_dot_weights(int e, int comp) {
+  int wre = 0, wim = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = (e * q) & 3;
+    const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
+    if (k == 0) { wre |= 1 << sr;   wim |= 1 << si; }
+    if (k == 1) { wre |= 1 << si;   wim |= 0xF << sr; }
+    if (k == 2) { wre |= 0xF << sr; wim |= 0xF << si; }
+    if (k == 3) { wre |= 0xF << si; wim |= 1 << sr; }
+  }
+  return comp ? wim : wre;
+}
+
+// The E-W sums x (|x| <= 32) of eight dwords as FP16, without conversion
+// instructions: the dot product starts from 0x6600, the FP16 pattern of
+// 1536, whose unit step is 1, so the low half of 0x6600 + x is exactly
+// FP16(1536 + x); two are packed and 1536 comes off in one packed FP16
+// subtraction (exact).
+__device__ __forceinline__ half8 ew_sums_f16(const uint32_t* dw, int w) {
+  half8 A;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t lo = (uint32_t)sdot8_acc((int)dw[2 * j], w, 0x6600);
+    const uint32_t hi = (uint32_t)sdot8_acc((int)dw[2 * j + 1], w, 0x6600);
+    const half2 v = __builtin_bit_cast(half2, __builtin_amdgcn_perm(hi, lo, 0x05040100u)) -
+                    half2{(_Float16)1536.0f, (_Float16)1536.0f};
+    A[2 * j] = v[0];
+    A[2 * j + 1] = v[1];
+  }
+  return A;
 }
 
 template <int PREC>
@@ -157,6 +187,9 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
       for (int part = 0; part < 2; ++part) B[p][kt][part] = load_b<PREC>(a.mat, p, kt, part, lane);
 
   const int sh = (g >> 1) ? 0 : 4;            // real part: high nibble, imaginary: low
+  int wts[4];                                 // FP16: E-W dot8 weights of this lane's component
+#pragma unroll
+  for (int e = 0; e < 4; ++e) wts[e] = ew_dot_weights(e, g >> 1);
   const int pol_lo = (a.pol_iter == 1) ? pg : 0;
   const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
   const int keep = a.n_keep;
@@ -174,26 +207,40 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
         const uint4 d0 = fr[2 * (g & 1)], d1 = fr[2 * (g & 1) + 1];
         const uint32_t dw[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
 
-        f32x4 acc[4][2][2];
+        if constexpr (PREC == kPrecFp16) {
+          // FP16 holds the E-W sums exactly, so the E-W DFT goes first (as
+          // signed 4-bit dot products on the packed bytes) and each E-W
+          // beam's N-S products land straight in its |B|^2
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          int v[8];
+          for (int e = 0; e < 4; ++e) {
+            const half8 A = ew_sums_f16(dw, wts[e]);
+            f32x4 y[2][2];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = (int)__builtin_amdgcn_sbfe((int)dw[j], 8 * c + sh, 4);
+            for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-          for (int kt = 0; kt < 2; ++kt)
+              for (int part = 0; part < 2; ++part) {
+                y[kt][part] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int part = 0; part < 2; ++part) acc[c][kt][part] = f32x4{0.f, 0.f, 0.f, 0.f};
-          if constexpr (PREC == kPrecFp16) {
-            const op_t A = to_f16(v);
+                for (int p = 0; p < P; ++p) y[kt][part] = mfma<PREC>(A, B[p][kt][part], y[kt][part]);
+              }
 #pragma unroll
-            for (int p = 0; p < P; ++p)
+            for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-              for (int kt = 0; kt < 2; ++kt)
+              for (int i = 0; i < 4; ++i) ia[e][kt] = cnorm_acc(cf{y[kt][0][i], y[kt][1][i]}, ia[e][kt]);
+          }
+        } else {
+          // FP8: the raw int4 of each E-W column (e4m3-exact) through the N-S
+          // products, then the E-W 4-point DFT in FP32 on the accumulators
+          f32x4 acc[4][2][2];
 #pragma unroll
-                for (int part = 0; part < 2; ++part)
-                  acc[c][kt][part] = mfma<PREC>(A, B[p][kt][part], acc[c][kt][part]);
-          } else {
+          for (int c = 0; c < 4; ++c) {
+            int v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (int)__builtin_amdgcn_sbfe((int)dw[j], 8 * c + sh, 4);
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+              for (int part = 0; part < 2; ++part) acc[c][kt][part] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int p = 0; p < P; ++p) {
               const op_t A = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
@@ -204,23 +251,23 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
                   acc[c][kt][part] = mfma<PREC>(A, B[p][kt][part], acc[c][kt][part]);
             }
           }
-        }
 
-        // E-W 4-point DFT across the four columns, |B|^2, sum of the lane's 4 samples
+          // E-W 4-point DFT across the four columns, |B|^2, sum of the lane's 4 samples
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
+          for (int kt = 0; kt < 2; ++kt) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float y0r = acc[0][kt][0][i], y0i = acc[0][kt][1][i];
-            const float y1r = acc[1][kt][0][i], y1i = acc[1][kt][1][i];
-            const float y2r = acc[2][kt][0][i], y2i = acc[2][kt][1][i];
-            const float y3r = acc[3][kt][0][i], y3i = acc[3][kt][1][i];
-            const float s02r = y0r + y2r, s02i = y0i + y2i, d02r = y0r - y2r, d02i = y0i - y2i;
-            const float s13r = y1r + y3r, s13i = y1i + y3i, d13r = y1r - y3r, d13i = y1i - y3i;
-            ia[0][kt] = cnorm_acc(cf{s02r + s13r, s02i + s13i}, ia[0][kt]);
-            ia[2][kt] = cnorm_acc(cf{s02r - s13r, s02i - s13i}, ia[2][kt]);
-            ia[1][kt] = cnorm_acc(cf{d02r + d13i, d02i - d13r}, ia[1][kt]);
-            ia[3][kt] = cnorm_acc(cf{d02r - d13i, d02i + d13r}, ia[3][kt]);
+            for (int i = 0; i < 4; ++i) {
+              const float y0r = acc[0][kt][0][i], y0i = acc[0][kt][1][i];
+              const float y1r = acc[1][kt][0][i], y1i = acc[1][kt][1][i];
+              const float y2r = acc[2][kt][0][i], y2i = acc[2][kt][1][i];
+              const float y3r = acc[3][kt][0][i], y3i = acc[3][kt][1][i];
+              const float s02r = y0r + y2r, s02i = y0i + y2i, d02r = y0r - y2r, d02i = y0i - y2i;
+              const float s13r = y1r + y3r, s13i = y1i + y3i, d13r = y1r - y3r, d13i = y1i - y3i;
+              ia[0][kt] = cnorm_acc(cf{s02r + s13r, s02i + s13i}, ia[0][kt]);
+              ia[2][kt] = cnorm_acc(cf{s02r - s13r, s02i - s13i}, ia[2][kt]);
+              ia[1][kt] = cnorm_acc(cf{d02r + d13i, d02i - d13r}, ia[1][kt]);
+              ia[3][kt] = cnorm_acc(cf{d02r - d13i, d02i + d13r}, ia[3][kt]);
+            }
           }
         }
       }
@@ -337,19 +384,7 @@ __global__ __launch_bounds__(64) void k_mix256(MixArgs a) {
   // E-W dot8 weights for this lane's component (g >> 1) of each E-W beam
   int wts[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    int wre = 0, wim = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = (e * q) & 3;
-      const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
-      if (k == 0) { wre |= 1 << sr;   wim |= 1 << si; }
-      if (k == 1) { wre |= 1 << si;   wim |= 0xF << sr; }
-      if (k == 2) { wre |= 0xF << sr; wim |= 0xF << si; }
-      if (k == 3) { wre |= 0xF << si; wim |= 1 << sr; }
-    }
-    wts[e] = (g >> 1) ? wim : wre;
-  }
+  for (int e = 0; e < 4; ++e) wts[e] = ew_dot_weights(e, g >> 1);
 
   float acc[4][2][4];
 #pragma unroll
@@ -382,20 +417,7 @@ __global__ __launch_bounds__(64) void k_mix256(MixArgs a) {
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        // E-W sum x (|x| <= 32) straight to FP16: the dot product starts from
-        // 0x6600, the FP16 pattern of 1536, whose unit step is 1, so the low
-        // half of 0x6600 + x is exactly FP16(1536 + x); two of them are packed
-        // and 1536 comes off in one packed FP16 subtraction (exact).
-        half8 A1;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t lo = (uint32_t)sdot8_acc((int)buf[0][2 * j], wts[e], 0x6600);
-          const uint32_t hi = (uint32_t)sdot8_acc((int)buf[0][2 * j + 1], wts[e], 0x6600);
-          const half2 v = __builtin_bit_cast(half2, __builtin_amdgcn_perm(hi, lo, 0x05040100u)) -
-                          half2{(_Float16)1536.0f, (_Float16)1536.0f};
-          A1[2 * j] = v[0];
-          A1[2 * j + 1] = v[1];
-        }
+        const half8 A1 = ew_sums_f16(buf[0], wts[e]);
         f32x4 y[2][2];
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt)
