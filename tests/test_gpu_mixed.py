@@ -119,3 +119,62 @@ def test_mix256_extremes_and_point_source():
     got = _run(w, v, 1, clamp=False)
     ref = orc.beamform_fft(v, 4, 512, 16)
     assert np.max(np.abs(got - ref)) / ref.max() < TOL_MIXED
+
+
+def test_mix256_c2_full_size_sampled():
+    """The CHIME-shaped workload at full size through the FP16-MFMA plan, in the
+    launch configuration the benchmark times; sampled (block, channel,
+    polarisation) outputs against the oracle.  The bar is the mixed-precision
+    1e-3; the three-product stage 2 is meant to stay within the FP32 bar
+    (1e-5) as well, which the second assertion holds it to."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c2")
+    plan = plan_for(w, precision=1)
+    v = sg.volts(w, backend="torch", device="cuda")
+    out = bf.beamform_fft(plan, v)
+    torch.cuda.synchronize()
+    assert out.shape == (1024, 256, 2, 4, 256)
+    rng = np.random.default_rng(1)
+    picks = [(0, 0, 0), (1023, 255, 1)] + [tuple(int(x) for x in (rng.integers(1024), rng.integers(256),
+                                                                  rng.integers(2))) for _ in range(4)]
+    sel = w.ns_select()
+    worst = 0.0
+    for blk, c, p in picks:
+        vs = sg.volts(w, blk * 16, 16, chans=[c], pols=[p])
+        ref = orc.beamform_fft(vs, w.m_ew, w.m_ns, 16)[0, 0, 0][:, sel[c]]
+        worst = max(worst, rel_err(out[blk, c, p].cpu().numpy(), ref))
+    print(f"4x256 FP16 MFMA, full size: max rel beam-power error {worst:.3e}")
+    assert worst < TOL_MIXED
+    assert worst < 1e-5
+    plan.close()
+    del v, out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_lattice4x16_scaled_full_size_sampled(prec):
+    """The scaled 4 x 16 workload of the precision comparison (2 pol, 256
+    channels, 16384 samples) at full size, each precision in the launch
+    configuration the benchmark times; sampled outputs against the oracle."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.Workload("lattice4x16_scaled", 4, 16, 256, 2, 16384, 4, 32, 16, 6,
+                    src_dircos=((0.3, -0.2), (-0.7, 0.5)), src_snr=(10.0, 30.0), dl_lo=0.4, dl_hi=0.8)
+    v = sg.volts(w, backend="torch", device="cuda")
+    plan = bf.Plan(n_ew=4, n_ns=16, n_pol=2, n_chan=256, block=16, precision=prec)
+    out = bf.beamform_fft(plan, v)
+    torch.cuda.synchronize()
+    assert out.shape == (1024, 256, 2, 4, 32)
+    rng = np.random.default_rng(2)
+    picks = [(0, 0, 0), (1023, 255, 1)] + [tuple(int(x) for x in (rng.integers(1024), rng.integers(256),
+                                                                  rng.integers(2))) for _ in range(4)]
+    worst = 0.0
+    for blk, c, p in picks:
+        vs = sg.volts(w, blk * 16, 16, chans=[c], pols=[p])
+        ref = orc.beamform_fft(vs, 4, 32, 16)[0, 0, 0]
+        worst = max(worst, rel_err(out[blk, c, p].cpu().numpy(), ref))
+    assert worst < (1e-5 if prec < 2 else TOL_MIXED), worst
+    plan.close()
+    del v, out
+    torch.cuda.empty_cache()
