@@ -104,3 +104,29 @@ def test_gains_errors():
         bf.beamform_fft(mixed, v, gains=torch.ones((16, 4), dtype=torch.complex64, device="cuda"))
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
     mixed.close()
+
+
+def test_gains_c2_full_size_sampled():
+    """Complex per-antenna gains on the CHIME-shaped workload at full size, in
+    the launch configuration the benchmark times; sampled outputs against the
+    oracle with the same gains."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c2")
+    plan = plan_for(w)
+    grng = np.random.default_rng(17)
+    gains = np.exp(0.1 * grng.normal(size=(w.n_ns, w.n_ew)) + 0.1j * grng.normal(size=(w.n_ns, w.n_ew)))
+    g64 = gains.astype(np.complex64)
+    v = sg.volts(w, backend="torch", device="cuda")
+    out = bf.beamform_fft(plan, v, gains=torch.from_numpy(g64).cuda())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    sel = w.ns_select()
+    for blk, c, p in [(0, 0, 0), (1023, 255, 1)] + [tuple(int(x) for x in (rng.integers(1024), rng.integers(256),
+                                                                          rng.integers(2))) for _ in range(3)]:
+        vs = sg.volts(w, blk * 16, 16, chans=[c], pols=[p])
+        ref = orc.beamform_fft(vs, w.m_ew, w.m_ns, 16, taper=g64.astype(np.complex128))[0, 0, 0][:, sel[c]]
+        assert rel_err(out[blk, c, p].cpu().numpy(), ref) < TOL_FP32
+    plan.close()
+    del v, out
+    torch.cuda.empty_cache()

@@ -150,3 +150,32 @@ def test_tied_on_grid_and_odd_counts():
     gv = bf.form_tied_beams_v(plan, vt, 2, 3, d).cpu().numpy()
     assert rel_err(gv, ref) < TOL_FP32
     plan.close()
+
+
+def test_tied_beams_benchmark_configuration_sampled():
+    """Tied beams as the benchmark times them: the 4 x 16 lattice, 256
+    channels, 16384 samples, 64 pointings, from voltages and from stored
+    complex FFT beams; sampled (block, channel) outputs against the oracle's
+    direct phased sums."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c5")
+    vt = sg.volts(w, 0, 16384, backend="torch", device="cuda")
+    plan = bf.Plan(n_ew=4, n_ns=16, n_chan=256, block=16, d_over_lambda=w.d_over_lambda())
+    dirs = sg.pointings(64, 11)
+    d = torch.from_numpy(dirs).cuda()
+    got_v = bf.form_tied_beams_v(plan, vt, 0, 256, d)
+    beams = bf.beamform_fft(plan, vt, kind=bf.BF_OUT_COMPLEX)
+    got_b = bf.form_tied_beams(plan, beams, 0, 256, d)
+    torch.cuda.synchronize()
+    assert got_v.shape == got_b.shape == (1024, 256, 1, 64)
+    rng = np.random.default_rng(4)
+    dl = w.d_over_lambda()
+    for blk, c in [(0, 0), (1023, 255)] + [(int(rng.integers(1024)), int(rng.integers(256))) for _ in range(3)]:
+        vs = sg.volts(w, blk * 16, 16, chans=[c])
+        ref = orc.tied_intensity(vs, dirs, dl, 16, chans=[c])[0, 0, 0]
+        assert rel_err(got_v[blk, c, 0].cpu().numpy(), ref) < TOL_FP32
+        assert rel_err(got_b[blk, c, 0].cpu().numpy(), ref) < TOL_FP32
+    plan.close()
+    del vt, beams, got_v, got_b
+    torch.cuda.empty_cache()
