@@ -312,3 +312,45 @@ def test_regrid_c2_shape_sampled():
     plan.close()
     del fft_i, got
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n_taps", [0, 5])
+def test_windowed_regrid_c2_shape_sampled(n_taps):
+    """The optimally windowed beams (half-sine window) on the CHIME-shaped
+    lattice at full size, dense and with the compact 5-tap kernel, in the
+    launch configuration the benchmark times; sampled (block, channel)
+    outputs against the oracle's windowed weights applied to its own FFT-beam
+    intensities."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c2")
+    plan = bf.Plan(n_ew=4, n_ns=256, n_chan=256, n_pol=2, block=16, d_over_lambda=w.d_over_lambda())
+    st = np.linspace(-0.95, 0.95, 256)
+    h = np.sin(np.pi * (np.arange(256) + 1) / 257)
+    rg = bf.Regrid(plan, st, window=h, n_taps=n_taps)
+    v = sg.volts(w, backend="torch", device="cuda")
+    fft_i = bf.beamform_fft(plan, v)
+    del v
+    got = rg(fft_i)
+    torch.cuda.synchronize()
+    assert got.shape == (1024, 256, 2, 4, 256)
+    rng = np.random.default_rng(6)
+    dl = w.d_over_lambda()
+    for blk, c in [(0, 0), (1023, 255)] + [(int(rng.integers(1024)), int(rng.integers(256))) for _ in range(2)]:
+        b = orc.beamform_fft(sg.volts(w, blk * 16, 16, chans=[c]), 4, 512, 16)[0, 0]
+        ys = dl[c, 1] * st
+        full = orc.optimal_window_weights(h, 512, ys)
+        W = np.zeros_like(full)
+        for t, y in enumerate(ys):
+            if n_taps:
+                first, taps = orc.compact_taps(full[t], y, n_taps)
+                W[t, (first + np.arange(n_taps)) % 512] = taps
+            else:
+                W[t] = full[t]
+        ref = orc.regrid_intensity(b, W)
+        scale = orc.regrid_intensity(b, np.abs(W))
+        assert np.all(np.abs(got[blk, c].cpu().numpy() - ref) <= TOL_FP32 * scale)
+    rg.close()
+    plan.close()
+    del fft_i, got
+    torch.cuda.empty_cache()
