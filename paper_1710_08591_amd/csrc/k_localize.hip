@@ -13,7 +13,8 @@
 // stops, when b_p <= 0 or when it would leave one beam spacing around the
 // starting beam.
 //
-// Each 64-lane wavefront takes the argmax of its rows in turn (coalesced,
+// Each 64-lane wavefront takes the argmax of its rows (lane l holds the PER
+// consecutive beams from l PER on, all rows' loads in flight together,
 // deterministic lowest-index tie break), then runs the Newton phase for all
 // of them at once: with windows of up to 16 beams, four rows per wavefront
 // in 16-lane groups (else one row per wavefront).  Lane j < K of a group owns
@@ -43,8 +44,9 @@ __device__ __forceinline__ void dirichlet(double u, int N, double& d, double& dd
   double s, c, S, C;
   sincospi(e, &s, &c);
   sincospi(Nd * e, &S, &C);
-  d = S / s;
-  dd = kPiD * (Nd * C * s - S * c) / (s * s);
+  const double inv = 1.0 / s;                     // one division: dD = pi (N C - D c) / s
+  d = S * inv;
+  dd = kPiD * (Nd * C - d * c) * inv;
 }
 
 // sum over the G-lane group of this lane (G a power of two <= 64)
@@ -57,7 +59,9 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // G lanes per row in the Newton phase: G = 16 packs 4 rows per wavefront
 // (windows of up to 16 beams), G = 64 gives a row the whole wavefront.
-template <int G>
+// PER = max(1, m / 64) beams per lane in the argmax; VEC loads them as
+// 16-byte vectors (PER >= 4 and a 16-byte aligned input).
+template <int G, int PER, bool VEC>
 __global__ __launch_bounds__(256) void k_localize(LocArgs a) {
   constexpr int RW = 64 / G;                       // rows per wavefront
   const int lane = threadIdx.x & 63;
@@ -65,20 +69,43 @@ __global__ __launch_bounds__(256) void k_localize(LocArgs a) {
   if (row0 >= a.n_rows) return;                    // wave-uniform
   const int m = a.m;
 
-  // argmax of each of the wave's rows, whole wavefront per row (coalesced)
+  // every row's loads first, so that the wave waits for memory once
+  float v[RW][PER];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const bool ok = row0 + r < a.n_rows;           // wave-uniform
+    const float* x = a.in + (ok ? row0 + r : row0) * m + lane * PER;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int q = 0; q < PER / 4; ++q) {
+        const float4 f = reinterpret_cast<const float4*>(x)[q];
+        v[r][4 * q] = f.x;
+        v[r][4 * q + 1] = f.y;
+        v[r][4 * q + 2] = f.z;
+        v[r][4 * q + 3] = f.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        v[r][i] = -INFINITY;
+        if (lane * PER + i < m) v[r][i] = x[i];     // lanes past a short row load nothing
+      }
+    }
+  }
+
+  // argmax of each of the wave's rows
   int a0v[RW];
 #pragma unroll
   for (int r = 0; r < RW; ++r) {
     a0v[r] = 0;
     if (row0 + r >= a.n_rows) continue;            // wave-uniform
-    const float* x = a.in + (row0 + r) * m;
     float best = -INFINITY;
     int bi = 0x7FFFFFFF;
-    for (int A = lane; A < m; A += 64) {
-      const float v = x[A];
-      if (v > best) {
-        best = v;
-        bi = A;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (lane * PER + i < m && v[r][i] > best) {
+        best = v[r][i];
+        bi = lane * PER + i;
       }
     }
 #pragma unroll
@@ -138,6 +165,35 @@ __global__ __launch_bounds__(256) void k_localize(LocArgs a) {
 
 }  // namespace
 
+namespace {
+
+template <int G, int PER>
+void launch_loc(const LocArgs& a, bool vec, unsigned nb, hipStream_t s) {
+  if constexpr (PER >= 4) {
+    if (vec) {
+      hipLaunchKernelGGL((k_localize<G, PER, true>), dim3(nb), dim3(256), 0, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_localize<G, PER, false>), dim3(nb), dim3(256), 0, s, a);
+}
+
+template <int G>
+hipError_t launch_loc_g(const LocArgs& a, unsigned nb, hipStream_t s) {
+  const bool vec = (reinterpret_cast<uintptr_t>(a.in) % 16) == 0;
+  switch (a.m) {
+    case 32:
+    case 64: launch_loc<G, 1>(a, vec, nb, s); break;
+    case 128: launch_loc<G, 2>(a, vec, nb, s); break;
+    case 256: launch_loc<G, 4>(a, vec, nb, s); break;
+    case 512: launch_loc<G, 8>(a, vec, nb, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_localize(const LocArgs& a, hipStream_t s) {
   if (a.n_rows <= 0) return hipSuccess;
   if (a.n_window < 1 || a.n_window > 64 || a.n_window > a.m) return hipErrorInvalidValue;
@@ -145,11 +201,7 @@ hipError_t launch_localize(const LocArgs& a, hipStream_t s) {
   const int64_t waves = packed ? (a.n_rows + 3) / 4 : a.n_rows;
   const int64_t nb = (waves + 3) / 4;
   if (nb > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
-  if (packed)
-    hipLaunchKernelGGL(k_localize<16>, dim3((unsigned)nb), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_localize<64>, dim3((unsigned)nb), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return packed ? launch_loc_g<16>(a, (unsigned)nb, s) : launch_loc_g<64>(a, (unsigned)nb, s);
 }
 
 }  // namespace fftbf
