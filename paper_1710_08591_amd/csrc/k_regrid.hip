@@ -214,13 +214,19 @@ __global__ __launch_bounds__(256, 2) void k_regrid(RegridArgs a) {
 }
 
 // Compact-kernel regridding (K taps per target): an HBM-bound gather.  A
-// 256-thread workgroup stages 16 rows (all M beams) of one channel in LDS with
+// 256-thread workgroup stages kTapRows rows (all M beams) of one channel in LDS with
 // float4 loads; each thread then takes targets t = tid, tid + 256, ... and
-// forms sum_j tw[j][t] I[row][(first[t] + j) mod M] for the 16 rows, writing
+// forms sum_j tw[j][t] I[row][(first[t] + j) mod M] for those rows, writing
 // each row's targets contiguously.
+// rows per workgroup of the compact-tap kernel: 8 rows (16 KB of LDS at
+// M = 512) let ten workgroups share a compute unit; 16 rows (32 KB, five
+// workgroups) left the loads of one workgroup less to overlap with and
+// were 10% slower at the CHIME shape, 4 rows no faster
+constexpr int kTapRows = 8;
+
 template <int K>
 __global__ __launch_bounds__(256) void k_regrid_taps(RegridArgs a) {
-  constexpr int RT = 16;
+  constexpr int RT = kTapRows;
   __shared__ __attribute__((aligned(16))) float lds[RT * 512];
   const int tid = threadIdx.x, chan = blockIdx.y;
   const int m = a.m_ns, mv = m >> 2;
@@ -310,7 +316,7 @@ hipError_t launch_regrid(const RegridArgs& a_in, hipStream_t s) {
   a.rows_per_chan = (int)rows;
   if (a.n_taps > 0) {
     if (a.n_taps > kRegridMaxTaps || a.m_ns > 512) return hipErrorNotSupported;
-    const dim3 g((unsigned)((rows + 15) / 16), (unsigned)a.n_chan);
+    const dim3 g((unsigned)((rows + kTapRows - 1) / kTapRows), (unsigned)a.n_chan);
     switch (a.n_taps) {
       case 1: hipLaunchKernelGGL(k_regrid_taps<1>, g, dim3(256), 0, s, a); break;
       case 2: hipLaunchKernelGGL(k_regrid_taps<2>, g, dim3(256), 0, s, a); break;
