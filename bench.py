@@ -157,6 +157,17 @@ def cpu_baseline(seconds: float = 15.0, checks: "OracleChecks | None" = None):
     return rec
 
 
+def _leg(fn, *args):
+    """Run one side measurement; an exception in it is reported in its record
+    instead of taking the headline line down with it."""
+    try:
+        return fn(*args)
+    except Exception as e:
+        import traceback
+        traceback.print_exc(file=sys.stderr)
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def _time_launches(fn, n: int, warmup: int = 2) -> float:
     """Average milliseconds of fn() (one launch on the current stream)."""
     import torch
@@ -400,7 +411,7 @@ def run_extras(dev, checks: OracleChecks) -> dict:
     plan.close()
     del vt
     torch.cuda.empty_cache()
-    ex["serving"] = run_serving(dev)
+    ex["serving"] = _leg(run_serving, dev)
     return ex
 
 
@@ -621,10 +632,10 @@ def main():
 
     chime_mixed = chime_regrid = None
     if not args.skip_extras:
-        chime_mixed = run_chime_mixed(dev, w, volts, ms_avg, checks)
+        chime_mixed = _leg(run_chime_mixed, dev, w, volts, ms_avg, checks)
         del out
         torch.cuda.empty_cache()
-        chime_regrid = run_chime_regrid(dev, w, volts, checks)
+        chime_regrid = _leg(run_chime_regrid, dev, w, volts, checks)
     else:
         del out
     del volts
@@ -632,10 +643,10 @@ def main():
     torch.cuda.empty_cache()
     if not args.skip_extras:
         rec["extras"] = {"chime_fp16_mfma": chime_mixed, "chime_regrid": chime_regrid}
-        rec["extras"].update(run_extras(dev, checks))
+        rec["extras"].update(_leg(run_extras, dev, checks))
         torch.cuda.empty_cache()
     if not args.skip_cpu:
-        rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds, checks)
+        rec["cpu_baseline"] = _leg(cpu_baseline, args.cpu_seconds, checks)
     print(json.dumps(rec))
 
 
