@@ -100,6 +100,15 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
   return (float)(int)__builtin_amdgcn_sbfe((int)d, shift, 4);
 }
 
+// The workgroup is one wavefront, and a wavefront's LDS operations execute
+// in the order it issues them: between the transpose's writes and reads only
+// the compiler's order has to be kept, with no wait for the writes to land.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // row[k] = y[k] W_M^{a1 k} / Re W (tangent form, two fused multiply-adds), or
 // y[k] W_M^{a1 k} in the columns that keep whole twiddles
 template <int G, int M, int L2, int K>
@@ -287,17 +296,26 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
       cf* row = &lds_y[((f1 * 4 + e1) * G + a1) * YS];
       row[0] = y[0];
       Pass1Tw<G, M, L2, 1>::run(y, t1, c1, row);
-      __syncthreads();
+      wave_lds_sync();
 
       // ---- pass 2: G-point DFT over a1 ----
+      // every task's column is read before any is transformed, so the later
+      // tasks' reads overlap the first task's arithmetic
+      cf zz[R2][G];
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
         const int q = lane + 64 * r;
         const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
-        cf z[G];
         const cf* col = &lds_y[(f * 4 + e) * G * YS + k2];
 #pragma unroll
-        for (int j = 0; j < G; ++j) z[j] = col[j * YS];
+        for (int j = 0; j < G; ++j) zz[r][j] = col[j * YS];
+      }
+      __builtin_amdgcn_sched_barrier(0);     // keep every read ahead of the transforms
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int q = lane + 64 * r;
+        const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+        cf* z = zz[r];
         dit_rs<G>(z, mu);
         if constexpr (CPLX) {
           // with FOLD > 1 only the even padded outputs 2A are beams (A < N)
@@ -317,7 +335,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
           for (int k1 = 0; k1 < G; ++k1) acc[r][k1] = cnorm_acc(z[k1], acc[r][k1]);
         }
       }
-      __syncthreads();
+      wave_lds_sync();
 
 #pragma unroll
       for (int j = 0; j < LA; ++j) cur[j] = nxt[j];
