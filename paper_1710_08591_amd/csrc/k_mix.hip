@@ -230,37 +230,36 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
           }
         } else {
           // FP8: the raw int4 of each E-W column (e4m3-exact) through the N-S
-          // products, then the E-W 4-point DFT in FP32 on the accumulators
-          f32x4 acc[4][2][2];
+          // products, then the E-W 4-point DFT in FP32 on the accumulators;
+          // one beam tile (kt) at a time, so that only half of the
+          // accumulators are live
+          op_t A[4][P];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             int v[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) v[j] = (int)__builtin_amdgcn_sbfe((int)dw[j], 8 * c + sh, 4);
 #pragma unroll
-            for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-              for (int part = 0; part < 2; ++part) acc[c][kt][part] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-              const op_t A = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
-#pragma unroll
-              for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-                for (int part = 0; part < 2; ++part)
-                  acc[c][kt][part] = mfma<PREC>(A, B[p][kt][part], acc[c][kt][part]);
-            }
+            for (int p = 0; p < P; ++p) A[c][p] = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
           }
-
-          // E-W 4-point DFT across the four columns, |B|^2, sum of the lane's 4 samples
 #pragma unroll
           for (int kt = 0; kt < 2; ++kt) {
+            f32x4 acc[4][2];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+              for (int part = 0; part < 2; ++part) {
+                acc[c][part] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int p = 0; p < P; ++p) acc[c][part] = mfma<PREC>(A[c][p], B[p][kt][part], acc[c][part]);
+              }
+            // E-W 4-point DFT across the four columns, |B|^2, sum of the lane's 4 samples
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float y0r = acc[0][kt][0][i], y0i = acc[0][kt][1][i];
-              const float y1r = acc[1][kt][0][i], y1i = acc[1][kt][1][i];
-              const float y2r = acc[2][kt][0][i], y2i = acc[2][kt][1][i];
-              const float y3r = acc[3][kt][0][i], y3i = acc[3][kt][1][i];
+              const float y0r = acc[0][0][i], y0i = acc[0][1][i];
+              const float y1r = acc[1][0][i], y1i = acc[1][1][i];
+              const float y2r = acc[2][0][i], y2i = acc[2][1][i];
+              const float y3r = acc[3][0][i], y3i = acc[3][1][i];
               const float s02r = y0r + y2r, s02i = y0i + y2i, d02r = y0r - y2r, d02i = y0i - y2i;
               const float s13r = y1r + y3r, s13i = y1i + y3i, d13r = y1r - y3r, d13i = y1i - y3i;
               ia[0][kt] = cnorm_acc(cf{s02r + s13r, s02i + s13i}, ia[0][kt]);
