@@ -214,19 +214,18 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const half8 A = ew_sums_f16(dw, wts[e]);
-            f32x4 y[2][2];
 #pragma unroll
-            for (int kt = 0; kt < 2; ++kt)
+            for (int kt = 0; kt < 2; ++kt) {
+              f32x4 y[2];
 #pragma unroll
               for (int part = 0; part < 2; ++part) {
-                y[kt][part] = f32x4{0.f, 0.f, 0.f, 0.f};
+                y[part] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int p = 0; p < P; ++p) y[kt][part] = mfma<PREC>(A, B[p][kt][part], y[kt][part]);
+                for (int p = 0; p < P; ++p) y[part] = mfma<PREC>(A, B[p][kt][part], y[part]);
               }
 #pragma unroll
-            for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) ia[e][kt] = cnorm_acc(cf{y[kt][0][i], y[kt][1][i]}, ia[e][kt]);
+              for (int i = 0; i < 4; ++i) ia[e][kt] = cnorm_acc(cf{y[0][i], y[1][i]}, ia[e][kt]);
+            }
           }
         } else {
           // FP8: the raw int4 of each E-W column (e4m3-exact) through the N-S
