@@ -236,6 +236,40 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
     return rec
 
 
+def run_library_fft_comparator(dev, w, volts, plan, fp32_ms: float, chunk: int = 1024) -> dict:
+    """Context only, not the product: the same CHIME-shaped step written with
+    torch's FFT (rocFFT) and elementwise ops on the resident voltages -- decode
+    to complex64, 2-D FFT with the N-S axis zero-padded to M, |B|^2, block sum,
+    clamp -- timed on a slice of the samples and scaled to the whole workload."""
+    import torch
+    sel = torch.from_numpy(w.ns_select()).to(dev).long()                  # [chan][keep]
+    v = volts[:chunk]
+
+    def step():
+        b = v.to(torch.int16)
+        re = ((b >> 4) ^ 8) - 8                                          # signed high nibble
+        im = ((b & 15) ^ 8) - 8                                          # signed low nibble
+        x = torch.complex(re.float(), im.float())                        # [T][chan][pol][ns][ew]
+        f = torch.fft.fft2(x, s=(w.m_ns, w.m_ew), dim=(-2, -1))          # [T][chan][pol][M][4]
+        i = (f.real ** 2 + f.imag ** 2).view(chunk // w.block, w.block, *f.shape[1:]).sum(1)
+        i = i.transpose(-1, -2)                                          # [blk][chan][pol][4][M]
+        idx = sel.view(1, w.n_chan, 1, 1, w.keep).expand(i.shape[0], w.n_chan, w.n_pol, w.m_ew, w.keep)
+        return torch.gather(i, -1, idx) / float(w.n_ew * w.n_ns)
+
+    ms = _time_launches(step, 3, warmup=1)
+    full_ms = ms * (w.n_time / chunk)
+    import paper_1710_08591_amd as bf
+    ours = bf.beamform_fft(plan, v)
+    theirs = step()
+    agree = float(((ours.double() - theirs.double()).abs() / theirs.double()).max())
+    return {"what": "context only: torch.fft (rocFFT) and torch elementwise ops, not the product",
+            "slice": f"{chunk} of {w.n_time} samples, all channels and pols; time scaled by {w.n_time // chunk}",
+            "ms_per_slice": ms, "ms_scaled_to_workload": full_ms,
+            "antenna_samples_per_s": w.antenna_samples / (full_ms / 1e3),
+            "fused_kernel_speedup": full_ms / fp32_ms,
+            "max_rel_diff_vs_fused_kernel_on_slice": agree}
+
+
 def run_chime_regrid(dev, w, volts, checks: OracleChecks, n_target: int = 256) -> dict:
     """All 512 N-S FFT beams of the resident CHIME-shaped voltages (no clamp),
     regridded to n_target achromatic N-S steering angles (eq. e:bp_max_arbitrary)."""
@@ -630,19 +664,23 @@ def main():
                    v=sg.volts(w, blk * w.block, w.block, chans=[c], pols=[p]), m_ew=w.m_ew, m_ns=w.m_ns,
                    index=(0, 0, 0), sel=sel[c])
 
-    chime_mixed = chime_regrid = None
+    chime_mixed = chime_regrid = library_fft = None
     if not args.skip_extras:
         chime_mixed = _leg(run_chime_mixed, dev, w, volts, ms_avg, checks)
         del out
         torch.cuda.empty_cache()
         chime_regrid = _leg(run_chime_regrid, dev, w, volts, checks)
+        torch.cuda.empty_cache()
+        library_fft = _leg(run_library_fft_comparator, dev, w, volts, plan, ms_avg)
+        torch.cuda.empty_cache()
     else:
         del out
     del volts
     plan.close()
     torch.cuda.empty_cache()
     if not args.skip_extras:
-        rec["extras"] = {"chime_fp16_mfma": chime_mixed, "chime_regrid": chime_regrid}
+        rec["extras"] = {"chime_fp16_mfma": chime_mixed, "chime_regrid": chime_regrid,
+                         "library_fft_comparator": library_fft}
         rec["extras"].update(_leg(run_extras, dev, checks))
         torch.cuda.empty_cache()
     if not args.skip_cpu:
