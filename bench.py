@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-# FP32 VALU issue ceiling without packed FP32 instructions (which this build
+# FP32 VALU issue ceiling without packed FP32 instructions (which this library
 # does not emit): 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP32_UNPACKED_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -561,7 +561,7 @@ def main():
                     help="only run a plain 1 GiB device copy (counter calibration for HBM bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the path shards by frequency channel "
+        print(json.dumps({"error": "this benchmark runs on one GPU; the path shards by frequency channel "
                                    "across GPUs but no multi-GPU run is provided", "n_gpus": args.gpus}))
         sys.exit(2)
 
