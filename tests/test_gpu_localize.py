@@ -146,3 +146,24 @@ def test_localize_c2_shape_sampled():
     plan.close()
     del fft_i
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n_ns", [16, 64, 128, 256])
+def test_localize_unaligned_input_matches_aligned(n_ns):
+    """An intensity view that is 4- but not 16-byte aligned takes the scalar
+    loads of the argmax (the aligned one takes 16-byte vectors when a lane
+    holds at least four beams); both must give identical estimates."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=3, n_pol=2, n_time=16 * 5, seed=n_ns + 3, n_src=3,
+                           snr=20.0, dl=(0.4, 0.8))
+    plan = _plan(bf, w)
+    x = torch.from_numpy(orc.beamform_fft(sg.volts(w), 4, 2 * n_ns, 16).astype(np.float32)).cuda()
+    st_a, pk_a = bf.localize(plan, x, n_window=10, n_iter=6)
+    buf = torch.empty(x.numel() + 1, dtype=torch.float32, device="cuda")
+    xv = buf[1:].view(x.shape)
+    xv.copy_(x)
+    assert xv.data_ptr() % 16 == 4
+    st_b, pk_b = bf.localize(plan, xv, n_window=10, n_iter=6)
+    assert torch.equal(st_a, st_b) and torch.equal(pk_a, pk_b)
+    plan.close()
