@@ -354,3 +354,32 @@ def test_windowed_regrid_c2_shape_sampled(n_taps):
     plan.close()
     del fft_i, got
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n_blk", [1, 3, 11])
+def test_regrid_compact_taps_ragged_row_tiles(n_blk):
+    """Compact taps on pol-summed intensities, so a channel has 4 n_blk rows:
+    1, 3 and 11 blocks leave the last workgroup's row tile short (4, 12 and
+    44 rows against tiles of 8)."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    n_ns, k = 64, 5
+    m = 2 * n_ns
+    w, x = _oracle_case(n_ns, n_blk, seed=13)
+    xs = x.sum(axis=2)                                            # [blk][chan][4][M]: the pol-summed rows
+    plan = bf.Plan(n_ew=4, n_ns=n_ns, n_chan=3, n_pol=2, block=16, pol_sum=True, d_over_lambda=w.d_over_lambda())
+    st = _targets(70, 5)
+    rg = bf.Regrid(plan, st, n_taps=k)
+    got = rg(torch.from_numpy(np.ascontiguousarray(xs)).cuda()).cpu().numpy()
+    assert got.shape == (n_blk, 3, 4, 70)
+    x64 = xs.astype(np.float64)
+    for c in range(3):
+        ys = w.d_over_lambda()[c, 1] * st
+        for t, y in enumerate(ys):
+            first, taps = orc.compact_taps(orc.regrid_weights_paper(n_ns, m, y), y, k)
+            idx = (first + np.arange(k)) % m
+            ref = x64[:, c][..., idx] @ taps
+            scale = np.abs(x64[:, c][..., idx]) @ np.abs(taps)
+            assert np.all(np.abs(got[:, c, :, t] - ref) <= 1e-6 * scale)
+    rg.close()
+    plan.close()
