@@ -642,6 +642,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
                      "kernel": "k_fft32<256,16>", "kernel_ms": ms_avg,
+                     "kernel_ms_p10_p50_p90": [float(np.percentile(kern_ms, q)) for q in (10, 50, 90)],
                      "unpacked_fp32_issue_peak": FP32_UNPACKED_ISSUE_TFLOPS,
                      "frac_of_unpacked_issue_peak": achieved_tflops / FP32_UNPACKED_ISSUE_TFLOPS,
                      "flop_per_antenna_sample": flops / ant_samples,
