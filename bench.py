@@ -42,10 +42,16 @@ def flops_per_frame(n_ns: int, m_ns: int, keep: int, m_ew: int = 4) -> float:
 
 
 def kernel_source_hash(*names) -> str:
+    """Hash of the kernel sources with comments and whitespace removed, so a
+    profile stays matched to the code it measured across comment edits."""
+    import re
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(ROOT, "paper_1710_08591_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1710_08591_amd", "csrc", n), encoding="utf-8") as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -16,7 +16,10 @@
 //       pass 2 (lanes over (frame, e, k2)): G-point DFT over a1, in registers.
 //     The in-register DFTs are radix-2 decimation in time with each
 //     compile-time twiddle factored into a tangent form (6 operations per
-//     twiddled butterfly instead of 8).
+//     twiddled butterfly instead of 8).  The pass-1 twiddle and the
+//     zero-padding pre-twiddles take the same form (2 operations instead of
+//     4): their real factors stay on the values and are absorbed by the
+//     multipliers of the following butterflies, so no output carries one.
 //   * the E-W 4-point DFT has twiddles in {1, -i, -1, +i}: without a window
 //     it is two signed 4-bit dot products per N-S position (v_dot8_i32_i4
 //     straight on the packed voltage bytes, exact integers); with a window
