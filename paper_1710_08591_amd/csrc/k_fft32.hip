@@ -216,132 +216,145 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   const int n_it = p.block / F;
   const int64_t frame_stride = (int64_t)p.n_chan * p.n_pol * NA;  // dwords per sample
 
+  // Frames of this block that hold data: all of them, except in a short
+  // final block (complex output with n_time not a multiple of the block).
+  // Every load is unconditional: a lane whose frame lies past the data
+  // re-reads its last valid one (its results are never stored), and the
+  // prefetch of the final pass re-reads the current frames, so no load
+  // sits under an execution mask and the next frames stay in flight while
+  // the current ones are transformed.
+  const int n_valid = (int)((p.n_time - t_base) < p.block ? (p.n_time - t_base) : p.block);
+  const int64_t f_step = (int64_t)F * frame_stride;
+
   for (int pi = 0; pi < p.pol_iter; ++pi) {
     const int pol = (p.pol_iter == 1) ? pg : pi;
     const uint32_t* src = p.volts + ((int64_t)chan * p.n_pol + pol) * NA + a1;
 
-    uint32_t cur[LA], nxt[LA];
-    {
-      const int64_t t = t_base + f1;
-      const bool ok = t < p.n_time;
+    // two frame buffers in turn: while one group of frames is transformed,
+    // the next one is in flight in the other
+    uint32_t b0[LA], b1[LA];
+    const uint32_t* p0 = src + (t_base + (f1 < n_valid ? f1 : n_valid - 1)) * frame_stride;
+    const uint32_t* p1 = p0;
 #pragma unroll
-      for (int j = 0; j < LA; ++j) cur[j] = ok ? __builtin_nontemporal_load(src + t * frame_stride + G * j) : 0u;
-    }
+    for (int j = 0; j < LA; ++j) b0[j] = __builtin_nontemporal_load(p0 + G * j);
+    // this lane's frame in pass k follows its frame in pass k - 1, unless
+    // that is past the data (then the lane re-reads its last valid frame)
+    auto next = [&](const uint32_t* q, int k) { return (k * F + f1 < n_valid) ? q + f_step : q; };
 
-    for (int it = 0; it < n_it; ++it) {
-      const int64_t t = t_base + (int64_t)it * F + f1;
-      // prefetch the next group of frames
-      if (it + 1 < n_it) {
-        const int64_t tn = t + F;
-        const bool okn = tn < p.n_time;
+    auto frame_pass = [&](const uint32_t (&cur)[LA], int it) {
+        // ---- E-W DFT for this lane's beam e1 at N-S positions a1 + G j ----
+        // (with FOLD > 1, summed over the antennas a1 + G j + N f, f < FOLD)
+        cf x[L];
 #pragma unroll
-        for (int j = 0; j < LA; ++j) nxt[j] = okn ? __builtin_nontemporal_load(src + tn * frame_stride + G * j) : 0u;
-      }
-
-      // ---- E-W DFT for this lane's beam e1 at N-S positions a1 + G j ----
-      // (with FOLD > 1, summed over the antennas a1 + G j + N f, f < FOLD)
-      cf x[L];
+        for (int j = 0; j < L; ++j) {
+          if constexpr (TAPER == 0) {
+            int sr = 0, si = 0;
 #pragma unroll
-      for (int j = 0; j < L; ++j) {
-        if constexpr (TAPER == 0) {
-          int sr = 0, si = 0;
-#pragma unroll
-          for (int f = 0; f < FOLD; ++f) {
-            sr += sdot8((int)cur[j + L * f], wre);
-            si += sdot8((int)cur[j + L * f], wim);
-          }
-          x[j] = cf{(float)sr, (float)si};
-        } else if constexpr (TAPER == 3) {
-          constexpr float kS = 0.70710678118654752f;
-          const uint32_t d = cur[j];
-          const float pr = (float)sdot8((int)d, wre), pi = (float)sdot8((int)d, wim);
-          const float qr = (float)sdot8((int)d, wqr), qi = (float)sdot8((int)d, wqi);
-          x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pi)};
-        } else if constexpr (TAPER == 2) {
-          // z_q = g_q x_q, then the E-W twiddle (-i)^{e q} as a swap and signs
-          const uint32_t d = cur[j];
-          const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
-          const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
-          const float gr[4] = {g01.x, g01.z, g23.x, g23.z}, gi[4] = {g01.y, g01.w, g23.y, g23.w};
-          float re = 0.f, im = 0.f;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
-            const float zr = fmaf(xr, gr[q], -(xi * gi[q]));
-            const float zi = fmaf(xr, gi[q], xi * gr[q]);
-            re = fmaf(tl.sre[q], tl.swap[q] ? zi : zr, re);
-            im = fmaf(tl.sim[q], tl.swap[q] ? zr : zi, im);
-          }
-          x[j] = cf{re, im};
-        } else {
-          float re = 0.f, im = 0.f;
-#pragma unroll
-          for (int f = 0; f < FOLD; ++f) {
-            const uint32_t d = cur[j + L * f];
-            const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * (j + L * f)) * 4]);
-            const float hq[4] = {h.x, h.y, h.z, h.w};
+            for (int f = 0; f < FOLD; ++f) {
+              sr += sdot8((int)cur[j + L * f], wre);
+              si += sdot8((int)cur[j + L * f], wim);
+            }
+            x[j] = cf{(float)sr, (float)si};
+          } else if constexpr (TAPER == 3) {
+            constexpr float kS = 0.70710678118654752f;
+            const uint32_t d = cur[j];
+            const float pr = (float)sdot8((int)d, wre), pi = (float)sdot8((int)d, wim);
+            const float qr = (float)sdot8((int)d, wqr), qi = (float)sdot8((int)d, wqi);
+            x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pi)};
+          } else if constexpr (TAPER == 2) {
+            // z_q = g_q x_q, then the E-W twiddle (-i)^{e q} as a swap and signs
+            const uint32_t d = cur[j];
+            const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
+            const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
+            const float gr[4] = {g01.x, g01.z, g23.x, g23.z}, gi[4] = {g01.y, g01.w, g23.y, g23.w};
+            float re = 0.f, im = 0.f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
-              const float u = tl.swap[q] ? xi : xr;
-              const float v = tl.swap[q] ? xr : xi;
-              re = fmaf(tl.sre[q] * hq[q], u, re);
-              im = fmaf(tl.sim[q] * hq[q], v, im);
+              const float zr = fmaf(xr, gr[q], -(xi * gi[q]));
+              const float zi = fmaf(xr, gi[q], xi * gr[q]);
+              re = fmaf(tl.sre[q], tl.swap[q] ? zi : zr, re);
+              im = fmaf(tl.sim[q], tl.swap[q] ? zr : zi, im);
             }
-          }
-          x[j] = cf{re, im};
-        }
-      }
-
-      // ---- pass 1: zero-padded 2L-point DFT over a2, twiddle, to LDS ----
-      cf y[L2];
-      padded_dft_t<L>(x, y);
-      cf* row = &lds_y[((f1 * 4 + e1) * G + a1) * YS];
-      row[0] = y[0];
-      Pass1Tw<G, M, L2, 1>::run(y, t1, c1, row);
-      wave_lds_sync();
-
-      // ---- pass 2: G-point DFT over a1 ----
-      // every task's column is read before any is transformed, so the later
-      // tasks' reads overlap the first task's arithmetic
-      cf zz[R2][G];
+            x[j] = cf{re, im};
+          } else {
+            float re = 0.f, im = 0.f;
 #pragma unroll
-      for (int r = 0; r < R2; ++r) {
-        const int q = lane + 64 * r;
-        const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
-        const cf* col = &lds_y[(f * 4 + e) * G * YS + k2];
+            for (int f = 0; f < FOLD; ++f) {
+              const uint32_t d = cur[j + L * f];
+              const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * (j + L * f)) * 4]);
+              const float hq[4] = {h.x, h.y, h.z, h.w};
 #pragma unroll
-        for (int j = 0; j < G; ++j) zz[r][j] = col[j * YS];
-      }
-      __builtin_amdgcn_sched_barrier(0);     // keep every read ahead of the transforms
-#pragma unroll
-      for (int r = 0; r < R2; ++r) {
-        const int q = lane + 64 * r;
-        const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
-        cf* z = zz[r];
-        dit_rs<G>(z, mu);
-        if constexpr (CPLX) {
-          // with FOLD > 1 only the even padded outputs 2A are beams (A < N)
-          constexpr int MO = FOLD > 1 ? N : M, SO = FOLD > 1 ? 2 : 1;
-          const int64_t tt = t_base + (int64_t)it * F + f;
-          if (tt < p.n_time && (k2 % SO) == 0) {
-            float2* o = static_cast<float2*>(p.out) +
-                        (((tt * p.n_chan + chan) * p.n_pol + pg) * p.ew_rows + e * p.ew_mul + p.ew_off) * MO + k2 / SO;
-#pragma unroll
-            for (int k1 = 0; k1 < G; ++k1) {
-              const cf b = z[k1];
-              o[(L2 / SO) * k1] = make_float2(b.r * p.norm, b.i * p.norm);
+              for (int q = 0; q < 4; ++q) {
+                const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
+                const float u = tl.swap[q] ? xi : xr;
+                const float v = tl.swap[q] ? xr : xi;
+                re = fmaf(tl.sre[q] * hq[q], u, re);
+                im = fmaf(tl.sim[q] * hq[q], v, im);
+              }
             }
+            x[j] = cf{re, im};
           }
-        } else {
-#pragma unroll
-          for (int k1 = 0; k1 < G; ++k1) acc[r][k1] = cnorm_acc(z[k1], acc[r][k1]);
         }
-      }
-      wave_lds_sync();
 
+        // ---- pass 1: zero-padded 2L-point DFT over a2, twiddle, to LDS ----
+        cf y[L2];
+        padded_dft_t<L>(x, y);
+        cf* row = &lds_y[((f1 * 4 + e1) * G + a1) * YS];
+        row[0] = y[0];
+        Pass1Tw<G, M, L2, 1>::run(y, t1, c1, row);
+        wave_lds_sync();
+
+        // ---- pass 2: G-point DFT over a1 ----
+        // every task's column is read before any is transformed, so the later
+        // tasks' reads overlap the first task's arithmetic
+        cf zz[R2][G];
 #pragma unroll
-      for (int j = 0; j < LA; ++j) cur[j] = nxt[j];
+        for (int r = 0; r < R2; ++r) {
+          const int q = lane + 64 * r;
+          const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+          const cf* col = &lds_y[(f * 4 + e) * G * YS + k2];
+#pragma unroll
+          for (int j = 0; j < G; ++j) zz[r][j] = col[j * YS];
+        }
+        __builtin_amdgcn_sched_barrier(0);     // keep every read ahead of the transforms
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          const int q = lane + 64 * r;
+          const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+          cf* z = zz[r];
+          dit_rs<G>(z, mu);
+          if constexpr (CPLX) {
+            // with FOLD > 1 only the even padded outputs 2A are beams (A < N)
+            constexpr int MO = FOLD > 1 ? N : M, SO = FOLD > 1 ? 2 : 1;
+            const int64_t tt = t_base + (int64_t)it * F + f;
+            if (tt < p.n_time && (k2 % SO) == 0) {
+              float2* o = static_cast<float2*>(p.out) +
+                          (((tt * p.n_chan + chan) * p.n_pol + pg) * p.ew_rows + e * p.ew_mul + p.ew_off) * MO + k2 / SO;
+#pragma unroll
+              for (int k1 = 0; k1 < G; ++k1) {
+                const cf b = z[k1];
+                o[(L2 / SO) * k1] = make_float2(b.r * p.norm, b.i * p.norm);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int k1 = 0; k1 < G; ++k1) acc[r][k1] = cnorm_acc(z[k1], acc[r][k1]);
+          }
+        }
+        wave_lds_sync();
+    };
+
+    for (int it = 0; it < n_it; it += 2) {
+      p1 = next(p0, it + 1);
+#pragma unroll
+      for (int j = 0; j < LA; ++j) b1[j] = __builtin_nontemporal_load(p1 + G * j);
+      frame_pass(b0, it);
+      if (it + 1 == n_it) break;
+      p0 = next(p1, it + 2);
+#pragma unroll
+      for (int j = 0; j < LA; ++j) b0[j] = __builtin_nontemporal_load(p0 + G * j);
+      frame_pass(b1, it + 1);
     }
   }
 

@@ -92,13 +92,14 @@ def test_clamp_and_pol_sum():
     assert rel_err(ps, refp) < TOL_FP32
 
 
-@pytest.mark.parametrize("n_time", [1, 5, 17, 64])
-def test_complex_beams_ragged(n_time):
-    """Complex FFT beams for every sample, including a ragged last chunk."""
-    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=2, n_pol=2, n_time=n_time, seed=3)
+@pytest.mark.parametrize("n_ns,n_time", [(16, 1), (16, 5), (16, 17), (16, 64), (256, 3), (256, 21)])
+def test_complex_beams_ragged(n_ns, n_time):
+    """Complex FFT beams for every sample, including a ragged last chunk
+    (four frames side by side per wavefront at n_ns = 16, one at 256)."""
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=2, n_pol=2, n_time=n_time, seed=3)
     v = sg.volts(w)
     got = _run(w, v, kind=1, clamp=False)
-    ref = orc.fft_beams(orc.decode_int4(v), 4, 32)
+    ref = orc.fft_beams(orc.decode_int4(v), 4, 2 * n_ns)
     assert got.shape == ref.shape
     assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-6
 
@@ -107,6 +108,24 @@ def test_block_sizes():
     w = sg.custom_workload(n_ew=4, n_ns=32, n_chan=1, n_pol=1, n_time=96, seed=4)
     v = sg.volts(w)
     for blk in (4, 8, 32, 48):
+        got = _run(w, v, clamp=False, block=blk)
+        ref = orc.beamform_fft(v, w.m_ew, w.m_ns, blk)
+        assert rel_err(got, ref) < TOL_FP32
+
+
+def test_block_sizes_odd_pass_count():
+    """Blocks whose frames take an odd number of passes (four frames side by
+    side per pass at n_ns = 16: blocks of 4, 12 and 20 samples), and short
+    blocks at n_ns = 256 (one frame per pass)."""
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=2, n_pol=2, n_time=120, seed=14)
+    v = sg.volts(w)
+    for blk in (4, 12, 20):
+        got = _run(w, v, clamp=False, block=blk)
+        ref = orc.beamform_fft(v, w.m_ew, w.m_ns, blk)
+        assert rel_err(got, ref) < TOL_FP32
+    w = sg.custom_workload(n_ew=4, n_ns=256, n_chan=1, n_pol=1, n_time=24, seed=15)
+    v = sg.volts(w)
+    for blk in (4, 12):
         got = _run(w, v, clamp=False, block=blk)
         ref = orc.beamform_fft(v, w.m_ew, w.m_ns, blk)
         assert rel_err(got, ref) < TOL_FP32
