@@ -28,7 +28,9 @@ FP16_MFMA_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 # FP32 VALU issue ceiling without packed FP32 instructions (which this library
 # does not emit): 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-FP32_UNPACKED_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+N_SIMD = 256 * 4
+CLOCK_HZ = 2.4e9
+FP32_UNPACKED_ISSUE_TFLOPS = N_SIMD * 16 * 2 * CLOCK_HZ / 1e12
 
 
 def flops_per_frame(n_ns: int, m_ns: int, keep: int, m_ew: int = 4) -> float:
@@ -55,18 +57,19 @@ def kernel_source_hash(*names) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name: str, src_hash: str):
-    """Counter-measured HBM bytes per launch, if taken on the current kernel source."""
+def counters_from_profile(name: str, src_hash: str) -> dict:
+    """Counter readings per launch stored under profiles/, if they were taken
+    on the current kernel source (else an empty dict)."""
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
-        return None
+        return {}
     try:
         d = json.load(open(p))
     except Exception:
-        return None
+        return {}
     if d.get("kernel_source_hash") != src_hash:
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return {}
+    return d
 
 
 class OracleChecks:
@@ -563,8 +566,6 @@ def main():
     ap.add_argument("--skip-extras", action="store_true", help="only the headline FP32 measurement")
     ap.add_argument("--skip-cpu", action="store_true", help="no CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device copy (counter calibration for HBM bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the path shards by frequency channel "
@@ -579,14 +580,6 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)    # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(max(1, args.steps)):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": src.numel() * 4, "launches": max(1, args.steps)}))
-        return
     w = sg.make_workload("c2")
     plan = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=w.m_ew, m_ns=w.m_ns, n_pol=w.n_pol, n_chan=w.n_chan,
                    block=w.block, ns_select=w.ns_select(), d_over_lambda=w.d_over_lambda())
@@ -625,7 +618,12 @@ def main():
     out_bytes = out.numel() * 4
     alg_bytes = in_bytes + out_bytes
     src_hash = kernel_source_hash("k_fft32.hip", "dev_common.h")
-    traffic = traffic_from_profile("traffic_fft32_chime.json", src_hash)
+    prof = counters_from_profile("traffic_fft32_chime.json", src_hash)
+    traffic = prof.get("hbm_bytes_per_launch")
+    # share of the vector issue slots the kernel's VALU instructions fill: a
+    # wavefront instruction occupies its SIMD for 4 cycles (no packed FP32)
+    valu = prof.get("sq_insts_valu_per_launch")
+    valu_frac = (valu * 4 / (N_SIMD * CLOCK_HZ * ms_avg / 1000.0)) if valu else None
 
     rec = {
         "metric": METRIC,
@@ -650,7 +648,8 @@ def main():
                      "kernel": "k_fft32<256,16>", "kernel_ms": ms_avg,
                      "kernel_ms_p10_p50_p90": [float(np.percentile(kern_ms, q)) for q in (10, 50, 90)],
                      "unpacked_fp32_issue_peak": FP32_UNPACKED_ISSUE_TFLOPS,
-                     "frac_of_unpacked_issue_peak": achieved_tflops / FP32_UNPACKED_ISSUE_TFLOPS,
+                     "valu_insts_per_launch": valu,
+                     "valu_issue_frac": valu_frac,
                      "flop_per_antenna_sample": flops / ant_samples,
                      "hbm_alg_bytes": alg_bytes,
                      "hbm_alg_gbs": alg_bytes / (ms_avg / 1000.0) / 1e9,

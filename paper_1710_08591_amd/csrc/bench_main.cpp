@@ -3,6 +3,7 @@
 //
 //   fftbf_bench [--n-ns N] [--n-chan C] [--n-pol P] [--n-time T] [--keep K]
 //               [--precision 0|1|2] [--steps S] [--warmup W] [--random 0|1]
+//   fftbf_bench --copy 1 [--steps S]
 //
 // Voltages are device-resident, filled with a fixed byte pattern (0x5A) or,
 // with --random 1, with hashed bytes: the memory traffic and the instruction
@@ -10,6 +11,9 @@
 // the clock it holds, does.  The N-S clamp keeps K beams per channel (every
 // other beam, 0 = no clamp).
 // Prints the average time per launch from HIP events on the launch stream.
+// With --copy 1 it only copies 1 GiB between two device buffers with a plain
+// streaming kernel (k_copy_calib), S times: the known byte count against
+// which memory-traffic counters are calibrated.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -46,6 +50,32 @@ __global__ void k_fill_hash(uint32_t* v, size_t n) {
   }
 }
 
+// dst[i] = src[i], grid-stride over n 16-byte elements
+__global__ void k_copy_calib(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+int copy_calibration(int steps) {
+  const size_t bytes = (size_t)1 << 30;
+  void *src = nullptr, *dst = nullptr;
+  int rc = 1;
+  if (!ok_hip(hipMalloc(&src, bytes), "hipMalloc src") || !ok_hip(hipMalloc(&dst, bytes), "hipMalloc dst")) goto done;
+  if (!ok_hip(hipMemset(src, 0x3C, bytes), "hipMemset") || !ok_hip(hipDeviceSynchronize(), "hipMemset")) goto done;
+  for (int i = 0; i < steps; ++i) {
+    hipLaunchKernelGGL(k_copy_calib, dim3(8192), dim3(256), 0, 0, static_cast<const float4*>(src),
+                       static_cast<float4*>(dst), bytes / sizeof(float4));
+    if (!ok_hip(hipGetLastError(), "k_copy_calib")) goto done;
+  }
+  if (!ok_hip(hipDeviceSynchronize(), "k_copy_calib")) goto done;
+  std::printf("fftbf_bench: copied %zu bytes per launch, %d launches\n", bytes, steps);
+  rc = 0;
+done:
+  if (src) (void)hipFree(src);
+  if (dst) (void)hipFree(dst);
+  return rc;
+}
+
 bool ok_bf(bf_status s, const char* what) {
   if (s == BF_OK) return true;
   std::fprintf(stderr, "%s: %s: %s\n", what, bf_status_string(s), bf_last_error());
@@ -64,11 +94,13 @@ int main(int argc, char** argv) {
   const int warmup = arg_int(argc, argv, "--warmup", 2);
   const int precision = arg_int(argc, argv, "--precision", BF_PREC_FP32);
   const int random = arg_int(argc, argv, "--random", 0);
+  const int copy = arg_int(argc, argv, "--copy", 0);
   if (n_ns <= 0 || n_chan <= 0 || n_pol <= 0 || n_time <= 0 || keep < 0 || keep > 2 * n_ns || steps <= 0 ||
-      warmup < 0 || (random != 0 && random != 1)) {
+      warmup < 0 || (random != 0 && random != 1) || (copy != 0 && copy != 1)) {
     std::fprintf(stderr, "invalid arguments\n");
     return 2;
   }
+  if (copy) return copy_calibration(steps);
 
   std::vector<int32_t> sel;
   bf_plan_desc d{};

@@ -218,9 +218,8 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 
   // Frames of this block that hold data: all of them, except in a short
   // final block (complex output with n_time not a multiple of the block).
-  // Every load is unconditional: a lane whose frame lies past the data
-  // re-reads its last valid one (its results are never stored), and the
-  // prefetch of the final pass re-reads the current frames, so no load
+  // Every load is unconditional (a lane whose frame lies past the data
+  // re-reads its last valid one; its results are never stored), so no load
   // sits under an execution mask and the next frames stay in flight while
   // the current ones are transformed.
   const int n_valid = (int)((p.n_time - t_base) < p.block ? (p.n_time - t_base) : p.block);
@@ -238,8 +237,14 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 #pragma unroll
     for (int j = 0; j < LA; ++j) b0[j] = __builtin_nontemporal_load(p0 + G * j);
     // this lane's frame in pass k follows its frame in pass k - 1, unless
-    // that is past the data (then the lane re-reads its last valid frame)
-    auto next = [&](const uint32_t* q, int k) { return (k * F + f1 < n_valid) ? q + f_step : q; };
+    // that is past the data (then the lane re-reads its last valid frame);
+    // the prefetch past the block's last pass reads the first frame of the
+    // voltage buffer instead, which every wavefront shares, so it stays in
+    // the L2 cache and costs no memory traffic
+    auto next = [&](const uint32_t* q, int k) {
+      if (k >= n_it) return p.volts + a1;
+      return (k * F + f1 < n_valid) ? q + f_step : q;
+    };
 
     auto frame_pass = [&](const uint32_t (&cur)[LA], int it) {
         // ---- E-W DFT for this lane's beam e1 at N-S positions a1 + G j ----

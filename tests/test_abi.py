@@ -108,3 +108,5 @@ def test_native_driver_rejects_bad_arguments():
     assert r.returncode == 2
     r = subprocess.run([exe, "--random", "2"], capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "invalid arguments" in r.stderr
+    r = subprocess.run([exe, "--copy", "2"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "invalid arguments" in r.stderr
