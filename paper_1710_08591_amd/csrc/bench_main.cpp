@@ -4,6 +4,7 @@
 //   fftbf_bench [--n-ns N] [--n-chan C] [--n-pol P] [--n-time T] [--keep K]
 //               [--precision 0|1|2] [--steps S] [--warmup W] [--random 0|1]
 //   fftbf_bench --copy 1 [--steps S]
+//   fftbf_bench --issue 1
 //
 // Voltages are device-resident, filled with a fixed byte pattern (0x5A) or,
 // with --random 1, with hashed bytes: the memory traffic and the instruction
@@ -13,7 +14,10 @@
 // Prints the average time per launch from HIP events on the launch stream.
 // With --copy 1 it only copies 1 GiB between two device buffers with a plain
 // streaming kernel (k_copy_calib), S times: the known byte count against
-// which memory-traffic counters are calibrated.
+// which memory-traffic counters are calibrated.  With --issue 1 it measures
+// the vector issue rate: 16 independent chains of one FP32 instruction form
+// (v_fmac_f32, v_fma_f32 with three vector operands, v_add_f32) per lane, at
+// 1, 2, 4 and 8 wavefronts per SIMD.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -76,6 +80,69 @@ done:
   return rc;
 }
 
+constexpr int kIssueChains = 16;
+
+// kind 0: a += x * y (v_fmac_f32); 1: a = a * y + z (v_fma_f32, three vector
+// operands); 2: a = a + b (v_add_f32).  One store per thread.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_issue(float* out, int iters) {
+  float u[kIssueChains], v[kIssueChains], a[kIssueChains];
+#pragma unroll
+  for (int i = 0; i < kIssueChains; ++i) {
+    u[i] = KIND == 1 ? 0.999f - threadIdx.x * 1e-7f : threadIdx.x * 1e-6f + i * 1e-3f;
+    v[i] = KIND == 1 ? 1e-3f * i + threadIdx.x * 1e-7f : 0.5f + i * 1e-4f;
+    a[i] = (float)i;
+  }
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < kIssueChains; ++i) {
+      if constexpr (KIND == 0) a[i] = fmaf(u[i], v[i], a[i]);
+      else if constexpr (KIND == 1) a[i] = fmaf(a[i], u[i], v[i]);
+      else a[i] = a[i] + u[i];
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < kIssueChains; ++i) s += a[i];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+int issue_probe() {
+  const int threads = 256, iters = 20000, cus = 256;
+  float* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = 1;
+  const char* names[3] = {"v_fmac_f32 (a += x y)", "v_fma_f32 (a = a y + z)", "v_add_f32 (a = a + b)"};
+  if (!ok_hip(hipMalloc(&out, sizeof(float) * cus * 8 * threads), "hipMalloc out")) goto done;
+  if (!ok_hip(hipEventCreate(&e0), "hipEventCreate") || !ok_hip(hipEventCreate(&e1), "hipEventCreate")) goto done;
+  for (int kind = 0; kind < 3; ++kind)
+    for (int wps = 1; wps <= 8; wps *= 2) {
+      const int blocks = cus * wps;            // a block is 4 wavefronts, one per SIMD of a compute unit
+      float best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        if (!ok_hip(hipEventRecord(e0, 0), "hipEventRecord")) goto done;
+        if (kind == 0) hipLaunchKernelGGL(k_issue<0>, dim3(blocks), dim3(threads), 0, 0, out, iters);
+        if (kind == 1) hipLaunchKernelGGL(k_issue<1>, dim3(blocks), dim3(threads), 0, 0, out, iters);
+        if (kind == 2) hipLaunchKernelGGL(k_issue<2>, dim3(blocks), dim3(threads), 0, 0, out, iters);
+        if (!ok_hip(hipGetLastError(), "k_issue") || !ok_hip(hipEventRecord(e1, 0), "hipEventRecord") ||
+            !ok_hip(hipEventSynchronize(e1), "hipEventSynchronize"))
+          goto done;
+        float ms = 0.f;
+        if (!ok_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) goto done;
+        if (ms < best) best = ms;
+      }
+      const double wave_instr = (double)blocks * (threads / 64) * iters * kIssueChains;
+      std::printf("fftbf_bench: %-26s %d wavefronts per SIMD: %.3f ms, %.3f wavefront-instructions per SIMD "
+                  "and cycle at 2.4 GHz\n", names[kind], wps, best, wave_instr / (best * 1e-3) / (cus * 4) / 2.4e9);
+    }
+  rc = 0;
+done:
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (out) (void)hipFree(out);
+  return rc;
+}
+
 bool ok_bf(bf_status s, const char* what) {
   if (s == BF_OK) return true;
   std::fprintf(stderr, "%s: %s: %s\n", what, bf_status_string(s), bf_last_error());
@@ -95,12 +162,15 @@ int main(int argc, char** argv) {
   const int precision = arg_int(argc, argv, "--precision", BF_PREC_FP32);
   const int random = arg_int(argc, argv, "--random", 0);
   const int copy = arg_int(argc, argv, "--copy", 0);
+  const int issue = arg_int(argc, argv, "--issue", 0);
   if (n_ns <= 0 || n_chan <= 0 || n_pol <= 0 || n_time <= 0 || keep < 0 || keep > 2 * n_ns || steps <= 0 ||
-      warmup < 0 || (random != 0 && random != 1) || (copy != 0 && copy != 1)) {
+      warmup < 0 || (random != 0 && random != 1) || (copy != 0 && copy != 1) ||
+      (issue != 0 && issue != 1)) {
     std::fprintf(stderr, "invalid arguments\n");
     return 2;
   }
   if (copy) return copy_calibration(steps);
+  if (issue) return issue_probe();
 
   std::vector<int32_t> sel;
   bf_plan_desc d{};

@@ -110,3 +110,5 @@ def test_native_driver_rejects_bad_arguments():
     assert r.returncode == 2 and "invalid arguments" in r.stderr
     r = subprocess.run([exe, "--copy", "2"], capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "invalid arguments" in r.stderr
+    r = subprocess.run([exe, "--issue", "3"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "invalid arguments" in r.stderr
