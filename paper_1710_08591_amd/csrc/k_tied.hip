@@ -360,6 +360,30 @@ __global__ __launch_bounds__(256) void k_tied_b16(TiedArgs a) {
   const float* beams = reinterpret_cast<const float*>(a.beams);
   const int kbg = lane & 31, kb = kbg >> 2, gq = kbg & 3;
 
+  // this wavefront's group of 16 samples (pol) starting at tw: lane (kbg,
+  // half) holds 8 consecutive floats of samples 2 it + half, it < 8
+  auto load_group = [&](int64_t tw, int pol, f32x4 (&v)[8][2]) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int s = 2 * it + (lane >> 5);
+      const float* src = beams + (((tw + s) * a.n_chan + chan) * a.n_pol + pol) * 256 + 8 * kbg;
+      v[it][0] = *reinterpret_cast<const f32x4*>(src);
+      v[it][1] = *reinterpret_cast<const f32x4*>(src + 4);
+    }
+  };
+  // The next group's beams are loaded into registers while the matrix
+  // cores interpolate the current quad, so the loads overlap that work.
+  f32x4 nv[8][2];
+  {
+    const int64_t tw = t0 + kV16TS * wave;
+    if (tw < t1) {
+      load_group(tw, pol_lo, nv);
+    } else {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) nv[it][0] = nv[it][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+
   float acc = 0.f;
   for (int64_t tq = t0; tq < t1; tq += 4 * kV16TS) {
     float accg[4] = {0.f, 0.f, 0.f, 0.f};
@@ -367,12 +391,11 @@ __global__ __launch_bounds__(256) void k_tied_b16(TiedArgs a) {
       const int64_t tw = tq + kV16TS * wave;
       if (tw < t1) {
         _Float16* lds_g = lds_b + wave * kBuf;
-#pragma unroll 2
+#pragma unroll
         for (int it = 0; it < 8; ++it) {
           const int s = 2 * it + (lane >> 5);
-          const float* src = beams + (((tw + s) * a.n_chan + chan) * a.n_pol + pol) * 256 + 8 * kbg;
-          const f32x4 v0 = *reinterpret_cast<const f32x4*>(src);
-          const f32x4 v1 = *reinterpret_cast<const f32x4*>(src + 4);
+          const f32x4 v0 = nv[it][0];
+          const f32x4 v1 = nv[it][1];
           float m = fmaxf(fmaxf(fmaxf(fabsf(v0[0]), fabsf(v0[1])), fmaxf(fabsf(v0[2]), fabsf(v0[3]))),
                           fmaxf(fmaxf(fabsf(v1[0]), fabsf(v1[1])), fmaxf(fabsf(v1[2]), fabsf(v1[3]))));
 #pragma unroll
@@ -392,6 +415,22 @@ __global__ __launch_bounds__(256) void k_tied_b16(TiedArgs a) {
         }
       }
       __syncthreads();
+      {
+        // the next (quad, pol) of this wavefront, if any
+        int64_t tn = tq;
+        int pn = pol + 1;
+        if (pn >= pol_hi) {
+          pn = pol_lo;
+          tn = tq + 4 * kV16TS;
+        }
+        const int64_t twn = tn + kV16TS * wave;
+        if (tn < t1 && twn < t1) {
+          load_group(twn, pn, nv);
+        } else {
+#pragma unroll
+          for (int it = 0; it < 8; ++it) nv[it][0] = nv[it][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
       if (wave_live) {
 #pragma unroll
         for (int g = 0; g < 4; ++g)
