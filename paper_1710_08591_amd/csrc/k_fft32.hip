@@ -377,13 +377,15 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
     const int keep = p.n_keep;
     const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
     float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
-    for (int idx = lane; idx < 4 * keep; idx += 64) {
-      const int e = idx / keep, j = idx - e * keep;
-      const int A = sel ? sel[j] : j;
-      float v = 0.f;
 #pragma unroll
-      for (int f = 0; f < F; ++f) v += lds_i[(f * 4 + e) * M + A];
-      o[(e * p.ew_mul + p.ew_off) * keep + j] = v * p.norm;
+    for (int e = 0; e < 4; ++e) {
+      for (int j = lane; j < keep; j += 64) {
+        const int A = sel ? sel[j] : j;
+        float v = 0.f;
+#pragma unroll
+        for (int f = 0; f < F; ++f) v += lds_i[(f * 4 + e) * M + A];
+        o[(e * p.ew_mul + p.ew_off) * keep + j] = v * p.norm;
+      }
     }
   }
 }
