@@ -126,6 +126,29 @@ def test_tied_from_fft_beams_scaling_and_fallback(scale):
     plan.close()
 
 
+@pytest.mark.parametrize("n_time,block", [(368, 16), (352, 32)])
+def test_tied_from_fft_beams_pol_sum_ragged_quads(n_time, block):
+    """Tied beams from stored FFT beams on the matrix cores with both
+    polarisations summed, and sample counts that leave the last quad of
+    16-sample groups partly empty, over two workgroup spans (368) or with
+    blocks of two groups (352): the next group's beams are loaded while the
+    current quad is interpolated, stepping through (quad, polarisation)."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=2, n_pol=2, n_time=n_time, seed=71, n_src=2, snr=20.0,
+                           dl=(0.4, 0.8))
+    v = sg.volts(w)
+    plan = plan_for(w, clamp=False, pol_sum=True, block=block)
+    beams = bf.beamform_fft(plan, torch.from_numpy(v).cuda(), kind=bf.BF_OUT_COMPLEX)
+    assert beams.data_ptr() % 16 == 0          # the matrix-core kernel
+    dirs = np.concatenate([sg.pointings(40, 72), [[0.0, 0.0]]], axis=0)
+    got = bf.form_tied_beams(plan, beams, 0, 2, torch.from_numpy(dirs).cuda()).cpu().numpy()
+    ref = orc.tied_intensity(v, dirs, w.d_over_lambda(), block).sum(axis=2)
+    assert got.shape == ref.shape
+    assert rel_err(got, ref) < TOL_FP32
+    plan.close()
+
+
 def test_tied_on_grid_and_odd_counts():
     """On-grid pointings reproduce the FFT beams; ragged pointing tiles; channel subsets."""
     torch = _torch()
