@@ -384,6 +384,11 @@ __global__ __launch_bounds__(256) void k_tied_b16(TiedArgs a) {
     }
   }
 
+  // groups of kV16TS samples per block, and the block being summed (a
+  // workgroup's span starts at a block boundary)
+  const int gpb = a.block / kV16TS;
+  int gcnt = 0;
+  int64_t blk = (int64_t)trun * kTiedBlocksPerWg;
   float acc = 0.f;
   for (int64_t tq = t0; tq < t1; tq += 4 * kV16TS) {
     float accg[4] = {0.f, 0.f, 0.f, 0.f};
@@ -440,16 +445,16 @@ __global__ __launch_bounds__(256) void k_tied_b16(TiedArgs a) {
     }
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const int64_t tg = tq + kV16TS * g;
-      if (tg >= t1) break;
+      if (tq + kV16TS * g >= t1) break;
       acc += accg[g];
-      if ((tg + kV16TS) % a.block == 0) {
+      if (++gcnt == gpb) {                         // the block's last group
         if (live && lane < 16) {
-          const int64_t blk = tg / a.block;
           float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
           *o = acc;
         }
         acc = 0.f;
+        gcnt = 0;
+        ++blk;
       }
     }
   }
@@ -500,6 +505,11 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
   const int64_t t1 = t0 + span < a.n_time ? t0 + span : a.n_time;
   const int64_t frame_dw = (int64_t)a.n_chan * a.n_pol * kV16N;   // dwords per sample
 
+  // groups of kV16TS samples per block, and the block being summed (a
+  // workgroup's span starts at a block boundary)
+  const int gpb = a.block / kV16TS;
+  int gcnt = 0;
+  int64_t blk = (int64_t)trun * kTiedBlocksPerWg;
   float acc = 0.f;
   for (int64_t tq = t0; tq < t1; tq += 4 * kV16TS) {
     float accg[4] = {0.f, 0.f, 0.f, 0.f};
@@ -519,16 +529,16 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
     }
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const int64_t tg = tq + kV16TS * g;
-      if (tg >= t1) break;
+      if (tq + kV16TS * g >= t1) break;
       acc += accg[g];
-      if ((tg + kV16TS) % a.block == 0) {
+      if (++gcnt == gpb) {                         // the block's last group
         if (live && lane < 16) {
-          const int64_t blk = tg / a.block;
           float* o = static_cast<float*>(a.out) + ((blk * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p;
           *o = acc;
         }
         acc = 0.f;
+        gcnt = 0;
+        ++blk;
       }
     }
   }
@@ -558,10 +568,14 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
     if (wave_live)
       tied_weights(dl[2 * t.chan] * t.dircos[2 * pp], dl[2 * t.chan + 1] * t.dircos[2 * pp + 1], lane >> 4, w);
     for (int pol = 0; pol < n_pol; ++pol) {
+      // ring slot of this wavefront's first sample, advanced by a quad of
+      // groups per pass (the ring holds at least 16 samples, so a lane's
+      // sample l.ts < 16 past it wraps at most once)
+      int64_t sl = (t.t_start + (int64_t)(t.blk0 + wave) * kV16TS) % ring_samples;
       for (int b0 = 0; b0 < t.n_blk; b0 += 4) {
         if (b0 + wave < t.n_blk) {
-          const int64_t s0 = t.t_start + (int64_t)(t.blk0 + b0 + wave) * kV16TS;
-          const int64_t slot = (s0 + l.ts) % ring_samples;
+          int64_t slot = sl + l.ts;
+          if (slot >= ring_samples) slot -= ring_samples;
           const uint32_t* src = ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * kV16N;
           v16_fft_to_lds<false>(src, l, nullptr, lds_b + wave * kV16Buf, 8);
         }
@@ -581,6 +595,8 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
             t.out[((ob * t.n_chan_req + (t.chan - t.chan_lo)) * n_pol + pol) * (int64_t)t.n_point + p] = accg[g];
           }
         }
+        sl += 4 * kV16TS;
+        while (sl >= ring_samples) sl -= ring_samples;
       }
     }
   }
