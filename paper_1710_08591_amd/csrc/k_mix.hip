@@ -194,18 +194,6 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
   const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
   const int keep = a.n_keep;
   const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
-  // block-end gather, the same for every block: output lane + 64 i (of the
-  // 4 x keep <= 128 kept beams) comes from LDS element gsrc[i] (-1: none)
-  int gsrc[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int idx = lane + 64 * i;
-    gsrc[i] = -1;
-    if (idx < 4 * keep) {
-      const int e = idx / keep, j = idx - e * keep;
-      gsrc[i] = e * 32 + (sel ? sel[j] : j);
-    }
-  }
 
   for (int64_t blk = blk0; blk < blk1; ++blk) {
     float ia[4][2];
@@ -301,9 +289,10 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
     }
     __syncthreads();
     float* o = a.out + ((blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      if (gsrc[i] >= 0) o[lane + 64 * i] = lds_i[gsrc[i]];
+    for (int idx = lane; idx < 4 * keep; idx += 64) {
+      const int e = idx / keep, j = idx - e * keep;
+      o[idx] = lds_i[e * 32 + (sel ? sel[j] : j)];
+    }
     __syncthreads();
   }
 }
