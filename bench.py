@@ -447,7 +447,23 @@ def run_extras(dev, checks: OracleChecks) -> dict:
                                                    f"({beams.numel() * 8 / 2**30:.0f} GiB)",
                                        "kernel_ms": ms_b, "beam_samples_per_s": 64 * 256 * 16384 / (ms_b / 1e3),
                                        "hbm_alg_gbs": beams.numel() * 8 / (ms_b / 1e3) / 1e9}
-    del beams
+    # the standalone block sum of |B|^2 (bf_accumulate_intensity) over the same stored beams
+    z2 = beams.view(beams.shape[0], -1)
+    acc_out = torch.empty((z2.shape[0] // 16, z2.shape[1]), dtype=torch.float32, device=dev)
+    ms_a = _time_launches(lambda: bf.accumulate_intensity(z2, 16, out=acc_out), 5, warmup=1)
+    acc_bytes = z2.numel() * 8 + acc_out.numel() * 4
+    acc_rec = {"workload": f"|B|^2 summed over 16 samples of the same stored beams "
+                           f"({z2.shape[0]} samples x {z2.shape[1]} series)",
+               "kernel_ms": ms_a, "hbm_alg_gbs": acc_bytes / (ms_a / 1e3) / 1e9,
+               "hbm_frac": acc_bytes / (ms_a / 1e3) / 1e9 / HBM_PEAK_GBS}
+    prng = np.random.default_rng(13)
+    for _ in range(2):
+        b, c = int(prng.integers(z2.shape[0] // 16)), int(prng.integers(256))
+        got = acc_out[b].view(256, 1, 4, 32)[c].cpu().numpy()
+        checks.add(acc_rec, "max_rel_power_err_sampled", "fft_rel", got,
+                   v=sg.volts(wt, 16 * b, 16, chans=[c]), m_ew=4, m_ns=32, index=(0, 0))
+    ex["accumulate_intensity"] = acc_rec
+    del beams, z2, acc_out
     plan.close()
     del vt
     torch.cuda.empty_cache()

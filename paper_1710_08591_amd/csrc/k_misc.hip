@@ -63,6 +63,18 @@ __global__ __launch_bounds__(256) void k_accumulate(const float2* __restrict__ z
   const v2f* p = reinterpret_cast<const v2f*>(z) + b * block * n_series + s;
   float acc0 = 0.f, acc1 = 0.f;
   int t = 0;
+  // eight samples' loads in flight at once; even samples go to acc0, odd to
+  // acc1, in the same order as the pairwise loop below
+  for (; t + 8 <= block; t += 8) {
+    v2f u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = __builtin_nontemporal_load(p + (int64_t)(t + q) * n_series);
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+      acc0 = fmaf(u[q].x, u[q].x, fmaf(u[q].y, u[q].y, acc0));
+      acc1 = fmaf(u[q + 1].x, u[q + 1].x, fmaf(u[q + 1].y, u[q + 1].y, acc1));
+    }
+  }
   for (; t + 1 < block; t += 2) {
     const v2f u = __builtin_nontemporal_load(p + (int64_t)t * n_series);
     const v2f v = __builtin_nontemporal_load(p + (int64_t)(t + 1) * n_series);

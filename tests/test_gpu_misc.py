@@ -15,7 +15,8 @@ def _torch():
     return torch
 
 
-@pytest.mark.parametrize("n_time,n_series,block", [(64, 7, 16), (48, 1000, 3), (16, 64, 16), (5, 3, 1)])
+@pytest.mark.parametrize("n_time,n_series,block", [(64, 7, 16), (48, 1000, 3), (16, 64, 16), (5, 3, 1),
+                                                   (44, 33, 11), (40, 5, 10)])
 def test_accumulate_intensity(n_time, n_series, block):
     torch = _torch()
     import paper_1710_08591_amd as bf
