@@ -177,17 +177,24 @@ __device__ __forceinline__ int v16_data_scale(float hmax) {
   return e - 1;
 }
 
-// FFT beams of the 16 samples whose frames the lanes point at (lane = sample
+// This lane's frame of one group: the kV16N dwords of sample l.ts (the
+// voltages need only 4-byte alignment).
+__device__ __forceinline__ void v16_load(const uint32_t* __restrict__ src, uint32_t (&dw)[kV16N]) {
+#pragma unroll
+  for (int j = 0; j < kV16N; ++j) dw[j] = src[j];
+}
+
+// FFT beams of the 16 samples whose frames the lanes hold (lane = sample
 // l.ts, E-W beam l.e), normalised by 1/sqrt(64), scaled by 2^ds and split
 // into the FP16 operand layout above.
 template <bool TAPER>
-__device__ __forceinline__ void v16_fft_to_lds(const uint32_t* __restrict__ src, const V16Lane& l,
+__device__ __forceinline__ void v16_fft_to_lds(const uint32_t (&dw)[kV16N], const V16Lane& l,
                                                const float* lds_h, _Float16* lds_g, int ds) {
   constexpr int N = kV16N, MNS = kV16M;
   cf x[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const uint32_t d = src[j];
+    const uint32_t d = dw[j];
     if constexpr (TAPER) {
       float re = 0.f, im = 0.f;
 #pragma unroll
@@ -510,16 +517,41 @@ __global__ __launch_bounds__(256) void k_tied_v16(TiedArgs a) {
   const int gpb = a.block / kV16TS;
   int gcnt = 0;
   int64_t blk = (int64_t)trun * kTiedBlocksPerWg;
+  // The next group's frames are loaded into registers while the matrix
+  // cores interpolate the current quad.
+  auto frames = [&](int64_t tw, int pol) {
+    return a.volts + (tw + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * kV16N;
+  };
+  uint32_t nd[kV16N];
+  if (t0 + kV16TS * wave < t1) {
+    v16_load(frames(t0 + kV16TS * wave, pol_lo), nd);
+  } else {
+#pragma unroll
+    for (int j = 0; j < kV16N; ++j) nd[j] = 0u;
+  }
   float acc = 0.f;
   for (int64_t tq = t0; tq < t1; tq += 4 * kV16TS) {
     float accg[4] = {0.f, 0.f, 0.f, 0.f};
     for (int pol = pol_lo; pol < pol_hi; ++pol) {
       const int64_t tw = tq + kV16TS * wave;
-      if (tw < t1) {
-        const uint32_t* src = a.volts + (tw + l.ts) * frame_dw + ((int64_t)chan * a.n_pol + pol) * kV16N;
-        v16_fft_to_lds<TAPER>(src, l, lds_h, lds_b + wave * kV16Buf, ds);
-      }
+      if (tw < t1) v16_fft_to_lds<TAPER>(nd, l, lds_h, lds_b + wave * kV16Buf, ds);
       __syncthreads();
+      {
+        // the next (quad, pol) of this wavefront, if any
+        int64_t tn = tq;
+        int pn = pol + 1;
+        if (pn >= pol_hi) {
+          pn = pol_lo;
+          tn = tq + 4 * kV16TS;
+        }
+        const int64_t twn = tn + kV16TS * wave;
+        if (twn < t1) {
+          v16_load(frames(twn, pn), nd);
+        } else {
+#pragma unroll
+          for (int j = 0; j < kV16N; ++j) nd[j] = 0u;
+        }
+      }
       if (wave_live) {
 #pragma unroll
         for (int g = 0; g < 4; ++g)
@@ -567,19 +599,44 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
     TiedW w;
     if (wave_live)
       tied_weights(dl[2 * t.chan] * t.dircos[2 * pp], dl[2 * t.chan + 1] * t.dircos[2 * pp + 1], lane >> 4, w);
+    // ring slot of this wavefront's first sample (the same for every pol),
+    // advanced by a quad of groups per pass (the ring holds at least 16
+    // samples, so a lane's sample l.ts < 16 past it wraps at most once)
+    const int64_t sl0 = (t.t_start + (int64_t)(t.blk0 + wave) * kV16TS) % ring_samples;
+    auto frames = [&](int64_t sl, int pol) {
+      int64_t slot = sl + l.ts;
+      if (slot >= ring_samples) slot -= ring_samples;
+      return ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * kV16N;
+    };
+    // the next group's frames are loaded while the current quad is interpolated
+    uint32_t nd[kV16N];
+    if (wave < t.n_blk) {
+      v16_load(frames(sl0, 0), nd);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kV16N; ++j) nd[j] = 0u;
+    }
     for (int pol = 0; pol < n_pol; ++pol) {
-      // ring slot of this wavefront's first sample, advanced by a quad of
-      // groups per pass (the ring holds at least 16 samples, so a lane's
-      // sample l.ts < 16 past it wraps at most once)
-      int64_t sl = (t.t_start + (int64_t)(t.blk0 + wave) * kV16TS) % ring_samples;
+      int64_t sl = sl0;
       for (int b0 = 0; b0 < t.n_blk; b0 += 4) {
-        if (b0 + wave < t.n_blk) {
-          int64_t slot = sl + l.ts;
-          if (slot >= ring_samples) slot -= ring_samples;
-          const uint32_t* src = ring + slot * frame_dw + ((int64_t)t.chan * n_pol + pol) * kV16N;
-          v16_fft_to_lds<false>(src, l, nullptr, lds_b + wave * kV16Buf, 8);
-        }
+        if (b0 + wave < t.n_blk) v16_fft_to_lds<false>(nd, l, nullptr, lds_b + wave * kV16Buf, 8);
         __syncthreads();
+        {
+          int64_t sn = sl + 4 * kV16TS;
+          while (sn >= ring_samples) sn -= ring_samples;
+          int bn = b0 + 4, pn = pol;
+          if (bn >= t.n_blk) {
+            bn = 0;
+            ++pn;
+            sn = sl0;
+          }
+          if (pn < n_pol && bn + wave < t.n_blk) {
+            v16_load(frames(sn, pn), nd);
+          } else {
+#pragma unroll
+            for (int j = 0; j < kV16N; ++j) nd[j] = 0u;
+          }
+        }
         float accg[4] = {0.f, 0.f, 0.f, 0.f};
         if (wave_live) {
 #pragma unroll
