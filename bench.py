@@ -225,6 +225,17 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
         checks.add(gains_rec, "max_rel_power_err_sampled", "fft_rel", out[blk, c, p].cpu().numpy(),
                    v=sg.volts(w, blk * 16, 16, chans=[c], pols=[p]), m_ew=w.m_ew, m_ns=w.m_ns,
                    index=(0, 0, 0), sel=sel[c], taper=gains.astype(np.complex64).astype(np.complex128))
+    # the per-antenna Gaussian window (real sculpting weights) on the same voltages, FP32 plan
+    h = sg.gaussian_taper(w.n_ew, w.n_ns)
+    h_dev = torch.from_numpy(np.ascontiguousarray(h, dtype=np.float32)).to(dev)
+    h_ms = _time_launches(lambda: bf.beamform_fft(plan32, volts, out=out, taper=h_dev), 5)
+    window_rec = {"kernel_ms": h_ms, "antenna_samples_per_s": w.antenna_samples / (h_ms / 1e3),
+                  "slowdown_vs_no_window": h_ms / fp32_ms}
+    for _ in range(2):
+        blk, c, p = int(rng.integers(1024)), int(rng.integers(256)), int(rng.integers(2))
+        checks.add(window_rec, "max_rel_power_err_sampled", "fft_rel", out[blk, c, p].cpu().numpy(),
+                   v=sg.volts(w, blk * 16, 16, chans=[c], pols=[p]), m_ew=w.m_ew, m_ns=w.m_ns,
+                   index=(0, 0, 0), sel=sel[c], taper=np.asarray(h, dtype=np.float64))
     plan32.close()
     # MFMA work issued per sample frame: 4 E-W beams x (stage 1: 2 terms x [64 x 32] over 16 a1
     # + stage 2: 3 products of [32 x 32] over 32 k2), 2 flop per multiply-add
@@ -238,7 +249,7 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
                 "hbm_alg_gbs": alg / (ms / 1e3) / 1e9, "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                 "mfma_tflops": mfma_flops / (ms / 1e3) / 1e12,
                 "mfma_frac_of_fp16_peak": mfma_flops / (ms / 1e3) / 1e12 / FP16_MFMA_PEAK_TFLOPS,
-                "fp32_with_complex_gains": gains_rec})
+                "fp32_with_complex_gains": gains_rec, "fp32_with_real_window": window_rec})
     return rec
 
 
