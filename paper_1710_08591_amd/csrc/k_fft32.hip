@@ -6,8 +6,9 @@
 // M = 2 n_ns -- then |B|^2 summed over blocks of samples (the time sum of
 // eq. e:bf), clamped to the kept N-S beams of each channel.
 //
-// Work split (one 64-lane wavefront per workgroup, one workgroup per
-// (block, channel, polarisation group)):
+// Work split (one 64-lane wavefront per (block, channel, polarisation
+// group), each with its own LDS tile; one wave per workgroup, or a few that
+// share the table of per-antenna factors):
 //   * the N-S transform M = (2L) x G, with n_ns = L G:
 //       a = a1 + G a2,  A = k2 + 2L k1
 //       pass 1 (one lane per (frame, E-W beam e, a1)): zero-padded 2L-point
@@ -103,9 +104,10 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
   return (float)(int)__builtin_amdgcn_sbfe((int)d, shift, 4);
 }
 
-// The workgroup is one wavefront, and a wavefront's LDS operations execute
-// in the order it issues them: between the transpose's writes and reads only
-// the compiler's order has to be kept, with no wait for the writes to land.
+// Each wavefront works in an LDS tile of its own, and a wavefront's LDS
+// operations execute in the order it issues them: between the transpose's
+// writes and reads only the compiler's order has to be kept, with no wait
+// for the writes to land.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -131,8 +133,28 @@ struct Pass1Tw {
 // M < n): the N * FOLD antennas along N-S are summed onto N positions by
 // a mod N before an N-point transform, whose outputs are the even outputs
 // of the zero-padded 2N-point transform computed here.
+// Waves per workgroup.  Every wave transforms its own (block, channel,
+// polarisation group) in its own LDS tile; the variants with per-antenna
+// factors keep one table of them per workgroup, shared by its waves.  With
+// one wave per workgroup that table would let the LDS, not the registers,
+// bound the waves per CU (7 instead of 8 with real weights on 256 N-S
+// positions, 6 with complex gains); enough waves share it that the LDS
+// allows the occupancy the registers do (8 waves per CU at N x FOLD = 256,
+// 16 below).
+template <int N, int G, int TAPER, int FOLD>
+constexpr int fft32_wpg() {
+  constexpr int kLds = 160 * 1024;
+  constexpr int tile = 64 * (2 * (N / G) + 1) * 8;   // F * 4 * G = 64 rows
+  constexpr int table = TAPER == 2 ? N * FOLD * 32 : TAPER == 1 ? N * FOLD * 16 : 0;
+  if (table == 0) return 1;
+  constexpr int want = (N * FOLD >= 256 ? 8 : 16) < kLds / tile ? (N * FOLD >= 256 ? 8 : 16) : kLds / tile;
+  for (int w = 1; w < 4; w *= 2)
+    if (kLds / (w * tile + table) * w >= want) return w;
+  return 4;
+}
+
 template <int N, int G, int TAPER, bool CPLX, int FOLD = 1>
-__global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
+__global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32(Fft32Args p) {
   constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
   constexpr int NA = N * FOLD, LA = L * FOLD;   // antennas along N-S; dwords per lane per frame
   constexpr int F = 64 / (4 * G);      // frames handled side by side
@@ -142,25 +164,29 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
   static_assert(R2 >= 1 && R2 * 64 == F * 4 * L2, "pass-2 tasks must tile the wavefront");
   static_assert(F * 4 * M * 4 <= F * 4 * G * YS * 8, "block-end sums must fit the LDS");
 
-  __shared__ cf lds_y[F * 4 * G * YS];
+  constexpr int WPG = fft32_wpg<N, G, TAPER, FOLD>();
+  constexpr int TILE = F * 4 * G * YS;
+  __shared__ cf lds_tiles[WPG * TILE];
   __shared__ float lds_h[TAPER == 2 ? NA * 8 : TAPER == 1 ? NA * 4 : 1];
 
-  const int lane = threadIdx.x;
+  const int lane = WPG == 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  const int wave = WPG == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  cf* const lds_y = lds_tiles + wave * TILE;
   const int f1 = lane / (4 * G), e1 = (lane / G) & 3, a1 = lane % G;
 
-  int wg = blockIdx.x;
+  int wg = (int)((int64_t)blockIdx.x * WPG + wave);
   const int pg = wg % p.n_pg;
   wg /= p.n_pg;
   const int chan = wg % p.n_chan;
   const int blk = wg / p.n_chan;
 
   if constexpr (TAPER == 1) {
-    for (int i = lane; i < NA * 4; i += 64) lds_h[i] = p.taper[i];
+    for (int i = threadIdx.x; i < NA * 4; i += 64 * WPG) lds_h[i] = p.taper[i];
     __syncthreads();
   } else if constexpr (TAPER == 2) {
     // per antenna (a_ns, q): g = 1, h or the complex gain, times W_8^q when twisting
     constexpr float kS = 0.70710678118654752f;
-    for (int i = lane; i < NA * 4; i += 64) {
+    for (int i = threadIdx.x; i < NA * 4; i += 64 * WPG) {
       float gr = 1.f, gi = 0.f;
       if (p.gain_src == 2) {
         gr = p.taper[2 * i];
@@ -181,6 +207,9 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
     }
     __syncthreads();
   }
+  // the last workgroup's spare waves (task count not a multiple of WPG)
+  // leave after the workgroup's only barrier
+  if (WPG > 1 && (int64_t)blockIdx.x * WPG + wave >= p.n_wg) return;
 
   // pass-1 twiddles W_M^{a1 k2}, generated in FP64 at plan creation, in
   // tangent form W = Re W (1 + i t): only t is applied here, the factor
@@ -373,7 +402,7 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 #pragma unroll
       for (int k1 = 0; k1 < G; ++k1) lds_i[(f * 4 + e) * M + k2 + L2 * k1] = acc[r][k1];
     }
-    __syncthreads();
+    wave_lds_sync();
     const int keep = p.n_keep;
     const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
     float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
@@ -391,20 +420,21 @@ __global__ __launch_bounds__(64) void k_fft32(Fft32Args p) {
 }
 
 template <int N, int G, int T, int FOLD = 1>
-void launch_nt(const Fft32Args& a, bool cplx, dim3 grid, hipStream_t s) {
-  if (cplx) hipLaunchKernelGGL((k_fft32<N, G, T, true, FOLD>), grid, dim3(64), 0, s, a);
-  else hipLaunchKernelGGL((k_fft32<N, G, T, false, FOLD>), grid, dim3(64), 0, s, a);
+void launch_nt(const Fft32Args& a, bool cplx, hipStream_t s) {
+  constexpr int W = fft32_wpg<N, G, T, FOLD>();
+  const dim3 grid((unsigned)((a.n_wg + W - 1) / W)), threads(64 * W);
+  if (cplx) hipLaunchKernelGGL((k_fft32<N, G, T, true, FOLD>), grid, threads, 0, s, a);
+  else hipLaunchKernelGGL((k_fft32<N, G, T, false, FOLD>), grid, threads, 0, s, a);
 }
 
 // cyclic co-adding: no window, or a real window for folds up to 8 (the
 // 16-fold windowed variant would not fit its registers)
 template <int N, int G, int FOLD>
-hipError_t launch_fold(const Fft32Args& a, int taper, bool cplx, int64_t n_wg, hipStream_t s) {
-  const dim3 grid((unsigned)n_wg);
+hipError_t launch_fold(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
   if (taper == 0) {
-    launch_nt<N, G, 0, FOLD>(a, cplx, grid, s);
+    launch_nt<N, G, 0, FOLD>(a, cplx, s);
   } else if (taper == 1) {
-    if constexpr (FOLD <= 8) launch_nt<N, G, 1, FOLD>(a, cplx, grid, s);
+    if constexpr (FOLD <= 8) launch_nt<N, G, 1, FOLD>(a, cplx, s);
     else return hipErrorNotSupported;
   } else {
     return hipErrorNotSupported;
@@ -413,12 +443,11 @@ hipError_t launch_fold(const Fft32Args& a, int taper, bool cplx, int64_t n_wg, h
 }
 
 template <int N, int G>
-hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, int64_t n_wg, hipStream_t s) {
-  const dim3 grid((unsigned)n_wg);
-  if (taper == 3) launch_nt<N, G, 3>(a, cplx, grid, s);
-  else if (taper == 2) launch_nt<N, G, 2>(a, cplx, grid, s);
-  else if (taper == 1) launch_nt<N, G, 1>(a, cplx, grid, s);
-  else launch_nt<N, G, 0>(a, cplx, grid, s);
+hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
+  if (taper == 3) launch_nt<N, G, 3>(a, cplx, s);
+  else if (taper == 2) launch_nt<N, G, 2>(a, cplx, s);
+  else if (taper == 1) launch_nt<N, G, 1>(a, cplx, s);
+  else launch_nt<N, G, 0>(a, cplx, s);
   return hipGetLastError();
 }
 
@@ -448,28 +477,30 @@ int fft32_group(int n_ns) {
 
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s) {
-  if (a.fold > 1) {
-    const int key = n_ns * 1000 + a.fold;
+  Fft32Args b = a;
+  b.n_wg = n_wg;
+  if (b.fold > 1) {
+    const int key = n_ns * 1000 + b.fold;
     switch (key) {
-      case 16002: return launch_fold<16, 4, 2>(a, taper, cplx, n_wg, s);
-      case 16004: return launch_fold<16, 4, 4>(a, taper, cplx, n_wg, s);
-      case 16008: return launch_fold<16, 4, 8>(a, taper, cplx, n_wg, s);
-      case 16016: return launch_fold<16, 4, 16>(a, taper, cplx, n_wg, s);
-      case 32002: return launch_fold<32, 8, 2>(a, taper, cplx, n_wg, s);
-      case 32004: return launch_fold<32, 8, 4>(a, taper, cplx, n_wg, s);
-      case 32008: return launch_fold<32, 8, 8>(a, taper, cplx, n_wg, s);
-      case 64002: return launch_fold<64, 8, 2>(a, taper, cplx, n_wg, s);
-      case 64004: return launch_fold<64, 8, 4>(a, taper, cplx, n_wg, s);
-      case 128002: return launch_fold<128, 16, 2>(a, taper, cplx, n_wg, s);
+      case 16002: return launch_fold<16, 4, 2>(b, taper, cplx, s);
+      case 16004: return launch_fold<16, 4, 4>(b, taper, cplx, s);
+      case 16008: return launch_fold<16, 4, 8>(b, taper, cplx, s);
+      case 16016: return launch_fold<16, 4, 16>(b, taper, cplx, s);
+      case 32002: return launch_fold<32, 8, 2>(b, taper, cplx, s);
+      case 32004: return launch_fold<32, 8, 4>(b, taper, cplx, s);
+      case 32008: return launch_fold<32, 8, 8>(b, taper, cplx, s);
+      case 64002: return launch_fold<64, 8, 2>(b, taper, cplx, s);
+      case 64004: return launch_fold<64, 8, 4>(b, taper, cplx, s);
+      case 128002: return launch_fold<128, 16, 2>(b, taper, cplx, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (n_ns) {
-    case 16: return launch_n<16, 4>(a, taper, cplx, n_wg, s);
-    case 32: return launch_n<32, 8>(a, taper, cplx, n_wg, s);
-    case 64: return launch_n<64, 8>(a, taper, cplx, n_wg, s);
-    case 128: return launch_n<128, 16>(a, taper, cplx, n_wg, s);
-    case 256: return launch_n<256, 16>(a, taper, cplx, n_wg, s);
+    case 16: return launch_n<16, 4>(b, taper, cplx, s);
+    case 32: return launch_n<32, 8>(b, taper, cplx, s);
+    case 64: return launch_n<64, 8>(b, taper, cplx, s);
+    case 128: return launch_n<128, 16>(b, taper, cplx, s);
+    case 256: return launch_n<256, 16>(b, taper, cplx, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -32,6 +32,8 @@ struct Fft32Args {
   // cyclic co-adding: the n_ns = fold * N antennas along N-S are summed by
   // a mod N onto the N positions of the transform (1: none)
   int fold;
+  // (block, channel, polarisation group) tasks, one per wave; set by the launch
+  int64_t n_wg;
 };
 
 int fft32_frames_per_pass(int n_ns);

@@ -104,6 +104,45 @@ def test_complex_beams_ragged(n_ns, n_time):
     assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-6
 
 
+@pytest.mark.parametrize("n_ns", [64, 128, 256])
+@pytest.mark.parametrize("weights", ["window", "gains"])
+def test_weighted_partial_last_workgroup(n_ns, weights):
+    """With per-antenna weights several wavefronts share a workgroup and its
+    table of weights, one (block, channel, polarisation group) each: 9 tasks
+    (3 blocks x 3 channels) leave the last workgroup partly empty, for
+    intensities per polarisation and summed, and for complex beams with a
+    ragged last chunk."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    rng = np.random.default_rng(n_ns)
+    if weights == "window":
+        wt = sg.half_sine_taper(4, n_ns, shifted=True)
+        ref_wt = wt
+    else:
+        wt = (np.exp(rng.normal(size=(n_ns, 4)) * 0.3 + 1j * rng.uniform(-np.pi, np.pi, (n_ns, 4)))
+              ).astype(np.complex64)
+        ref_wt = wt.astype(np.complex128)
+    wd = torch.from_numpy(wt).cuda()
+    kw = {"taper": wd} if weights == "window" else {"gains": wd}
+    for n_pol, n_time in [(1, 48), (2, 48), (1, 37)]:
+        w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=3, n_pol=n_pol, n_time=n_time, seed=60 + n_ns,
+                               n_src=2, snr=5.0)
+        v = sg.volts(w)
+        plan = plan_for(w, clamp=False, pol_sum=n_pol == 2)
+        vt = torch.from_numpy(v).cuda()
+        if n_time == 37:
+            got = bf.beamform_fft(plan, vt, kind=bf.BF_OUT_COMPLEX, **kw).cpu().numpy()
+            ref = orc.fft_beams(orc.decode_int4(v), 4, 2 * n_ns, taper=ref_wt)
+            assert got.shape == ref.shape
+            assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-5
+        else:
+            got = bf.beamform_fft(plan, vt, **kw).cpu().numpy()
+            ref = orc.beamform_fft(v, 4, 2 * n_ns, w.block, taper=ref_wt, pol_sum=n_pol == 2)
+            assert got.shape == ref.shape
+            assert rel_err(got, ref) < TOL_FP32
+        plan.close()
+
+
 def test_block_sizes():
     w = sg.custom_workload(n_ew=4, n_ns=32, n_chan=1, n_pol=1, n_time=96, seed=4)
     v = sg.volts(w)
