@@ -104,6 +104,30 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
   return (float)(int)__builtin_amdgcn_sbfe((int)d, shift, 4);
 }
 
+// Real weights h_q on the four E-W antennas of a byte-packed N-S position
+// (antenna q: real part in bits 8q+4..8q+7, imaginary in 8q..8q+3).  Beam e
+// of sum_q h_q z_q (-i)^{eq}, with s = (-1)^e, splits into
+//   Re = (h0 x0 + s h2 x2) + tr (h1 u1 + s h3 u3),
+//   Im = (h0 y0 + s h2 y2) + ti (h1 v1 + s h3 v3),
+// x, y the real and imaginary parts, (u, v) = (x, y) for even e and (y, x)
+// for odd e, tr = +1 for e < 2, ti = +1 for e in {0, 3} (-1 otherwise).
+// The lane picks u and v by the bit offset of its field, so its beam costs
+// no selects, and its signs two multiplies per position.
+struct WindowLane {
+  float s, tr, ti;
+  int ou, ov;      // bit offsets of u1 and v1 (u3, v3: 16 higher)
+};
+
+__device__ __forceinline__ WindowLane window_lane(int e) {
+  WindowLane w;
+  w.s = (e & 1) ? -1.f : 1.f;
+  w.tr = e < 2 ? 1.f : -1.f;
+  w.ti = (e == 0 || e == 3) ? 1.f : -1.f;
+  w.ou = (e & 1) ? 8 : 12;
+  w.ov = (e & 1) ? 12 : 8;
+  return w;
+}
+
 // Each wavefront works in an LDS tile of its own, and a wavefront's LDS
 // operations execute in the order it issues them: between the transpose's
 // writes and reads only the compiler's order has to be kept, with no wait
@@ -231,8 +255,10 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
 
   int wre = 0, wim = 0, wqr = 0, wqi = 0;
   TaperLane tl{};
+  WindowLane wl{};
   if constexpr (TAPER == 3) ew8_odd_weights(e1, wre, wim, wqr, wqi);
-  else if constexpr (TAPER != 0) tl = taper_lane(e1);
+  else if constexpr (TAPER == 2) tl = taper_lane(e1);
+  else if constexpr (TAPER == 1) wl = window_lane(e1);
   else ew_weights(e1, wre, wim);
 
   float acc[R2][G];
@@ -312,21 +338,18 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
             }
             x[j] = cf{re, im};
           } else {
-            float re = 0.f, im = 0.f;
+            float pr = 0.f, pi = 0.f, qr = 0.f, qi = 0.f;
 #pragma unroll
             for (int f = 0; f < FOLD; ++f) {
               const uint32_t d = cur[j + L * f];
               const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * (j + L * f)) * 4]);
-              const float hq[4] = {h.x, h.y, h.z, h.w};
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
-                const float u = tl.swap[q] ? xi : xr;
-                const float v = tl.swap[q] ? xr : xi;
-                re = fmaf(tl.sre[q] * hq[q], u, re);
-                im = fmaf(tl.sim[q] * hq[q], v, im);
-              }
+              const float h2 = wl.s * h.z, h3 = wl.s * h.w;
+              pr = fmaf(h2, nib(d, 20), fmaf(h.x, nib(d, 4), pr));
+              pi = fmaf(h2, nib(d, 16), fmaf(h.x, nib(d, 0), pi));
+              qr = fmaf(h3, nib(d, wl.ou + 16), fmaf(h.y, nib(d, wl.ou), qr));
+              qi = fmaf(h3, nib(d, wl.ov + 16), fmaf(h.y, nib(d, wl.ov), qi));
             }
+            const float re = fmaf(wl.tr, qr, pr), im = fmaf(wl.ti, qi, pi);
             x[j] = cf{re, im};
           }
         }
