@@ -253,6 +253,47 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
     return rec
 
 
+def run_chime_coadding(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict:
+    """Cyclic co-adding (fewer N-S beams than antennas): the same resident
+    voltages, 256 N-S antennas summed a mod m onto m = 128 and 64 positions
+    before an m-point transform, unclamped FP32 plans, sampled outputs against
+    the oracle's beams over all 256 antennas."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08591_amd as bf
+    import synthgen as sg
+    rng = np.random.default_rng(29)
+    frames = w.n_time * w.n_chan * w.n_pol
+    rec = {"workload": "same voltages as the headline (4x256, 2 pol, 256 chan, 16384 samples), m_ns < n_ns, no clamp"}
+    for m in (128, 64):
+        plan = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=w.m_ew, m_ns=m, n_pol=w.n_pol, n_chan=w.n_chan,
+                       block=w.block, d_over_lambda=w.d_over_lambda())
+        out = torch.empty(plan.out_shape(w.n_time), dtype=torch.float32, device=dev)
+        ms = _time_launches(lambda: bf.beamform_fft(plan, volts, out=out), 5)
+        # nominal: the m-point transform per E-W beam, the E-W DFT, the
+        # co-adding of n_ns onto m positions (2 flop per complex addition)
+        # and |B|^2 plus accumulation per beam
+        flops = frames * (w.m_ew * 5 * m * math.log2(m) + 16 * w.n_ns + 2 * w.m_ew * (w.n_ns - m)
+                          + 4 * w.m_ew * m)
+        alg = frames * w.frame_bytes + out.numel() * 4
+        r = {"kernel_ms": ms, "antenna_samples_per_s": w.antenna_samples / (ms / 1e3),
+             "vs_headline_ms": ms / fp32_ms,
+             "alu_tflops_nominal": flops / (ms / 1e3) / 1e12,
+             "alu_frac_nominal": flops / (ms / 1e3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+             "hbm_alg_gbs": alg / (ms / 1e3) / 1e9, "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        for _ in range(2):
+            blk, c, p = int(rng.integers(w.n_time // w.block)), int(rng.integers(w.n_chan)), int(rng.integers(w.n_pol))
+            checks.add(r, "max_rel_power_err_sampled", "fft_rel", out[blk, c, p].cpu().numpy(),
+                       v=sg.volts(w, blk * w.block, w.block, chans=[c], pols=[p]), m_ew=w.m_ew, m_ns=m,
+                       index=(0, 0, 0))
+        rec[f"m_ns_{m}"] = r
+        plan.close()
+        del out
+        torch.cuda.empty_cache()
+    return rec
+
+
 def run_library_fft_comparator(dev, w, volts, plan, fp32_ms: float, chunk: int = 1024) -> dict:
     """Context only, not the product: the same CHIME-shaped step written with
     torch's FFT (rocFFT) and elementwise ops on the resident voltages -- decode
@@ -693,10 +734,12 @@ def main():
                    v=sg.volts(w, blk * w.block, w.block, chans=[c], pols=[p]), m_ew=w.m_ew, m_ns=w.m_ns,
                    index=(0, 0, 0), sel=sel[c])
 
-    chime_mixed = chime_regrid = library_fft = None
+    chime_mixed = chime_regrid = library_fft = chime_coadding = None
     if not args.skip_extras:
         chime_mixed = _leg(run_chime_mixed, dev, w, volts, ms_avg, checks)
         del out
+        torch.cuda.empty_cache()
+        chime_coadding = _leg(run_chime_coadding, dev, w, volts, ms_avg, checks)
         torch.cuda.empty_cache()
         chime_regrid = _leg(run_chime_regrid, dev, w, volts, checks)
         torch.cuda.empty_cache()
@@ -709,7 +752,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.skip_extras:
         rec["extras"] = {"chime_fp16_mfma": chime_mixed, "chime_regrid": chime_regrid,
-                         "library_fft_comparator": library_fft}
+                         "chime_cyclic_coadding": chime_coadding, "library_fft_comparator": library_fft}
         rec["extras"].update(_leg(run_extras, dev, checks))
         torch.cuda.empty_cache()
     if not args.skip_cpu:
