@@ -149,6 +149,18 @@ struct Pass1Tw {
   }
 };
 
+// the same for the even columns k = 2 m only, from the unpadded L-point DFT
+// x[m] (cyclic co-adding keeps only the even outputs)
+template <int G, int M, int L, int MI>
+struct Pass1TwEven {
+  static __device__ __forceinline__ void run(const cf* x, const float* t1, const cf* c1, cf* row) {
+    constexpr int K = 2 * MI;
+    if constexpr (cmul_col(K, G, M)) row[K] = cmul(x[MI], c1[K]);
+    else row[K] = cf{fmaf(-t1[K], x[MI].i, x[MI].r), fmaf(t1[K], x[MI].r, x[MI].i)};
+    if constexpr (MI + 1 < L) Pass1TwEven<G, M, L, MI + 1>::run(x, t1, c1, row);
+  }
+};
+
 // TAPER: 0 none (E-W DFT as signed 4-bit dot products), 1 real per-antenna
 // weights h_a, 2 complex per-antenna gains g_a (float2), applied before the
 // E-W DFT, 3 none and the odd beams of the zero-padded 8-point E-W transform
@@ -182,10 +194,17 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
   constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
   constexpr int NA = N * FOLD, LA = L * FOLD;   // antennas along N-S; dwords per lane per frame
   constexpr int F = 64 / (4 * G);      // frames handled side by side
-  constexpr int R2 = (F * 4 * L2) / 64; // pass-2 tasks per lane
+  // With cyclic co-adding only the outputs A = k2 + L2 k1 with k2 even are
+  // beams: pass 1 then runs the unpadded L-point DFT (the even columns), and
+  // where the even columns' tasks tile the wavefront pass 2 takes only those
+  // (elsewhere the odd columns' tasks run on unused data and are never read).
+  constexpr bool EVEN = FOLD > 1;
+  constexpr bool REMAP = EVEN && (F * 4 * L) % 64 == 0;
+  constexpr int NCOL = REMAP ? L : L2;  // pass-2 columns per (frame, E-W beam)
+  constexpr int R2 = (F * 4 * NCOL) / 64; // pass-2 tasks per lane
   constexpr int YS = L2 + 1;           // padded LDS row, complex elements
   static_assert(F >= 1 && F * 4 * G == 64, "pass-1 lanes must fill the wavefront");
-  static_assert(R2 >= 1 && R2 * 64 == F * 4 * L2, "pass-2 tasks must tile the wavefront");
+  static_assert(R2 >= 1 && R2 * 64 == F * 4 * NCOL, "pass-2 tasks must tile the wavefront");
   static_assert(F * 4 * M * 4 <= F * 4 * G * YS * 8, "block-end sums must fit the LDS");
 
   constexpr int WPG = fft32_wpg<N, G, TAPER, FOLD>();
@@ -251,7 +270,7 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
   // pass-2 multipliers of this lane's column k2 (the same for all its tasks)
   float mu[NSL];
 #pragma unroll
-  for (int i = 0; i < NSL; ++i) mu[i] = p.mult[(lane % L2) * NSL + i];
+  for (int i = 0; i < NSL; ++i) mu[i] = p.mult[(REMAP ? 2 * (lane % L) : lane % L2) * NSL + i];
 
   int wre = 0, wim = 0, wqr = 0, wqi = 0;
   TaperLane tl{};
@@ -355,11 +374,17 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
         }
 
         // ---- pass 1: zero-padded 2L-point DFT over a2, twiddle, to LDS ----
-        cf y[L2];
-        padded_dft_t<L>(x, y);
         cf* row = &lds_y[((f1 * 4 + e1) * G + a1) * YS];
-        row[0] = y[0];
-        Pass1Tw<G, M, L2, 1>::run(y, t1, c1, row);
+        if constexpr (EVEN) {
+          dit<L>(x);
+          row[0] = x[0];
+          if constexpr (L > 1) Pass1TwEven<G, M, L, 1>::run(x, t1, c1, row);
+        } else {
+          cf y[L2];
+          padded_dft_t<L>(x, y);
+          row[0] = y[0];
+          Pass1Tw<G, M, L2, 1>::run(y, t1, c1, row);
+        }
         wave_lds_sync();
 
         // ---- pass 2: G-point DFT over a1 ----
@@ -369,7 +394,7 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
 #pragma unroll
         for (int r = 0; r < R2; ++r) {
           const int q = lane + 64 * r;
-          const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+          const int k2 = REMAP ? 2 * (q % NCOL) : q % NCOL, e = (q / NCOL) & 3, f = q / (4 * NCOL);
           const cf* col = &lds_y[(f * 4 + e) * G * YS + k2];
 #pragma unroll
           for (int j = 0; j < G; ++j) zz[r][j] = col[j * YS];
@@ -378,7 +403,7 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
 #pragma unroll
         for (int r = 0; r < R2; ++r) {
           const int q = lane + 64 * r;
-          const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+          const int k2 = REMAP ? 2 * (q % NCOL) : q % NCOL, e = (q / NCOL) & 3, f = q / (4 * NCOL);
           cf* z = zz[r];
           dit_rs<G>(z, mu);
           if constexpr (CPLX) {
@@ -421,7 +446,7 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
       const int q = lane + 64 * r;
-      const int k2 = q % L2, e = (q / L2) & 3, f = q / (4 * L2);
+      const int k2 = REMAP ? 2 * (q % NCOL) : q % NCOL, e = (q / NCOL) & 3, f = q / (4 * NCOL);
 #pragma unroll
       for (int k1 = 0; k1 < G; ++k1) lds_i[(f * 4 + e) * M + k2 + L2 * k1] = acc[r][k1];
     }

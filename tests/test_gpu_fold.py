@@ -24,7 +24,8 @@ def _plan(bf, w, m_ns, pol_sum=False):
 
 
 @pytest.mark.parametrize("n_ns,m_ns,window", [(32, 16, False), (64, 16, True), (256, 16, False),
-                                              (256, 128, True), (128, 32, False), (256, 32, True)])
+                                              (256, 128, True), (128, 32, False), (256, 32, True),
+                                              (256, 64, False), (256, 64, True)])
 def test_fold_parity(n_ns, m_ns, window):
     torch = _torch()
     import paper_1710_08591_amd as bf
@@ -56,6 +57,27 @@ def test_fold_complex_and_pol_sum():
     ref = orc.beamform_fft(v, 4, 64, 16, pol_sum=True)
     assert got.shape == ref.shape == (3, 2, 4, 64)
     assert rel_err(got, ref) < TOL_FP32
+    plan.close()
+
+
+@pytest.mark.parametrize("n_ns,m_ns", [(256, 64), (64, 16), (256, 128)])
+def test_fold_complex_even_columns(n_ns, m_ns):
+    """Complex beams with cyclic co-adding, with and without a window, and a
+    ragged last chunk (19 samples): only the even pass-1 columns are formed;
+    pass 2 takes only those at m_ns = 64 and 16, and at 128 runs the odd
+    columns' tasks on unused data whose results are never stored."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=2, n_pol=2, n_time=19, seed=7 + m_ns, n_src=2, snr=6.0)
+    v = sg.volts(w)
+    vt = torch.from_numpy(v).cuda()
+    plan = _plan(bf, w, m_ns)
+    for h in (None, sg.gaussian_taper(4, n_ns)):
+        z = bf.beamform_fft(plan, vt, kind=bf.BF_OUT_COMPLEX,
+                            taper=None if h is None else torch.from_numpy(h).cuda()).cpu().numpy()
+        zr = orc.fft_beams(orc.decode_int4(v), 4, m_ns, taper=h)
+        assert z.shape == zr.shape == (19, 2, 2, 4, m_ns)
+        assert np.max(np.abs(z - zr)) < 1e-5 * np.max(np.abs(zr))
     plan.close()
 
 
