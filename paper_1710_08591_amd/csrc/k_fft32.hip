@@ -161,14 +161,6 @@ struct Pass1TwEven {
   }
 };
 
-// TAPER: 0 none (E-W DFT as signed 4-bit dot products), 1 real per-antenna
-// weights h_a, 2 complex per-antenna gains g_a (float2), applied before the
-// E-W DFT, 3 none and the odd beams of the zero-padded 8-point E-W transform
-// (signed 4-bit dot products again).
-// FOLD > 1: cyclic co-adding (fewer beams than antennas, e:fftbeamform with
-// M < n): the N * FOLD antennas along N-S are summed onto N positions by
-// a mod N before an N-point transform, whose outputs are the even outputs
-// of the zero-padded 2N-point transform computed here.
 // Waves per workgroup.  Every wave transforms its own (block, channel,
 // polarisation group) in its own LDS tile; the variants with per-antenna
 // factors keep one table of them per workgroup, shared by its waves.  With
@@ -189,6 +181,14 @@ constexpr int fft32_wpg() {
   return 4;
 }
 
+// TAPER: 0 none (E-W DFT as signed 4-bit dot products), 1 real per-antenna
+// weights h_a, 2 complex per-antenna gains g_a (float2), applied before the
+// E-W DFT, 3 none and the odd beams of the zero-padded 8-point E-W transform
+// (signed 4-bit dot products again).
+// FOLD > 1: cyclic co-adding (fewer beams than antennas, e:fftbeamform with
+// M < n): the N * FOLD antennas along N-S are summed onto N positions by
+// a mod N before an N-point transform, whose outputs are the even outputs
+// of the zero-padded 2N-point transform (only those are computed).
 template <int N, int G, int TAPER, bool CPLX, int FOLD = 1>
 __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32(Fft32Args p) {
   constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
