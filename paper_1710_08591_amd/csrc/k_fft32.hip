@@ -82,23 +82,6 @@ __device__ __forceinline__ void ew8_odd_weights(int e, int& wpr, int& wpi, int& 
   cweights(qcr, qci, wqr, wqi);
 }
 
-struct TaperLane {
-  bool swap[4];
-  float sre[4], sim[4];
-};
-
-__device__ __forceinline__ TaperLane taper_lane(int e) {
-  TaperLane t;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int k = (e * q) & 3;
-    t.swap[q] = (k & 1) != 0;
-    t.sre[q] = (k < 2) ? 1.f : -1.f;
-    t.sim[q] = (k == 0 || k == 3) ? 1.f : -1.f;
-  }
-  return t;
-}
-
 // sign-extended 4-bit field (the builtin's result type is unsigned)
 __device__ __forceinline__ float nib(uint32_t d, int shift) {
   return (float)(int)__builtin_amdgcn_sbfe((int)d, shift, 4);
@@ -112,15 +95,20 @@ __device__ __forceinline__ float nib(uint32_t d, int shift) {
 // x, y the real and imaginary parts, (u, v) = (x, y) for even e and (y, x)
 // for odd e, tr = +1 for e < 2, ti = +1 for e in {0, 3} (-1 otherwise).
 // The lane picks u and v by the bit offset of its field, so its beam costs
-// no selects, and its signs two multiplies per position.
+// no selects, and its signs two multiplies per position.  With complex
+// gains the same split holds for w_q = g_q z_q, and the lane's choice of
+// component folds into the product: with r = +1 for odd e, -1 for even,
+//   w1u = g1r u1 + r g1i v1,   w1v = g1r v1 - r g1i u1
+// (u, v the nibbles above), and s r = -1 for every e.
 struct WindowLane {
-  float s, tr, ti;
+  float s, r, tr, ti;
   int ou, ov;      // bit offsets of u1 and v1 (u3, v3: 16 higher)
 };
 
 __device__ __forceinline__ WindowLane window_lane(int e) {
   WindowLane w;
   w.s = (e & 1) ? -1.f : 1.f;
+  w.r = (e & 1) ? 1.f : -1.f;
   w.tr = e < 2 ? 1.f : -1.f;
   w.ti = (e == 0 || e == 3) ? 1.f : -1.f;
   w.ou = (e & 1) ? 8 : 12;
@@ -189,8 +177,15 @@ constexpr int fft32_wpg() {
 // M < n): the N * FOLD antennas along N-S are summed onto N positions by
 // a mod N before an N-point transform, whose outputs are the even outputs
 // of the zero-padded 2N-point transform (only those are computed).
+// The complex-gain intensity variant below 256 N-S positions is held to 128
+// registers (four wavefronts per SIMD, the occupancy its shared table is
+// sized for; it fits without spilling, the complex-output variant does not).
+template <int N, int G, int TAPER, bool CPLX, int FOLD>
+constexpr int fft32_min_waves() { return TAPER == 2 && !CPLX && N * FOLD < 256 ? 4 : 1; }
+
 template <int N, int G, int TAPER, bool CPLX, int FOLD = 1>
-__global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32(Fft32Args p) {
+__global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>()))
+__attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>()))) void k_fft32(Fft32Args p) {
   constexpr int L = N / G, L2 = 2 * L, M = 2 * N;
   constexpr int NA = N * FOLD, LA = L * FOLD;   // antennas along N-S; dwords per lane per frame
   constexpr int F = 64 / (4 * G);      // frames handled side by side
@@ -273,11 +268,9 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
   for (int i = 0; i < NSL; ++i) mu[i] = p.mult[(REMAP ? 2 * (lane % L) : lane % L2) * NSL + i];
 
   int wre = 0, wim = 0, wqr = 0, wqi = 0;
-  TaperLane tl{};
   WindowLane wl{};
   if constexpr (TAPER == 3) ew8_odd_weights(e1, wre, wim, wqr, wqi);
-  else if constexpr (TAPER == 2) tl = taper_lane(e1);
-  else if constexpr (TAPER == 1) wl = window_lane(e1);
+  else if constexpr (TAPER == 1 || TAPER == 2) wl = window_lane(e1);
   else ew_weights(e1, wre, wim);
 
   float acc[R2][G];
@@ -341,21 +334,21 @@ __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>())) void k_fft32
             const float qr = (float)sdot8((int)d, wqr), qi = (float)sdot8((int)d, wqi);
             x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pi)};
           } else if constexpr (TAPER == 2) {
-            // z_q = g_q x_q, then the E-W twiddle (-i)^{e q} as a swap and signs
+            // w_q = g_q z_q, split as for real weights (WindowLane)
             const uint32_t d = cur[j];
             const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
             const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
-            const float gr[4] = {g01.x, g01.z, g23.x, g23.z}, gi[4] = {g01.y, g01.w, g23.y, g23.w};
-            float re = 0.f, im = 0.f;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const float xr = nib(d, 8 * q + 4), xi = nib(d, 8 * q);
-              const float zr = fmaf(xr, gr[q], -(xi * gi[q]));
-              const float zi = fmaf(xr, gi[q], xi * gr[q]);
-              re = fmaf(tl.sre[q], tl.swap[q] ? zi : zr, re);
-              im = fmaf(tl.sim[q], tl.swap[q] ? zr : zi, im);
-            }
-            x[j] = cf{re, im};
+            const float s2r = wl.s * g23.x, s2i = wl.s * g23.y;     // s g2
+            const float r1i = wl.r * g01.w;                          // r g1i
+            const float s3r = wl.s * g23.z;                          // s g3r (s r g3i = -g3i)
+            const float xr0 = nib(d, 4), xi0 = nib(d, 0), xr2 = nib(d, 20), xi2 = nib(d, 16);
+            const float u1 = nib(d, wl.ou), v1 = nib(d, wl.ov);
+            const float u3 = nib(d, wl.ou + 16), v3 = nib(d, wl.ov + 16);
+            const float pr = fmaf(-s2i, xi2, fmaf(s2r, xr2, fmaf(-g01.y, xi0, g01.x * xr0)));
+            const float pi = fmaf(s2i, xr2, fmaf(s2r, xi2, fmaf(g01.y, xr0, g01.x * xi0)));
+            const float qr = fmaf(-g23.w, v3, fmaf(s3r, u3, fmaf(r1i, v1, g01.z * u1)));
+            const float qi = fmaf(g23.w, u3, fmaf(s3r, v3, fmaf(-r1i, u1, g01.z * v1)));
+            x[j] = cf{fmaf(wl.tr, qr, pr), fmaf(wl.ti, qi, pi)};
           } else {
             float pr = 0.f, pi = 0.f, qr = 0.f, qi = 0.f;
 #pragma unroll
