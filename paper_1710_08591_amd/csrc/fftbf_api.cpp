@@ -141,7 +141,7 @@ bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
   // the transform's N: n_ns, or m_ns when folding (its padded outputs 2A are the beams)
   const int kn = folded ? d.m_ns : d.n_ns;
   p->fold = d.n_ns / kn;
-  p->g = fftbf::fft32_group(kn);
+  p->g = fftbf::fft32_group(kn, p->fold);
   p->l2 = 2 * kn / p->g;
   hipStream_t s = nullptr;
   e = hipMalloc(&p->tw, sizeof(float2) * p->g * p->l2);

@@ -138,13 +138,13 @@ struct Pass1Tw {
 };
 
 // the same for the even columns k = 2 m only, from the unpadded L-point DFT
-// x[m] (cyclic co-adding keeps only the even outputs)
+// x[m], stored at row[m] (cyclic co-adding keeps only the even outputs)
 template <int G, int M, int L, int MI>
 struct Pass1TwEven {
   static __device__ __forceinline__ void run(const cf* x, const float* t1, const cf* c1, cf* row) {
     constexpr int K = 2 * MI;
-    if constexpr (cmul_col(K, G, M)) row[K] = cmul(x[MI], c1[K]);
-    else row[K] = cf{fmaf(-t1[K], x[MI].i, x[MI].r), fmaf(t1[K], x[MI].r, x[MI].i)};
+    if constexpr (cmul_col(K, G, M)) row[MI] = cmul(x[MI], c1[K]);
+    else row[MI] = cf{fmaf(-t1[K], x[MI].i, x[MI].r), fmaf(t1[K], x[MI].r, x[MI].i)};
     if constexpr (MI + 1 < L) Pass1TwEven<G, M, L, MI + 1>::run(x, t1, c1, row);
   }
 };
@@ -160,7 +160,7 @@ struct Pass1TwEven {
 template <int N, int G, int TAPER, int FOLD>
 constexpr int fft32_wpg() {
   constexpr int kLds = 160 * 1024;
-  constexpr int tile = 64 * (2 * (N / G) + 1) * 8;   // F * 4 * G = 64 rows
+  constexpr int tile = 64 * ((FOLD > 1 ? 1 : 2) * (N / G) + 1) * 8;   // F * 4 * G = 64 rows
   constexpr int table = TAPER == 2 ? N * FOLD * 32 : TAPER == 1 ? N * FOLD * 16 : 0;
   if (table == 0) return 1;
   constexpr int want = (N * FOLD >= 256 ? 8 : 16) < kLds / tile ? (N * FOLD >= 256 ? 8 : 16) : kLds / tile;
@@ -197,7 +197,7 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
   constexpr bool REMAP = EVEN && (F * 4 * L) % 64 == 0;
   constexpr int NCOL = REMAP ? L : L2;  // pass-2 columns per (frame, E-W beam)
   constexpr int R2 = (F * 4 * NCOL) / 64; // pass-2 tasks per lane
-  constexpr int YS = L2 + 1;           // padded LDS row, complex elements
+  constexpr int YS = (EVEN ? L : L2) + 1;   // padded LDS row (only the even columns with co-adding)
   static_assert(F >= 1 && F * 4 * G == 64, "pass-1 lanes must fill the wavefront");
   static_assert(R2 >= 1 && R2 * 64 == F * 4 * NCOL, "pass-2 tasks must tile the wavefront");
   static_assert(F * 4 * M * 4 <= F * 4 * G * YS * 8, "block-end sums must fit the LDS");
@@ -388,7 +388,7 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
         for (int r = 0; r < R2; ++r) {
           const int q = lane + 64 * r;
           const int k2 = REMAP ? 2 * (q % NCOL) : q % NCOL, e = (q / NCOL) & 3, f = q / (4 * NCOL);
-          const cf* col = &lds_y[(f * 4 + e) * G * YS + k2];
+          const cf* col = &lds_y[(f * 4 + e) * G * YS + (EVEN ? k2 / 2 : k2)];
 #pragma unroll
           for (int j = 0; j < G; ++j) zz[r][j] = col[j * YS];
         }
@@ -494,23 +494,23 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
 
 }  // namespace
 
-int fft32_frames_per_pass(int n_ns) {
+int fft32_frames_per_pass(int n_ns, int fold) {
   switch (n_ns) {
     case 16: return 64 / (4 * 4);
     case 32: return 64 / (4 * 8);
     case 64: return 64 / (4 * 8);
-    case 128: return 64 / (4 * 16);
+    case 128: return 64 / (4 * (fold > 1 ? 8 : 16));
     case 256: return 64 / (4 * 16);
     default: return 0;
   }
 }
 
-int fft32_group(int n_ns) {
+int fft32_group(int n_ns, int fold) {
   switch (n_ns) {
     case 16: return 4;
     case 32: return 8;
     case 64: return 8;
-    case 128: return 16;
+    case 128: return fold > 1 ? 8 : 16;   // co-adding: two frames per pass, even columns only
     case 256: return 16;
     default: return 0;
   }
@@ -532,7 +532,7 @@ hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int6
       case 32008: return launch_fold<32, 8, 8>(b, taper, cplx, s);
       case 64002: return launch_fold<64, 8, 2>(b, taper, cplx, s);
       case 64004: return launch_fold<64, 8, 4>(b, taper, cplx, s);
-      case 128002: return launch_fold<128, 16, 2>(b, taper, cplx, s);
+      case 128002: return launch_fold<128, 8, 2>(b, taper, cplx, s);
       default: return hipErrorInvalidValue;
     }
   }

@@ -36,8 +36,9 @@ struct Fft32Args {
   int64_t n_wg;
 };
 
-int fft32_frames_per_pass(int n_ns);
-int fft32_group(int n_ns);
+// n_ns: the transform's N; fold: n_ns / m_ns of a co-adding plan (1: none)
+int fft32_frames_per_pass(int n_ns, int fold = 1);
+int fft32_group(int n_ns, int fold = 1);
 // n_ns: the transform's N (m_ns / 2, or m_ns when folding); taper: 0 none,
 // 1 real weights, 2 complex gains, 3 none with the odd E-W beams of the
 // zero-padded 8-point E-W transform
