@@ -629,3 +629,89 @@ def test_clamp_table_points_near_targets():
         target = w.m_ns * dl[c] * s
         wrapped = (target + w.m_ns / 2) % w.m_ns - w.m_ns / 2
         assert np.all(np.abs(A - wrapped) <= 0.5 + 1e-9)
+
+
+# ------------------------------------ grouping of samples into blocks -----
+
+def test_intensity_blocks_are_consecutive_samples():
+    """The time sum of eq. e:bf over n_samp consecutive samples: with
+    z[t] = (t + 1) e^{i phi_t}, block b holds sum_{t=16b}^{16b+15} (t + 1)^2,
+    i.e. S(16b + 16) - S(16b) with S(n) = n (n + 1) (2n + 1) / 6.  Every block
+    differs, so a grouping of strided samples (or any other grouping) fails."""
+    nb, blk = 6, 16
+    t = np.arange(nb * blk)
+    ph = np.random.default_rng(21).uniform(0, 2 * np.pi, t.size)
+    z = ((t + 1) * np.exp(1j * ph))[:, None] * np.array([[1.0, 0.5]])       # two series
+    got = orc.intensity(z, blk)
+    S = lambda n: n * (n + 1) * (2 * n + 1) / 6
+    ref = np.array([S(blk * b + blk) - S(blk * b) for b in range(nb)])
+    assert got.shape == (nb, 2)
+    assert np.array_equal(got[:, 0], ref) and np.allclose(got[:, 1], ref / 4, rtol=1e-15)
+    assert np.array_equal(orc.accumulate_intensity(z, blk)[:, 0], ref)
+
+
+def test_beam_intensity_blocks_follow_the_samples():
+    """Through the whole oracle: every antenna carries the same int4 value c_t
+    (a source at y = 0 on both axes), so beam (0, 0) is n^-1/2 n c_t and its
+    block intensity is n sum_{t in block} |c_t|^2 over consecutive t; the
+    other E-W beams are exactly zero (unpadded axis), and the N-S row sums to
+    2 n sum |c_t|^2 (Parseval with M = 2n).  c_t is a different value in
+    every sample, so a block built from other samples fails."""
+    n_ew, n_ns, nb, blk = 4, 16, 5, 16
+    nt = nb * blk
+    t = np.arange(nt)
+    re = (t * 5) % 15 - 7
+    im = (t * 3 + 1) % 13 - 6
+    byte = sg.pack_nibbles(re, im)
+    v = np.broadcast_to(byte[:, None, None, None, None], (nt, 1, 1, n_ns, n_ew)).copy()
+    got = orc.beamform_fft(v, 4, 2 * n_ns, blk)[:, 0, 0]                # [blk][4][32]
+    p = (re.astype(np.float64) ** 2 + im.astype(np.float64) ** 2)
+    ref = np.array([n_ew * n_ns * p[b * blk:(b + 1) * blk].sum() for b in range(nb)])
+    assert np.allclose(got[:, 0, 0], ref, rtol=1e-12)
+    assert np.all(np.abs(got[:, 1:, :]) < 1e-9 * ref.max())
+    assert np.allclose(got[:, 0, :].sum(axis=1), 2 * ref, rtol=1e-12)
+    assert len(set(ref.tolist())) == nb
+
+
+# ------------------------------------------- per-channel d / lambda -------
+
+def _two_channel_volts(nt=16):
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=2, n_pol=2, n_time=nt, seed=41, snr=5.0)
+    return w, sg.volts(w)
+
+
+def test_tied_beams_use_each_channels_own_d_over_lambda():
+    """eq. e:c_pointed at y = (d/lambda)_c n: one direction lands on a
+    different FFT beam in each channel.  Two slices taken from channels 2 and 1
+    of a four-channel table (in that order); at n = (1/2, 1/2) channel 1
+    (d/lambda = (1/2, 1/2)) has y = (1/4, 1/4) -> beam (1, 8) of 4 x 32 and
+    channel 2 (d/lambda = (1, 3/4)) has y = (1/2, 3/8) -> beam (2, 12).  An
+    on-grid pointing reproduces the FFT beam exactly (the zero-padded inverse
+    transform), so each slice must equal its own channel's beam."""
+    w, v = _two_channel_volts()
+    dl = np.array([[9.0, 9.0], [0.5, 0.5], [1.0, 0.75], [3.0, 3.0]])
+    chans = [2, 1]
+    dircos = np.array([[0.5, 0.5]])
+    tb = orc.tied_beams(v, dircos, dl, chans=chans)[..., 0]              # [t][2][pol]
+    fb = orc.fft_beams(orc.decode_int4(v), 4, 32)                         # [t][2][pol][4][32]
+    assert np.allclose(tb[:, 0], fb[:, 0, :, 2, 12], atol=1e-11)
+    assert np.allclose(tb[:, 1], fb[:, 1, :, 1, 8], atol=1e-11)
+    assert not np.allclose(tb[:, 0], fb[:, 0, :, 1, 8], atol=1e-3)
+    ti = orc.tied_intensity(v, dircos, dl, 16, chans=chans)[..., 0]
+    assert np.allclose(ti[0, 0], (np.abs(fb[:, 0, :, 2, 12]) ** 2).sum(axis=0), rtol=1e-11)
+
+
+def test_localize_uses_each_channels_own_d_over_lambda():
+    """Sec. "Localization" per channel: a noise-free source at y_c in each of
+    two channel slices (from channels 3 and 0 of a table with different N-S
+    d/lambda) is found at sin(theta) = y_c / (d/lambda)_c of its own channel."""
+    n, m = 16, 32
+    dl_ns = np.array([0.4, 0.9, 0.3, 0.7])
+    chans = [3, 0]
+    ys = [0.1234, -0.2011]
+    rows = np.stack([_point_source_beams(n, m, y, 2.0) for y in ys])     # [2][m]
+    x = rows[None, :, None, :]                                            # [blk][chan][pol][m]
+    st, pk = orc.localize(x, n, dl_ns, m, 8, chans=chans)
+    for c in range(2):
+        assert abs(st[0, c, 0] - ys[c] / dl_ns[chans[c]]) < 1e-11
+        assert abs(pk[0, c, 0] - n * 4.0) < 1e-9 * n * 4.0
