@@ -81,49 +81,121 @@ class OracleChecks:
     def __init__(self):
         self.items = []
 
-    def add(self, rec: dict, key: str, kind: str, got, **args):
+    def add(self, rec: dict, key: str, kind: str, got, n_slices: int = 1, **args):
         import numpy as np
         rec.setdefault(key, None)
-        self.items.append((rec, key, kind, np.asarray(got, dtype=np.float64), args))
+        self.items.append((rec, key, kind, np.asarray(got, dtype=np.float64), dict(args, n_slices=n_slices)))
+
+    def add_blocks(self, rec: dict, key: str, out, w, blocks=None, **ref_args):
+        """Whole blocks of a CHIME-shaped output (every channel and both
+        polarisations, each channel's own clamp table), the first and the last
+        by default."""
+        blocks = (0, w.n_time // w.block - 1) if blocks is None else blocks
+        for blk in blocks:
+            self.add(rec, key, "fft_rel", out[blk].cpu().numpy(), n_slices=w.n_chan * w.n_pol,
+                     v=host_block(w, blk), m_ew=w.m_ew, m_ns=w.m_ns, ns_select=w.ns_select(), index=(0,),
+                     **ref_args)
 
 
-def cpu_baseline(seconds: float = 15.0, checks: "OracleChecks | None" = None):
+_HOST_BLOCKS = {}
+
+
+def host_block(w, blk: int):
+    """One whole block of the workload's voltages (every channel and
+    polarisation) on the host, from the seeded generator; kept for reuse."""
+    import synthgen as sg
+    key = (repr(w), blk)
+    if key not in _HOST_BLOCKS:
+        _HOST_BLOCKS[key] = sg.volts(w, blk * w.block, w.block)
+    return _HOST_BLOCKS[key]
+
+
+def _host_statement() -> dict:
+    """What the oracle ran on: CPU model, logical CPUs, the CPUs this process
+    may use, the thread variables of the environment and the BLAS pools."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = None
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS",
+                                          "BLIS_NUM_THREADS", "NUMEXPR_NUM_THREADS")}
+    try:
+        from threadpoolctl import threadpool_info
+        pools = [{"api": i.get("internal_api"), "threads": i.get("num_threads"), "version": i.get("version")}
+                 for i in threadpool_info()]
+    except Exception:
+        pools = []
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": affinity, "thread_env": env,
+            "blas_pools": pools}
+
+
+def cpu_baseline(seconds: float = 15.0, checks: "OracleChecks | None" = None, seconds_1t: float = 8.0):
     """The FP64 oracle: timed on a bounded slice of the same workload on the
-    host cores, then compared with every sampled GPU output in ``checks``."""
+    host cores (all BLAS threads, then one thread on the first of the same
+    slices), then compared with every sampled GPU output in ``checks``."""
     import numpy as np
 
     import oracle as orc
     import synthgen as sg
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    host = _host_statement()
+    cores = max([p["threads"] or 1 for p in host["blas_pools"]] or [1])
     w = sg.make_workload("c2")
     sel = w.ns_select()
     chunk = 1024
-    done = 0
+    slices = []
+
+    def one(k):
+        c = (37 * k) % w.n_chan
+        p = k % w.n_pol
+        t_lo = (k * chunk) % w.n_time
+        if k == len(slices):
+            slices.append(sg.volts(w, t_lo, chunk, chans=[c], pols=[p]))
+        ts = time.perf_counter()
+        i = orc.beamform_fft(slices[k], w.m_ew, w.m_ns, w.block)[..., sel[c]]
+        dt = time.perf_counter() - ts
+        assert i.shape == (chunk // 16, 1, 1, 4, 256)
+        return dt
+
     n_cp = 0
-    t0 = time.perf_counter()
     elapsed = 0.0
     while elapsed < seconds:
-        c = (37 * n_cp) % w.n_chan
-        p = n_cp % w.n_pol
-        t_lo = (n_cp * chunk) % w.n_time
-        v = sg.volts(w, t_lo, chunk, chans=[c], pols=[p])
-        ts = time.perf_counter()
-        i = orc.beamform_fft(v, w.m_ew, w.m_ns, w.block)[..., sel[c]]
-        elapsed += time.perf_counter() - ts
-        assert i.shape == (chunk // 16, 1, 1, 4, 256)
-        done += chunk * w.n_ant
+        elapsed += one(n_cp)
         n_cp += 1
+    done = n_cp * chunk * w.n_ant
+    # one thread, on the first slices of the same list
+    n_1t = 0
+    el_1t = 0.0
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            while el_1t < seconds_1t and n_1t < n_cp:
+                el_1t += one(n_1t)
+                n_1t += 1
+        rate_1t = n_1t * chunk * w.n_ant / el_1t
+    except Exception:
+        rate_1t = None
+    slices.clear()
     rec = {"value": done / elapsed, "unit": "antenna-samples/s", "cores": int(cores), "kind": "oracle",
            "sample": f"{n_cp} slices of {chunk} samples x 1 channel x 1 pol of the 4x256 lattice "
-                     f"({done} antenna-samples, {elapsed:.1f} s of oracle time, generation excluded)"}
+                     f"({done} antenna-samples, {elapsed:.1f} s of oracle time, generation excluded)",
+           "value_1_thread": rate_1t,
+           "sample_1_thread": f"the first {n_1t} of the same slices with the BLAS pools limited to one thread "
+                              f"({el_1t:.1f} s)",
+           **host}
 
     def reference(kind, a):
         if kind == "fft_rel":
-            r = orc.beamform_fft(a["v"], a["m_ew"], a["m_ns"], 16, taper=a.get("taper"))[a.get("index", ())]
+            r = orc.beamform_fft(a["v"], a["m_ew"], a["m_ns"], 16, taper=a.get("taper"),
+                                 ns_select=a.get("ns_select"))[a.get("index", ())]
             return r if a.get("sel") is None else r[..., a["sel"]]
         if kind == "tied_rel":
             r = orc.tied_intensity(a["v"], a["dircos"], a["dl"], 16, chans=[a["c"]])[0, 0]
@@ -158,7 +230,7 @@ def cpu_baseline(seconds: float = 15.0, checks: "OracleChecks | None" = None):
         else:
             err = float(np.max(np.abs(got - ref) / ref))
         target[key] = err if target.get(key) is None else max(target[key], err)
-        n_checked += 1
+        n_checked += a["n_slices"]
     rec["parity_slices_checked"] = n_checked
     return rec
 
@@ -205,6 +277,7 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
     rng = np.random.default_rng(3)
     sel = w.ns_select()
     rec = {}
+    checks.add_blocks(rec, "max_rel_power_err_sampled", out, w)
     for _ in range(4):
         blk, c, p = int(rng.integers(1024)), int(rng.integers(256)), int(rng.integers(2))
         checks.add(rec, "max_rel_power_err_sampled", "fft_rel", out[blk, c, p].cpu().numpy(),
@@ -220,6 +293,8 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
     g_ms = _time_launches(lambda: bf.beamform_fft(plan32, volts, out=out, gains=g_dev), 5)
     gains_rec = {"kernel_ms": g_ms, "antenna_samples_per_s": w.antenna_samples / (g_ms / 1e3),
                  "slowdown_vs_no_gains": g_ms / fp32_ms}
+    checks.add_blocks(gains_rec, "max_rel_power_err_sampled", out, w, blocks=(0,),
+                      taper=gains.astype(np.complex64).astype(np.complex128))
     for _ in range(2):
         blk, c, p = int(rng.integers(1024)), int(rng.integers(256)), int(rng.integers(2))
         checks.add(gains_rec, "max_rel_power_err_sampled", "fft_rel", out[blk, c, p].cpu().numpy(),
@@ -231,6 +306,8 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
     h_ms = _time_launches(lambda: bf.beamform_fft(plan32, volts, out=out, taper=h_dev), 5)
     window_rec = {"kernel_ms": h_ms, "antenna_samples_per_s": w.antenna_samples / (h_ms / 1e3),
                   "slowdown_vs_no_window": h_ms / fp32_ms}
+    checks.add_blocks(window_rec, "max_rel_power_err_sampled", out, w, blocks=(0,),
+                      taper=np.asarray(h, dtype=np.float64))
     for _ in range(2):
         blk, c, p = int(rng.integers(1024)), int(rng.integers(256)), int(rng.integers(2))
         checks.add(window_rec, "max_rel_power_err_sampled", "fft_rel", out[blk, c, p].cpu().numpy(),
@@ -722,9 +799,11 @@ def main():
     }
     # sampled slices of the headline output; the oracle leg fills in the error
     checks = OracleChecks()
-    rec["parity"] = {"reference": "FP64 oracle (direct phased sums), 4 sampled (block, channel, pol) slices "
-                                  "of the timed output, all 1024 kept beams each",
+    rec["parity"] = {"reference": "FP64 oracle (direct phased sums): every channel and pol of the first and the "
+                                  "last block of the timed output (each channel's own clamp table) and 4 random "
+                                  "(block, channel, pol) slices, all 1024 kept beams each",
                      "tolerance": 1e-5}
+    checks.add_blocks(rec["parity"], "max_rel_power_err_sampled", out, w)
     prng = np.random.default_rng(11)
     sel = w.ns_select()
     for _ in range(4):

@@ -46,3 +46,26 @@ def test_failing_side_measurement_is_reported_not_raised():
     def boom():
         raise RuntimeError("no device")
     assert bench._leg(boom) == {"error": "RuntimeError: no device"}
+
+
+def test_whole_block_checks_use_each_channels_clamp_table():
+    """add_blocks compares every channel and polarisation of whole blocks,
+    each channel with its own kept beams; a perturbation of one channel's
+    slice is what the oracle leg reports, and the CPU statement is filled in."""
+    import torch
+    w = sg.custom_workload(n_ew=4, n_ns=8, n_chan=3, n_pol=2, n_time=32, seed=9, n_ns_keep=8, dl=(0.4, 0.8))
+    v = sg.volts(w)
+    sel = w.ns_select()
+    assert not all(np.array_equal(sel[0], sel[c]) for c in range(3))
+    ref = orc.beamform_fft(v, 4, 16, 16, ns_select=sel)                       # [2][3][2][4][8]
+    got = ref.copy()
+    got[1, 2, 1] *= 1 + 5e-7
+    checks = bench.OracleChecks()
+    rec = {}
+    checks.add_blocks(rec, "err", torch.from_numpy(got), w)
+    out = bench.cpu_baseline(0.05, checks, seconds_1t=0.05)
+    assert out["parity_slices_checked"] == 2 * 3 * 2
+    assert abs(rec["err"] - 5e-7) < 1e-12
+    assert out["value_1_thread"] is None or out["value_1_thread"] > 0
+    for k in ("cpu_model", "nproc", "cpus_allowed", "thread_env", "blas_pools"):
+        assert k in out

@@ -18,7 +18,7 @@ import pytest
 
 import oracle as orc
 import synthgen as sg
-from tests.helpers import TOL_FP32, rel_err
+from tests.helpers import TOL_FP32, by_time_chunks, c2_wide_regions, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -279,11 +279,38 @@ def test_regrid_empty_and_validation():
     plan.close()
 
 
+def _c2_regrid_wide(w, v, got, weights_for):
+    """(largest error over 1e-5 sum_A |w^A| b_A, largest per-beam relative
+    error) of regridded CHIME-shaped outputs ``got`` [blk][chan][pol][4][T]
+    over the full-size comparison set; the reference is the oracle's
+    regridding (weights_for(channel) -> [T][M]) of its own FFT-beam
+    intensities."""
+    prop = beam = 0.0
+    cache = {}
+    for idx, vs, chans in c2_wide_regions(w, v):
+        b = by_time_chunks(lambda x: orc.beamform_fft(x, 4, 512, 16), vs)     # [nb][nc][pol][4][512]
+        g = got[idx].cpu().numpy()
+        for ci, c in enumerate(chans):
+            if c not in cache:
+                cache[c] = weights_for(int(c))
+            W = cache[c]
+            ref = orc.regrid_intensity(b[:, ci], W)
+            scale = orc.regrid_intensity(b[:, ci], np.abs(W))
+            d = np.abs(g[:, ci] - ref)
+            prop = max(prop, float(np.max(d / (TOL_FP32 * scale))))
+            beam = max(beam, float(np.max(d / ref)))
+    return prop, beam
+
+
 def test_regrid_c2_shape_sampled():
     """CHIME-shaped lattice (4 x 256, 256 channels, 2 pols, 16384 samples), all
     512 N-S beams regridded to 256 achromatic targets, in the launch
-    configuration the benchmark times; sampled (block, channel) outputs against
-    direct phased beams."""
+    configuration the benchmark times.  Sampled (block, channel) outputs
+    against direct phased beams, and the full-size comparison set (every
+    channel and both polarisations of the first and the last block, one
+    channel over all blocks) against the oracle's regridding of its own
+    FFT-beam intensities.  The bar is the propagated FP32 bar; the per-beam
+    relative error is printed beside it."""
     torch = _torch()
     import paper_1710_08591_amd as bf
     w = sg.make_workload("c2")
@@ -292,9 +319,9 @@ def test_regrid_c2_shape_sampled():
     rg = bf.Regrid(plan, st)
     v = sg.volts(w, backend="torch", device="cuda")
     fft_i = bf.beamform_fft(plan, v)
-    del v
     got = rg(fft_i)
     torch.cuda.synchronize()
+    del fft_i
     assert got.shape == (1024, 256, 2, 4, 256)
     rng = np.random.default_rng(4)
     picks = [(0, 0), (1023, 255)] + [(int(rng.integers(1024)), int(rng.integers(256))) for _ in range(3)]
@@ -305,12 +332,16 @@ def test_regrid_c2_shape_sampled():
         dircos = np.stack([e / (4 * dl[c, 0]), np.tile(st, 4)], axis=1)
         ref = orc.tied_intensity(vs, dircos, dl, 16, chans=[c])[0, 0].reshape(2, 4, len(st))
         b = orc.beamform_fft(vs, 4, 512, 16)[0, 0]                              # [pol][4][512]
-        W = np.stack([orc.regrid_weights_paper(256, 512, dl[c, 1] * s) for s in st])
+        W = orc.regrid_weights_paper(256, 512, dl[c, 1] * st[:, None])          # [T][512]
         scale = b @ np.abs(W).T
         assert np.all(np.abs(got[blk, c].cpu().numpy() - ref) <= TOL_FP32 * scale)
+    prop, beam = _c2_regrid_wide(w, v, got, lambda c: orc.regrid_weights_paper(256, 512, dl[c, 1] * st[:, None]))
+    print(f"4x256 regrid to 256 targets, full size: error / (1e-5 sum|w|b) {prop:.3f}, "
+          f"max per-beam rel error {beam:.3e}")
+    assert prop <= 1.0
     rg.close()
     plan.close()
-    del fft_i, got
+    del v, got
     torch.cuda.empty_cache()
 
 
