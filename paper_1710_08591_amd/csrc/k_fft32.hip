@@ -468,10 +468,20 @@ void launch_nt(const Fft32Args& a, bool cplx, hipStream_t s) {
   else hipLaunchKernelGGL((k_fft32<N, G, T, false, FOLD>), grid, threads, 0, s, a);
 }
 
+// The one choice of the group size G for each transform length N (and fold):
+// the launches below take it as a template argument and the plan sizes its
+// pass-1 twiddle and pass-2 multiplier tables with it (fft32_group).
+// Co-adding at N = 128 uses G = 8, two frames per pass, so that the even
+// columns' pass-2 tasks tile the wavefront.
+constexpr int fft32_g(int n, int fold) {
+  return n == 16 ? 4 : n == 32 ? 8 : n == 64 ? 8 : n == 128 ? (fold > 1 ? 8 : 16) : n == 256 ? 16 : 0;
+}
+
 // cyclic co-adding: no window, or a real window for folds up to 8 (the
 // 16-fold windowed variant would not fit its registers)
-template <int N, int G, int FOLD>
+template <int N, int FOLD>
 hipError_t launch_fold(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
+  constexpr int G = fft32_g(N, FOLD);
   if (taper == 0) {
     launch_nt<N, G, 0, FOLD>(a, cplx, s);
   } else if (taper == 1) {
@@ -483,8 +493,9 @@ hipError_t launch_fold(const Fft32Args& a, int taper, bool cplx, hipStream_t s) 
   return hipGetLastError();
 }
 
-template <int N, int G>
+template <int N>
 hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
+  constexpr int G = fft32_g(N, 1);
   if (taper == 3) launch_nt<N, G, 3>(a, cplx, s);
   else if (taper == 2) launch_nt<N, G, 2>(a, cplx, s);
   else if (taper == 1) launch_nt<N, G, 1>(a, cplx, s);
@@ -494,27 +505,7 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
 
 }  // namespace
 
-int fft32_frames_per_pass(int n_ns, int fold) {
-  switch (n_ns) {
-    case 16: return 64 / (4 * 4);
-    case 32: return 64 / (4 * 8);
-    case 64: return 64 / (4 * 8);
-    case 128: return 64 / (4 * (fold > 1 ? 8 : 16));
-    case 256: return 64 / (4 * 16);
-    default: return 0;
-  }
-}
-
-int fft32_group(int n_ns, int fold) {
-  switch (n_ns) {
-    case 16: return 4;
-    case 32: return 8;
-    case 64: return 8;
-    case 128: return fold > 1 ? 8 : 16;   // co-adding: two frames per pass, even columns only
-    case 256: return 16;
-    default: return 0;
-  }
-}
+int fft32_group(int n_ns, int fold) { return fft32_g(n_ns, fold); }
 
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s) {
@@ -523,25 +514,25 @@ hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int6
   if (b.fold > 1) {
     const int key = n_ns * 1000 + b.fold;
     switch (key) {
-      case 16002: return launch_fold<16, 4, 2>(b, taper, cplx, s);
-      case 16004: return launch_fold<16, 4, 4>(b, taper, cplx, s);
-      case 16008: return launch_fold<16, 4, 8>(b, taper, cplx, s);
-      case 16016: return launch_fold<16, 4, 16>(b, taper, cplx, s);
-      case 32002: return launch_fold<32, 8, 2>(b, taper, cplx, s);
-      case 32004: return launch_fold<32, 8, 4>(b, taper, cplx, s);
-      case 32008: return launch_fold<32, 8, 8>(b, taper, cplx, s);
-      case 64002: return launch_fold<64, 8, 2>(b, taper, cplx, s);
-      case 64004: return launch_fold<64, 8, 4>(b, taper, cplx, s);
-      case 128002: return launch_fold<128, 8, 2>(b, taper, cplx, s);
+      case 16002: return launch_fold<16, 2>(b, taper, cplx, s);
+      case 16004: return launch_fold<16, 4>(b, taper, cplx, s);
+      case 16008: return launch_fold<16, 8>(b, taper, cplx, s);
+      case 16016: return launch_fold<16, 16>(b, taper, cplx, s);
+      case 32002: return launch_fold<32, 2>(b, taper, cplx, s);
+      case 32004: return launch_fold<32, 4>(b, taper, cplx, s);
+      case 32008: return launch_fold<32, 8>(b, taper, cplx, s);
+      case 64002: return launch_fold<64, 2>(b, taper, cplx, s);
+      case 64004: return launch_fold<64, 4>(b, taper, cplx, s);
+      case 128002: return launch_fold<128, 2>(b, taper, cplx, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (n_ns) {
-    case 16: return launch_n<16, 4>(b, taper, cplx, s);
-    case 32: return launch_n<32, 8>(b, taper, cplx, s);
-    case 64: return launch_n<64, 8>(b, taper, cplx, s);
-    case 128: return launch_n<128, 16>(b, taper, cplx, s);
-    case 256: return launch_n<256, 16>(b, taper, cplx, s);
+    case 16: return launch_n<16>(b, taper, cplx, s);
+    case 32: return launch_n<32>(b, taper, cplx, s);
+    case 64: return launch_n<64>(b, taper, cplx, s);
+    case 128: return launch_n<128>(b, taper, cplx, s);
+    case 256: return launch_n<256>(b, taper, cplx, s);
     default: return hipErrorInvalidValue;
   }
 }

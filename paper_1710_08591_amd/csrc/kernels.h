@@ -36,8 +36,8 @@ struct Fft32Args {
   int64_t n_wg;
 };
 
-// n_ns: the transform's N; fold: n_ns / m_ns of a co-adding plan (1: none)
-int fft32_frames_per_pass(int n_ns, int fold = 1);
+// group size G of the transform of length n_ns (fold: n_ns / m_ns of a
+// co-adding plan, 1 for none); 0 for an unsupported length
 int fft32_group(int n_ns, int fold = 1);
 // n_ns: the transform's N (m_ns / 2, or m_ns when folding); taper: 0 none,
 // 1 real weights, 2 complex gains, 3 none with the odd E-W beams of the

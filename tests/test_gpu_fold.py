@@ -24,8 +24,9 @@ def _plan(bf, w, m_ns, pol_sum=False):
 
 
 @pytest.mark.parametrize("n_ns,m_ns,window", [(32, 16, False), (64, 16, True), (256, 16, False),
-                                              (256, 128, True), (128, 32, False), (256, 32, True),
-                                              (256, 64, False), (256, 64, True)])
+                                              (256, 128, True), (256, 128, False), (128, 32, False),
+                                              (256, 32, True), (256, 64, False), (256, 64, True),
+                                              (128, 16, False), (128, 16, True), (64, 32, False)])
 def test_fold_parity(n_ns, m_ns, window):
     torch = _torch()
     import paper_1710_08591_amd as bf
@@ -60,12 +61,13 @@ def test_fold_complex_and_pol_sum():
     plan.close()
 
 
-@pytest.mark.parametrize("n_ns,m_ns", [(256, 64), (64, 16), (256, 128)])
+@pytest.mark.parametrize("n_ns,m_ns", [(256, 64), (64, 16), (256, 128), (64, 32)])
 def test_fold_complex_even_columns(n_ns, m_ns):
     """Complex beams with cyclic co-adding, with and without a window, and a
     ragged last chunk (19 samples): only the even pass-1 columns are formed;
-    pass 2 takes only those at m_ns = 64 and 16, and at 128 runs the odd
-    columns' tasks on unused data whose results are never stored."""
+    pass 2 takes only those at m_ns = 16, 64 and 128 (at 128 with G = 8, two
+    frames per pass), and at m_ns = 32 runs the odd columns' tasks on unused
+    data whose results are never stored."""
     torch = _torch()
     import paper_1710_08591_amd as bf
     w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=2, n_pol=2, n_time=19, seed=7 + m_ns, n_src=2, snr=6.0)
