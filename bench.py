@@ -314,13 +314,14 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
                    v=sg.volts(w, blk * 16, 16, chans=[c], pols=[p]), m_ew=w.m_ew, m_ns=w.m_ns,
                    index=(0, 0, 0), sel=sel[c], taper=np.asarray(h, dtype=np.float64))
     plan32.close()
-    # MFMA work issued per sample frame: 4 E-W beams x (stage 1: 2 terms x [64 x 32] over 16 a1
-    # + stage 2: 3 products of [32 x 32] over 32 k2), 2 flop per multiply-add
+    # MFMA work issued per sample frame: 4 E-W beams x 2 beam tiles x (Re, Im) x 2 coefficient terms of
+    # v_mfma_f32_16x16x32_f16 (16 x 16 x 32 multiply-adds, 2 flop each)
     frames = w.n_time * w.n_chan * w.n_pol
-    mfma_flops = frames * 4 * (2 * 64 * 32 * 16 + 3 * 32 * 32 * 32) * 2
+    mfma_flops = frames * 4 * 2 * 2 * 2 * (16 * 16 * 32 * 2)
     plan.close()
     rec.update({"workload": "same as the headline (4x256, 2 pol, 256 chan, 16384 samples, clamp 256)",
-                "precision": "fp16 mfma: exact int inputs, two-term coefficients in stage 1; stage 2 with two-term data and coefficients (three products)",
+                "precision": "fp16 mfma for stage 1 of 512 = 32 x 16 (exact int E-W sums, two-term coefficients, fp32 "
+                             "accumulation); twiddle and 16-point stage 2 in fp32",
                 "kernel_ms": ms, "antenna_samples_per_s": w.antenna_samples / (ms / 1e3),
                 "speedup_vs_fp32": fp32_ms / ms,
                 "hbm_alg_gbs": alg / (ms / 1e3) / 1e9, "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,

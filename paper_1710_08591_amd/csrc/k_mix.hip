@@ -36,9 +36,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kPrecFp16 = 1;
 constexpr int kPrecFp8 = 2;
 constexpr int kMixBlocksPerWave = 4;
-#ifndef MIX256_TERMS
-#define MIX256_TERMS 3
-#endif
 
 template <int PREC> struct Mix;
 template <> struct Mix<kPrecFp16> {
@@ -297,188 +294,6 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
   }
 }
 
-// ---- 4 x 256 lattice: the N-S transform 512 = 32 x 16 in two MFMA stages ----
-// a = a1 + 16 a2, A = k2 + 32 k1 (a1, a2, k1 in [0, 16), k2 in [0, 32)):
-//   stage 1: Y[a1][k2] = sum_{a2} x[a1 + 16 a2] W_32^{k2 a2}   (the padded
-//            16 -> 32 DFT, exact int inputs, FP16 hi + lo coefficients: the
-//            same operand table as the 4 x 16 kernel, with a2 for a_ns)
-//   twiddle: Y'[a1][k2] = Y[a1][k2] W_512^{a1 k2}            (FP32, in-lane)
-//   stage 2: B[k2 + 32 k1] = sum_{a1} W_16^{k1 a1} Y'[a1][k2]  (Y' rounded to
-//            FP16, optionally with its residual as a second term)
-// Stage 1 runs per sample as C[a1][k2] = A[a1][(re|im, a2)] B[(re|im, a2)][k2];
-// its accumulator already holds, in lane (k2, g), the rows a1 = 4g..4g+3 that
-// stage 2 needs as its data operand B[(a1, re|im)][k2], so the data never
-// leaves the registers between the stages.  With a1 on the matrix rows the
-// E-W 4-point DFT goes first (exact integer sums of at most 32 in magnitude,
-// FP16-exact), as two signed 4-bit dot products per N-S position and beam.
-constexpr size_t kMix256T2Off = 8192;            // bytes: stage-1 table, 2 terms
-constexpr size_t kMix256TwOff = 8192 + 4096;     // stage-2 table, 2 terms
-constexpr size_t kMix256Bytes = 8192 + 4096 + 4096;
-
-__global__ void k_mix256_tables(void* tab) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  // stage-2 operand A[k1][(a1, re|im)] of W_16^{k1 a1}, [term 2][part 2][lane 64][8]
-  if (i < 2 * 64 * 8) {
-    const int j = i & 7, lane = (i >> 3) & 63, part = i >> 9;
-    const int k1 = lane & 15, g = lane >> 4, a1 = 4 * g + (j >> 1), comp = j & 1;
-    double sn, cs;
-    sincospi(2.0 * (double)((k1 * a1) & 15) / 16.0, &sn, &cs);   // theta = 2 pi k1 a1 / 16
-    // W = cos - i sin:  Re(W y) = cos yr + sin yi,  Im(W y) = -sin yr + cos yi
-    const double v = part == 0 ? (comp == 0 ? cs : sn) : (comp == 0 ? -sn : cs);
-    _Float16* t = reinterpret_cast<_Float16*>(static_cast<char*>(tab) + kMix256T2Off);
-    const _Float16 hi = (_Float16)(float)v;
-    t[i] = hi;
-    t[1024 + i] = (_Float16)(float)(v - (double)(float)hi);
-  }
-  // twiddles W_512^{a1 k2} for lane (k2 = 16 kt + lane % 16, a1 = 4 (lane / 16) + q): [lane][kt][q]
-  if (i < 64 * 2 * 4) {
-    const int q = i & 3, kt = (i >> 2) & 1, lane = i >> 3;
-    const int k2 = kt * 16 + (lane & 15), a1 = 4 * (lane >> 4) + q;
-    double sn, cs;
-    sincospi(-2.0 * (double)((a1 * k2) & 511) / 512.0, &sn, &cs);
-    float2* w = reinterpret_cast<float2*>(static_cast<char*>(tab) + kMix256TwOff);
-    w[i] = make_float2((float)cs, (float)sn);
-  }
-}
-
-__device__ __forceinline__ __attribute__((unused)) half8 pack8(const float* v) {
-  half8 h;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) h[j] = (_Float16)v[j];
-  return h;
-}
-
-template <int P2>
-__global__ __launch_bounds__(64) void k_mix256(MixArgs a) {
-  constexpr int N = 256, M = 512;
-  __shared__ float lds_i[4 * M];
-  const int lane = threadIdx.x;
-  const int n = lane & 15, g = lane >> 4;
-  int wg = blockIdx.x;
-  const int pg = wg % a.n_pg;
-  wg /= a.n_pg;
-  const int chan = wg % a.n_chan;
-  const int blk = wg / a.n_chan;
-
-  const char* tab = static_cast<const char*>(a.mat);
-  half8 B1[2][2][2], A2[2][2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-      for (int part = 0; part < 2; ++part) B1[p][kt][part] = load_b<kPrecFp16>(tab, p, kt, part, lane);
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int part = 0; part < 2; ++part)
-      A2[p][part] = *reinterpret_cast<const half8*>(tab + kMix256T2Off + ((p * 2 + part) * 64 + lane) * 16);
-  cf tw[2][4];
-  {
-    const float2* w = reinterpret_cast<const float2*>(tab + kMix256TwOff) + lane * 8;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) tw[k >> 2][k & 3] = cf{w[k].x, w[k].y};
-  }
-  // E-W dot8 weights for this lane's component (g >> 1) of each E-W beam
-  int wts[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) wts[e] = ew_dot_weights(e, g >> 1);
-
-  float acc[4][2][4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[e][kt][q] = 0.f;
-
-  const int pol_lo = (a.pol_iter == 1) ? pg : 0;
-  const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
-  const int64_t frame_stride = (int64_t)a.n_chan * a.n_pol * N;   // dwords per sample
-  const int pos0 = n + 16 * 8 * (g & 1);                            // a1 + 16 a2 for j = 0
-
-  for (int pol = pol_lo; pol < pol_hi; ++pol) {
-    const uint32_t* src = a.volts + ((int64_t)chan * a.n_pol + pol) * N + pos0;
-    const int64_t t0 = (int64_t)blk * a.block;
-    // samples s, s + 1 and s + 2 in flight (two loads ahead of the arithmetic)
-    uint32_t buf[3][8];
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-      if (b < a.block) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) buf[b][j] = __builtin_nontemporal_load(src + (t0 + b) * frame_stride + 16 * j);
-      }
-    for (int s = 0; s < a.block; ++s) {
-      if (s + 2 < a.block) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) buf[2][j] = __builtin_nontemporal_load(src + (t0 + s + 2) * frame_stride + 16 * j);
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const half8 A1 = ew_sums_f16(buf[0], wts[e]);
-        f32x4 y[2][2];
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-          for (int part = 0; part < 2; ++part) {
-            y[kt][part] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-              y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B1[p][kt][part], y[kt][part], 0, 0, 0);
-          }
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
-          float v[8];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const cf z = cmul(cf{y[kt][0][q], y[kt][1][q]}, tw[kt][q]);
-            v[2 * q] = z.r;
-            v[2 * q + 1] = z.i;
-          }
-          half8 Bh, Bl;
-          if constexpr (P2 >= 2) {
-            uint32_t hw[4], lw[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) split2(v[2 * q], v[2 * q + 1], hw[q], lw[q]);
-            Bh = __builtin_bit_cast(half8, hw);
-            Bl = __builtin_bit_cast(half8, lw);
-          } else {
-            Bh = pack8(v);
-          }
-          f32x4 o[2];
-#pragma unroll
-          for (int part = 0; part < 2; ++part) {
-            o[part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2[0][part], Bh, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-            if constexpr (P2 >= 2) o[part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2[0][part], Bl, o[part], 0, 0, 0);
-            if constexpr (P2 >= 3) o[part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2[1][part], Bh, o[part], 0, 0, 0);
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[e][kt][q] = cnorm_acc(cf{o[0][q], o[1][q]}, acc[e][kt][q]);
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) buf[b][j] = buf[b + 1][j];
-    }
-  }
-
-  // beams A = k2 + 32 k1, k2 = 16 kt + n, k1 = 4 g + q
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) lds_i[e * M + kt * 16 + n + 32 * (4 * g + q)] = acc[e][kt][q];
-  __syncthreads();
-  const int keep = a.n_keep;
-  const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
-  float* o = a.out + (((int64_t)blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    for (int j = lane; j < keep; j += 64) o[e * keep + j] = lds_i[e * M + (sel ? sel[j] : j)] * a.norm;
-}
-
 }  // namespace
 
 bool mix_supported(int n_ns, int prec, int block) {
@@ -488,26 +303,21 @@ bool mix_supported(int n_ns, int prec, int block) {
 }
 
 size_t mix_table_bytes(int n_ns, int prec) {
-  if (n_ns == 256) return kMix256Bytes;
+  if (n_ns == 256) return mix256_table_bytes();
   return prec == kPrecFp16 ? (size_t)Mix<kPrecFp16>::P * 2048 * 2 : (size_t)Mix<kPrecFp8>::P * 2048;
 }
 
 hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
   if (!mix_supported(n_ns, prec, 16)) return hipErrorNotSupported;
+  if (n_ns == 256) return launch_mix256_tables(mat, s);
   if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix_tables<kPrecFp16>, dim3(8), dim3(256), 0, s, mat);
   else hipLaunchKernelGGL(k_mix_tables<kPrecFp8>, dim3(8), dim3(256), 0, s, mat);
-  if (n_ns == 256) hipLaunchKernelGGL(k_mix256_tables, dim3(4), dim3(256), 0, s, mat);
   return hipGetLastError();
 }
 
 hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t n_wg_blocks, hipStream_t s) {
   if (!mix_supported(n_ns, prec, a.block) || a.taper) return hipErrorNotSupported;
-  if (n_ns == 256) {
-    if (n_wg_blocks == 0) return hipSuccess;
-    if (n_wg_blocks > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_mix256<MIX256_TERMS>, dim3((unsigned)n_wg_blocks), dim3(64), 0, s, a);
-    return hipGetLastError();
-  }
+  if (n_ns == 256) return launch_mix256(a, n_wg_blocks, s);
   const int64_t n_blk = a.n_time / a.block;
   const int64_t n_run = (n_blk + kMixBlocksPerWave - 1) / kMixBlocksPerWave;
   const int64_t n_wg = n_run * a.n_chan * a.n_pg;

@@ -1,0 +1,269 @@
+// Matrix-core FFT beamformer for the 4 x 256 lattice (gfx950).
+//
+// The N-S transform is zero-padded to M = 512 (eq. e:fftbeamform, weights
+// of eq. e:w_A^a) and split as 512 = 32 x 16:
+//   a = a1 + 16 a2,  A = k2 + 32 k1      (a1, a2, k1 in [0, 16), k2 in [0, 32))
+//   stage 1: Y[a1][k2] = sum_{a2} x[a1 + 16 a2] W_32^{a2 k2}   (padded 16 -> 32 DFT)
+//   twiddle: Z[a1][k2] = Y[a1][k2] W_512^{a1 k2}
+//   stage 2: B[k2 + 32 k1] = sum_{a1} Z[a1][k2] W_16^{a1 k1}
+//
+// Stage 1 is a dense product on the matrix cores, per sample and E-W beam:
+//   C[a1][k2] = A[a1][(a2, re|im)] * B[(a2, re|im)][k2]
+// A holds the E-W sums of the E-W beam at N-S position a1 + 16 a2: the
+// 4-point E-W DFT has twiddles +-1, +-i, so they are integers of magnitude
+// at most 32, formed by signed 4-bit dot products on the packed bytes, and
+// FP16 holds them exactly.  B holds the realified coefficients as two FP16
+// terms (hi + lo, about 22 significant bits) that accumulate into the same
+// FP32 accumulators, so stage 1 is accurate to FP32 rounding.
+//
+// The twiddle is a whole complex product in FP32 (four operations per
+// value).  Its tangent form (two operations, the factor Re W carried into
+// per-column stage-2 multipliers, as in the FP32 kernel) issues fewer vector
+// instructions, but the 25 multipliers per lane took the kernel past the 168
+// registers of three wavefronts per SIMD, and it measured no faster.
+//
+// Stage 2 is the FP32 16-point DFT over a1 in registers (compile-time
+// coefficients), one (E-W beam, k2) per lane.  The data go from the stage-1 layout (lane = (a1 group, k2)) to
+// the stage-2 layout (lane = (E-W beam, k2), all a1) through an LDS tile of
+// one E-W beam pair at a time (9 KB per wavefront), so three wavefronts per
+// SIMD fit.  |B|^2 accumulates in registers over the block; at its end the
+// sums pass once more through LDS so the kept beams of the channel's clamp
+// table can be stored with coalesced writes.
+#include "dev_common.h"
+#include "dev_f16.h"
+#include "kernels.h"
+
+namespace fftbf {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+
+// plan table layout (bytes)
+constexpr size_t kH256B1Off = 0;                       // [term 2][kt 2][part 2][lane 64][8] FP16
+constexpr size_t kH256TwOff = 8192;                    // [lane 64][kt 2][q 4] float2
+constexpr size_t kH256Bytes = 8192 + 4096;
+
+// FP64 on the device, rounded once into the operand layouts.
+__global__ void k_mix256_tables(void* tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  char* base = static_cast<char*>(tab);
+  // stage-1 operand B[k = 8 g + j][n] of the output part `part` of k2 = 16 kt + n,
+  // input (a2, comp) = (4 g + j / 2, j % 2):  W = c + i s,
+  //   Re(W x) = c xr - s xi,  Im(W x) = s xr + c xi
+  if (i < 2 * 2 * 64 * 8) {
+    const int j = i & 7, lane = (i >> 3) & 63, part = (i >> 9) & 1, kt = (i >> 10) & 1;
+    const int a2 = 4 * (lane >> 4) + (j >> 1), comp = j & 1, k2 = 16 * kt + (lane & 15);
+    double s, c;
+    sincospi(-2.0 * (double)((a2 * k2) & 31) / 32.0, &s, &c);
+    const double v = part == 0 ? (comp == 0 ? c : -s) : (comp == 0 ? s : c);
+    _Float16* t = reinterpret_cast<_Float16*>(base + kH256B1Off);
+    const _Float16 hi = (_Float16)(float)v;
+    t[i] = hi;
+    t[2048 + i] = (_Float16)(float)(v - (double)(float)hi);
+  }
+  // twiddles W_512^{a1 k2} of lane (g, n), slot (kt, q): a1 = 4 g + q, k2 = 16 kt + n
+  if (i < 64 * 8) {
+    const int kt = (i >> 2) & 1, q = i & 3, lane = i >> 3;
+    const int a1 = 4 * (lane >> 4) + q, k2 = 16 * kt + (lane & 15);
+    double s, c;
+    sincospi(-2.0 * (double)((a1 * k2) & 511) / 512.0, &s, &c);
+    reinterpret_cast<float2*>(base + kH256TwOff)[i] = make_float2((float)c, (float)s);
+  }
+}
+
+// dot8 weights of component comp (0 Re, 1 Im) of E-W beam e, sum_q x_q (-i)^{e q}
+// (nibble 2q + 1 is Re x_q, nibble 2q is Im x_q)
+__device__ __forceinline__ int ew_weights_comp(int e, int comp) {
+  int wre = 0, wim = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = (e * q) & 3;
+    const int sr = 4 * (2 * q + 1), si = 4 * (2 * q);
+    if (k == 0) { wre |= 1 << sr;   wim |= 1 << si; }
+    if (k == 1) { wre |= 1 << si;   wim |= 0xF << sr; }
+    if (k == 2) { wre |= 0xF << sr; wim |= 0xF << si; }
+    if (k == 3) { wre |= 0xF << si; wim |= 1 << sr; }
+  }
+  return comp ? wim : wre;
+}
+
+// Stage-1 data operand: (Re, Im) of the E-W beam at the lane's four N-S
+// positions, as FP16 without conversion instructions: each dot product
+// starts from 0x6600, the FP16 pattern of 1536 (unit step 1), so its low
+// half is FP16(1536 + x) for |x| <= 32; Re and Im are packed by one byte
+// permute and 1536 comes off in one packed FP16 subtraction (exact).
+__device__ __forceinline__ half8 ew_pairs_f16(const uint32_t* dw, int wre, int wim) {
+  half8 A;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t re = (uint32_t)sdot8_acc((int)dw[i], wre, 0x6600);
+    const uint32_t im = (uint32_t)sdot8_acc((int)dw[i], wim, 0x6600);
+    const half2 v = __builtin_bit_cast(half2, __builtin_amdgcn_perm(im, re, 0x05040100u)) -
+                    half2{(_Float16)1536.0f, (_Float16)1536.0f};
+    A[2 * i] = v[0];
+    A[2 * i + 1] = v[1];
+  }
+  return A;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront per (block, channel, polarisation group).  Lane l = 16 g + n:
+// stage 1 holds a1 = 4 g + q (q < 4) and k2 = 16 kt + n (kt < 2); stage 2
+// takes E-W beam 2 p + (l >> 5) of pair p and k2 = l & 31.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_mix256(MixArgs a) {
+  constexpr int N = 256, M = 512;
+  constexpr int ROW = 18;                     // complex values per (E-W beam, k2) row: 16 a1 + 2 pad
+  __shared__ float4 lds_raw[2 * 32 * ROW / 2];
+  cf* const tile = reinterpret_cast<cf*>(lds_raw);
+
+  const int lane = threadIdx.x;
+  const int n = lane & 15, g = lane >> 4;
+  int wg = blockIdx.x;
+  const int pg = wg % a.n_pg;
+  wg /= a.n_pg;
+  const int chan = wg % a.n_chan;
+  const int blk = wg / a.n_chan;
+
+  const char* tab = static_cast<const char*>(a.mat);
+  half8 B1[2][2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int part = 0; part < 2; ++part)
+        B1[p][kt][part] = *reinterpret_cast<const half8*>(
+            tab + kH256B1Off + 2 * (p * 2048 + ((kt * 2 + part) * 64 + lane) * 8));
+  cf tw[2][4];
+  {
+    const float2* w = reinterpret_cast<const float2*>(tab + kH256TwOff) + lane * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tw[k >> 2][k & 3] = cf{w[k].x, w[k].y};
+  }
+  const int k2s = lane & 31, es = lane >> 5;  // stage-2 column and E-W beam within the pair
+  int wre[4], wim[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    wre[e] = ew_weights_comp(e, 0);
+    wim[e] = ew_weights_comp(e, 1);
+  }
+
+  float acc[2][16];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[p][k] = 0.f;
+
+  const int pol_lo = (a.pol_iter == 1) ? pg : 0;
+  const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
+  const int64_t frame_stride = (int64_t)a.n_chan * a.n_pol * N;   // dwords per sample
+  const int64_t t0 = (int64_t)blk * a.block;
+
+  auto frame = [&](const uint32_t (&dw)[4]) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      // ---- stage 1 and twiddle for E-W beams 2p, 2p + 1, into the tile ----
+#pragma unroll
+      for (int ep = 0; ep < 2; ++ep) {
+        const int e = 2 * p + ep;
+        const half8 A = ew_pairs_f16(dw, wre[e], wim[e]);
+        f32x4 y[2][2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+          for (int part = 0; part < 2; ++part) {
+            y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1[0][kt][part], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                 0, 0, 0);
+            y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1[1][kt][part], y[kt][part], 0, 0, 0);
+          }
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+          cf z[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) z[q] = cmul(cf{y[kt][0][q], y[kt][1][q]}, tw[kt][q]);
+          float4* dst = reinterpret_cast<float4*>(&tile[(ep * 32 + 16 * kt + n) * ROW + 4 * g]);
+          dst[0] = make_float4(z[0].r, z[0].i, z[1].r, z[1].i);
+          dst[1] = make_float4(z[2].r, z[2].i, z[3].r, z[3].i);
+        }
+      }
+      wave_lds_sync();
+      // ---- stage 2: 16-point DFT over a1 for (E-W beam 2p + es, k2s) ----
+      cf x[16];
+      {
+        const float4* src = reinterpret_cast<const float4*>(&tile[(es * 32 + k2s) * ROW]);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const float4 v = src[m];
+          x[2 * m] = cf{v.x, v.y};
+          x[2 * m + 1] = cf{v.z, v.w};
+        }
+      }
+      wave_lds_sync();
+      dit<16>(x);
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) acc[p][k1] = cnorm_acc(x[k1], acc[p][k1]);
+    }
+  };
+
+  for (int pol = pol_lo; pol < pol_hi; ++pol) {
+    // the lane's N-S positions a1 + 16 a2 = n + 64 g + 16 i, i < 4
+    const uint32_t* src = a.volts + ((int64_t)chan * a.n_pol + pol) * N + n + 64 * g;
+    const uint32_t* last = src + (t0 + a.block - 1) * frame_stride;
+    uint32_t b0[4], b1[4];
+    const uint32_t* q0 = src + t0 * frame_stride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b0[i] = __builtin_nontemporal_load(q0 + 16 * i);
+    // two frame buffers in turn; the load past the block's last frame
+    // re-reads that frame (cached), so no load is conditional
+    for (int s = 0; s < a.block; s += 2) {
+      const uint32_t* q1 = (s + 1 < a.block) ? q0 + frame_stride : last;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b1[i] = __builtin_nontemporal_load(q1 + 16 * i);
+      frame(b0);
+      if (s + 1 >= a.block) break;
+      q0 = (s + 2 < a.block) ? q1 + frame_stride : last;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b0[i] = __builtin_nontemporal_load(q0 + 16 * i);
+      frame(b1);
+    }
+  }
+
+  // ---- block end: beams A = k2 + 32 k1 of E-W beam 2p + es, clamp, store ----
+  float* lds_i = reinterpret_cast<float*>(lds_raw);
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) lds_i[(2 * p + es) * M + k2s + 32 * k1] = acc[p][k1];
+  wave_lds_sync();
+  const int keep = a.n_keep;
+  const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
+  float* o = a.out + (((int64_t)blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    for (int j = lane; j < keep; j += 64) o[e * keep + j] = lds_i[e * M + (sel ? sel[j] : j)] * a.norm;
+}
+
+}  // namespace
+
+size_t mix256_table_bytes() { return kH256Bytes; }
+
+hipError_t launch_mix256_tables(void* mat, hipStream_t s) {
+  hipLaunchKernelGGL(k_mix256_tables, dim3(8), dim3(256), 0, s, mat);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix256(const MixArgs& a, int64_t n_wg, hipStream_t s) {
+  if (n_wg == 0) return hipSuccess;
+  if (n_wg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_mix256, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fftbf
