@@ -1,4 +1,4 @@
-// FP16 operand helpers for the matrix-core kernels (gfx950).
+// FP16 and FP8 (e4m3) operand helpers for the matrix-core kernels (gfx950).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +27,24 @@ __device__ __forceinline__ void split2(float v0, float v1, uint32_t& hi, uint32_
   asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r1) : "v"(h), "v"(v1));
   asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(lo) : "v"(r0), "v"(r1));
   hi = h;
+}
+
+// FP8 coefficient terms: W = hi + 2^-5 lo1 + 2^-9 lo2, each term stored
+// times 2^+s so it sits in the normal range of e4m3; the matching data
+// operand carries 2^-s (exact for the int4 voltages, |x| <= 8).
+__host__ __device__ constexpr int fp8_shift(int p) { return p == 0 ? 0 : (p == 1 ? 5 : 9); }
+
+__device__ __forceinline__ float fp8_to_f32(int byte) { return __builtin_amdgcn_cvt_f32_fp8(byte, 0); }
+__device__ __forceinline__ int f32_to_fp8(float v) { return __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xFF; }
+
+// eight small integers times a power-of-two scale as e4m3 bytes (exact for
+// the int4 voltages and the scales of fp8_shift), byte j = v[j]
+__device__ __forceinline__ long to_fp8(const int* v, float scale) {
+  int w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0] * scale, (float)v[1] * scale, 0, false);
+  w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2] * scale, (float)v[3] * scale, w0, true);
+  int w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[4] * scale, (float)v[5] * scale, 0, false);
+  w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[6] * scale, (float)v[7] * scale, w1, true);
+  return (long)(unsigned)w0 | ((long)(unsigned)w1 << 32);
 }
 
 }  // namespace fftbf

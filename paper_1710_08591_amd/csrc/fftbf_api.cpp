@@ -12,6 +12,7 @@
 
 #include "../../include/fftbf.h"
 #include "kernels.h"
+#include "trace.h"
 
 struct bf_plan {
   bf_plan_desc d;          // copy; pointer members are NULL
@@ -62,6 +63,23 @@ void free_plan(bf_plan* p) {
 
 int keep_of(const bf_plan_desc& d) { return d.n_ns_keep ? d.n_ns_keep : d.m_ns; }
 
+// The creators build their device tables on a non-blocking stream of their
+// own and wait for that stream only (temporary buffers come from the
+// stream-ordered allocator), so creating a plan or a regridder does not wait
+// for work that other streams have in flight.
+class SetupStream {
+ public:
+  hipError_t init() { return hipStreamCreateWithFlags(&s_, hipStreamNonBlocking); }
+  hipStream_t get() const { return s_; }
+  hipError_t finish() { return hipStreamSynchronize(s_); }
+  ~SetupStream() {
+    if (s_) (void)hipStreamDestroy(s_);
+  }
+
+ private:
+  hipStream_t s_ = nullptr;
+};
+
 }  // namespace
 
 extern "C" {
@@ -87,6 +105,7 @@ const char* bf_last_error(void) { return g_err.c_str(); }
 __attribute__((visibility("hidden"))) void bf_internal_set_error(const char* msg) { g_err = msg ? msg : ""; }
 
 bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
+  FFTBF_TRACE("bf_plan_create");
   if (!desc || !plan) return fail(BF_ERR_INVALID_ARGUMENT, "plan_create: NULL desc or plan");
   *plan = nullptr;
   const bf_plan_desc& d = *desc;
@@ -143,32 +162,35 @@ bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
   p->fold = d.n_ns / kn;
   p->g = fftbf::fft32_group(kn, p->fold);
   p->l2 = 2 * kn / p->g;
-  hipStream_t s = nullptr;
-  e = hipMalloc(&p->tw, sizeof(float2) * p->g * p->l2);
+  SetupStream ss;
+  e = ss.init();
+  const hipStream_t s = ss.get();
+  if (e == hipSuccess) e = hipMalloc(&p->tw, sizeof(float2) * p->g * p->l2);
   if (e == hipSuccess) e = hipMalloc(&p->mult, sizeof(float) * fftbf::twiddle_mult_count(p->g, p->l2));
   if (e == hipSuccess) e = fftbf::launch_twiddle_table(p->tw, p->mult, p->g, p->l2, 2 * kn, s);
+  std::vector<int32_t> ev;
   if (e == hipSuccess && folded) {
-    std::vector<int32_t> ev((size_t)d.n_chan * d.m_ns);
+    ev.resize((size_t)d.n_chan * d.m_ns);
     for (size_t i = 0; i < ev.size(); ++i) ev[i] = 2 * (int32_t)(i % d.m_ns);
     e = hipMalloc(&p->even, sizeof(int32_t) * ev.size());
-    if (e == hipSuccess) e = hipMemcpy(p->even, ev.data(), sizeof(int32_t) * ev.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->even, ev.data(), sizeof(int32_t) * ev.size(), hipMemcpyHostToDevice, s);
   }
   if (e == hipSuccess && d.ns_select) {
     e = hipMalloc(&p->sel, sizeof(int32_t) * d.n_chan * keep);
     if (e == hipSuccess)
-      e = hipMemcpy(p->sel, d.ns_select, sizeof(int32_t) * d.n_chan * keep, hipMemcpyHostToDevice);
+      e = hipMemcpyAsync(p->sel, d.ns_select, sizeof(int32_t) * d.n_chan * keep, hipMemcpyHostToDevice, s);
   }
+  std::vector<double> dl((size_t)d.n_chan * 2, 0.5);
   if (e == hipSuccess) {
-    std::vector<double> dl((size_t)d.n_chan * 2, 0.5);
     if (d.d_over_lambda) std::memcpy(dl.data(), d.d_over_lambda, sizeof(double) * dl.size());
     e = hipMalloc(&p->dl, sizeof(double) * dl.size());
-    if (e == hipSuccess) e = hipMemcpy(p->dl, dl.data(), sizeof(double) * dl.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->dl, dl.data(), sizeof(double) * dl.size(), hipMemcpyHostToDevice, s);
   }
   if (e == hipSuccess && d.precision != BF_PREC_FP32) {
     e = hipMalloc(&p->mix, fftbf::mix_table_bytes(d.n_ns, d.precision));
     if (e == hipSuccess) e = fftbf::launch_mix_tables(p->mix, d.n_ns, d.precision, s);
   }
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = ss.finish();
   if (e != hipSuccess) {
     free_plan(p);
     return dev_fail(e, "plan_create: device tables");
@@ -178,6 +200,7 @@ bf_status bf_plan_create(const bf_plan_desc* desc, bf_plan** plan) {
 }
 
 bf_status bf_plan_destroy(bf_plan* plan) {
+  FFTBF_TRACE("bf_plan_destroy");
   if (!plan) return BF_OK;
   hipError_t e = hipDeviceSynchronize();
   free_plan(plan);
@@ -285,11 +308,13 @@ extern "C" {
 
 bf_status bf_beamform_fft(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper, int32_t kind,
                           void* out, void* stream) {
+  FFTBF_TRACE("bf_beamform_fft");
   return beamform_fft_impl(plan, volts, n_time, taper, 1, kind, out, stream);
 }
 
 bf_status bf_beamform_fft_gains(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* gains,
                                 int32_t kind, void* out, void* stream) {
+  FFTBF_TRACE("bf_beamform_fft_gains");
   if (!gains) return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft_gains: NULL gains");
   if (plan && plan->d.precision != BF_PREC_FP32)
     return fail(BF_ERR_UNSUPPORTED, "beamform_fft_gains: complex gains need an FP32 plan");
@@ -316,6 +341,7 @@ static bf_status tied_common(const bf_plan* plan, int64_t n_time, int32_t chan_l
 bf_status bf_form_tied_beams(const bf_plan* plan, const void* fft_beams, int64_t n_time, int32_t chan_lo,
                              int32_t n_chan_sub, const double* dircos, int32_t n_point, int32_t kind,
                              void* out, void* stream) {
+  FFTBF_TRACE("bf_form_tied_beams");
   bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams");
   if (st != BF_OK) return st;
   const bf_plan_desc& d = plan->d;
@@ -356,6 +382,7 @@ bf_status bf_form_tied_beams(const bf_plan* plan, const void* fft_beams, int64_t
 bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
                                int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
                                void* out, void* stream) {
+  FFTBF_TRACE("bf_form_tied_beams_v");
   bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams_v");
   if (st != BF_OK) return st;
   const bf_plan_desc& d = plan->d;
@@ -434,6 +461,7 @@ extern "C" {
 
 bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t n_target, const double* window,
                            int32_t n_taps, bf_regrid** rg) {
+  FFTBF_TRACE("bf_regrid_create");
   if (!rg) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: NULL rg");
   *rg = nullptr;
   if (!plan || !sin_theta) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create: NULL plan or sin_theta");
@@ -467,26 +495,29 @@ bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t
   r->n_taps = n_taps;
   r->pad = fftbf::regrid_target_pad(n_target);
   double *st = nullptr, *dcoef = nullptr;
-  hipError_t e = hipMalloc(&st, sizeof(double) * n_target);
-  if (e == hipSuccess) e = hipMemcpy(st, sin_theta, sizeof(double) * n_target, hipMemcpyHostToDevice);
+  SetupStream ss;
+  hipError_t e = ss.init();
+  const hipStream_t s = ss.get();
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&st), sizeof(double) * n_target, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(st, sin_theta, sizeof(double) * n_target, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && window) {
-    e = hipMalloc(&dcoef, sizeof(double) * d.n_ns);
-    if (e == hipSuccess) e = hipMemcpy(dcoef, coef.data(), sizeof(double) * d.n_ns, hipMemcpyHostToDevice);
+    e = hipMallocAsync(reinterpret_cast<void**>(&dcoef), sizeof(double) * d.n_ns, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * d.n_ns, hipMemcpyHostToDevice, s);
   }
   if (n_taps == 0) {
     if (e == hipSuccess) e = hipMalloc(&r->w, sizeof(float) * (size_t)r->n_chan * r->pad * r->m_ns);
     if (e == hipSuccess)
-      e = fftbf::launch_regrid_weights(r->w, plan->dl, st, dcoef, r->n_chan, n_target, r->n_ns, r->m_ns, nullptr);
+      e = fftbf::launch_regrid_weights(r->w, plan->dl, st, dcoef, r->n_chan, n_target, r->n_ns, r->m_ns, s);
   } else {
     if (e == hipSuccess) e = hipMalloc(&r->first, sizeof(int) * (size_t)r->n_chan * n_target);
     if (e == hipSuccess) e = hipMalloc(&r->tw, sizeof(float) * (size_t)r->n_chan * n_taps * n_target);
     if (e == hipSuccess)
       e = fftbf::launch_regrid_tap_table(r->first, r->tw, plan->dl, st, dcoef, r->n_chan, n_target, n_taps, r->n_ns,
-                                         r->m_ns, nullptr);
+                                         r->m_ns, s);
   }
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (st) (void)hipFree(st);
-  if (dcoef) (void)hipFree(dcoef);
+  if (st) (void)hipFreeAsync(st, s);
+  if (dcoef) (void)hipFreeAsync(dcoef, s);
+  if (e == hipSuccess) e = ss.finish();
   if (e != hipSuccess) {
     regrid_free(r);
     return dev_fail(e, "regrid_create: weights");
@@ -496,6 +527,7 @@ bf_status bf_regrid_create(const bf_plan* plan, const double* sin_theta, int32_t
 }
 
 bf_status bf_regrid_create_2d(const bf_plan* plan, const double* dircos, int32_t n_point, bf_regrid** rg) {
+  FFTBF_TRACE("bf_regrid_create_2d");
   if (!rg) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create_2d: NULL rg");
   *rg = nullptr;
   if (!plan || !dircos) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_create_2d: NULL plan or dircos");
@@ -522,17 +554,20 @@ bf_status bf_regrid_create_2d(const bf_plan* plan, const double* dircos, int32_t
   r->n_target = n_point;
   r->pad = fftbf::regrid_target_pad(n_point);
   double *dd = nullptr;
-  hipError_t e = hipMalloc(&dd, sizeof(double) * 2 * n_point);
-  if (e == hipSuccess) e = hipMemcpy(dd, dns.data(), sizeof(double) * n_point, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(dd + n_point, dew.data(), sizeof(double) * n_point, hipMemcpyHostToDevice);
+  SetupStream ss;
+  hipError_t e = ss.init();
+  const hipStream_t s = ss.get();
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&dd), sizeof(double) * 2 * n_point, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dd, dns.data(), sizeof(double) * n_point, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dd + n_point, dew.data(), sizeof(double) * n_point, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMalloc(&r->w, sizeof(float) * (size_t)r->n_chan * r->pad * r->m_ns);
   if (e == hipSuccess) e = hipMalloc(&r->wew, sizeof(float) * (size_t)r->n_chan * r->pad * 8);
   if (e == hipSuccess)
-    e = fftbf::launch_regrid_weights(r->w, plan->dl, dd, nullptr, r->n_chan, n_point, r->n_ns, r->m_ns, nullptr);
+    e = fftbf::launch_regrid_weights(r->w, plan->dl, dd, nullptr, r->n_chan, n_point, r->n_ns, r->m_ns, s);
   if (e == hipSuccess)
-    e = fftbf::launch_regrid_ew_weights(r->wew, plan->dl, dd + n_point, r->n_chan, n_point, d.n_ew, d.m_ew, nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (dd) (void)hipFree(dd);
+    e = fftbf::launch_regrid_ew_weights(r->wew, plan->dl, dd + n_point, r->n_chan, n_point, d.n_ew, d.m_ew, s);
+  if (dd) (void)hipFreeAsync(dd, s);
+  if (e == hipSuccess) e = ss.finish();
   if (e != hipSuccess) {
     regrid_free(r);
     return dev_fail(e, "regrid_create_2d: weights");
@@ -542,6 +577,7 @@ bf_status bf_regrid_create_2d(const bf_plan* plan, const double* dircos, int32_t
 }
 
 bf_status bf_regrid_destroy(bf_regrid* rg) {
+  FFTBF_TRACE("bf_regrid_destroy");
   if (!rg) return BF_OK;
   hipError_t e = hipDeviceSynchronize();
   regrid_free(rg);
@@ -551,6 +587,7 @@ bf_status bf_regrid_destroy(bf_regrid* rg) {
 
 bf_status bf_regrid_intensity(const bf_regrid* rg, const float* fft_intensity, int64_t n_blk, float* out,
                               void* stream) {
+  FFTBF_TRACE("bf_regrid_intensity");
   if (!rg) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_intensity: NULL regrid");
   if (n_blk < 0) return fail(BF_ERR_INVALID_ARGUMENT, "regrid_intensity: negative n_blk");
   if (n_blk == 0) return BF_OK;
@@ -579,6 +616,7 @@ bf_status bf_regrid_intensity(const bf_regrid* rg, const float* fft_intensity, i
 
 bf_status bf_localize(const bf_plan* plan, const float* fft_intensity, int64_t n_blk, int32_t n_window,
                       int32_t n_iter, double* sin_theta, float* peak, void* stream) {
+  FFTBF_TRACE("bf_localize");
   if (!plan) return fail(BF_ERR_INVALID_ARGUMENT, "localize: NULL plan");
   const bf_plan_desc& d = plan->d;
   if (plan->sel || keep_of(d) != d.m_ns)
@@ -615,6 +653,7 @@ bf_status bf_localize(const bf_plan* plan, const float* fft_intensity, int64_t n
 
 bf_status bf_accumulate_intensity(const void* z, int64_t n_time, int64_t n_series, int32_t block, int32_t add,
                                   float* out, void* stream) {
+  FFTBF_TRACE("bf_accumulate_intensity");
   if (n_time < 0 || n_series < 0) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: negative size");
   if (block <= 0) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: block must be positive");
   if (add != 0 && add != 1) return fail(BF_ERR_INVALID_ARGUMENT, "accumulate_intensity: add is 0 or 1");

@@ -47,9 +47,6 @@ template <> struct Mix<kPrecFp8> {
   using op_t = long;
 };
 
-// data scale exponent of each FP8 term (the coefficient term carries 2^+s)
-__host__ __device__ constexpr int fp8_shift(int p) { return p == 0 ? 0 : (p == 1 ? 5 : 9); }
-
 // realified DFT coefficient B[k][n] of output part `part` (0 re, 1 im) for
 // beam k_out = kt*16 + n of the zero-padded 16 -> 32 N-S transform
 __device__ double mix_coef(int kt, int part, int k, int n) {
@@ -60,13 +57,6 @@ __device__ double mix_coef(int kt, int part, int k, int n) {
   sincospi(-2.0 * (double)r / 32.0, &s, &c);     // W = c + i s = exp(-i 2 pi r / 32)
   if (part == 0) return comp == 0 ? c : -s;        // Re(W x) = c xr - s xi
   return comp == 0 ? s : c;                        // Im(W x) = s xr + c xi
-}
-
-__device__ __forceinline__ float fp8_to_f32(int byte) {
-  return __builtin_amdgcn_cvt_f32_fp8(byte, 0);
-}
-__device__ __forceinline__ int f32_to_fp8(float v) {
-  return __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xFF;
 }
 
 // Table layout: [P][kt 2][part 2][lane 64][j 8], entry = term p of
@@ -113,14 +103,6 @@ template <int PREC>
 __device__ __forceinline__ f32x4 mfma(typename Mix<PREC>::op_t a, typename Mix<PREC>::op_t b, f32x4 c) {
   if constexpr (PREC == kPrecFp16) return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   else return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ long to_fp8(const int* v, float scale) {
-  int w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0] * scale, (float)v[1] * scale, 0, false);
-  w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2] * scale, (float)v[3] * scale, w0, true);
-  int w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[4] * scale, (float)v[5] * scale, 0, false);
-  w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[6] * scale, (float)v[7] * scale, w1, true);
-  return (long)(unsigned)w0 | ((long)(unsigned)w1 << 32);
 }
 
 // dot8 weights for component comp (0 Re, 1 Im) of E-W beam e:
@@ -298,7 +280,7 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
 
 bool mix_supported(int n_ns, int prec, int block) {
   if (n_ns == 16) return (prec == kPrecFp16 || prec == kPrecFp8) && block % 16 == 0;
-  if (n_ns == 256) return prec == kPrecFp16 && block >= 1;
+  if (n_ns == 256) return (prec == kPrecFp16 || prec == kPrecFp8) && block >= 1;
   return false;
 }
 
@@ -309,7 +291,7 @@ size_t mix_table_bytes(int n_ns, int prec) {
 
 hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
   if (!mix_supported(n_ns, prec, 16)) return hipErrorNotSupported;
-  if (n_ns == 256) return launch_mix256_tables(mat, s);
+  if (n_ns == 256) return launch_mix256_tables(mat, prec, s);
   if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix_tables<kPrecFp16>, dim3(8), dim3(256), 0, s, mat);
   else hipLaunchKernelGGL(k_mix_tables<kPrecFp8>, dim3(8), dim3(256), 0, s, mat);
   return hipGetLastError();
@@ -317,7 +299,7 @@ hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
 
 hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t n_wg_blocks, hipStream_t s) {
   if (!mix_supported(n_ns, prec, a.block) || a.taper) return hipErrorNotSupported;
-  if (n_ns == 256) return launch_mix256(a, n_wg_blocks, s);
+  if (n_ns == 256) return launch_mix256(a, prec, n_wg_blocks, s);
   const int64_t n_blk = a.n_time / a.block;
   const int64_t n_run = (n_blk + kMixBlocksPerWave - 1) / kMixBlocksPerWave;
   const int64_t n_wg = n_run * a.n_chan * a.n_pg;

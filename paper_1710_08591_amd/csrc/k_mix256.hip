@@ -29,6 +29,16 @@
 // SIMD fit.  |B|^2 accumulates in registers over the block; at its end the
 // sums pass once more through LDS so the kept beams of the channel's clamp
 // table can be stored with coalesced writes.
+//
+// FP8 variant: e4m3 does not hold every E-W sum (17, for one), so the data
+// operand holds the raw int4 of one E-W antenna column (exact), and the E-W
+// 4-point DFT runs in FP32 on the stage-1 outputs, before the twiddle.  The
+// coefficients are split into three e4m3 terms, W = hi + 2^-5 lo1 + 2^-9 lo2,
+// stacked along K of one v_mfma_scale_f32_16x16x128_f8f6f4 (unit block
+// scales): lane group g holds in its 32 K values the (a2, re|im) of a2 in
+// [4g, 4g + 4) once per term (8 values each) and 8 zeros, and the power of
+// two of each term sits on the exact data bytes (x, 2^-5 x, 2^-9 x).  The
+// LDS tile then holds all four E-W beams of one beam tile (16 k2) at a time.
 #include "dev_common.h"
 #include "dev_f16.h"
 #include "kernels.h"
@@ -40,28 +50,57 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 
+constexpr int kPrecFp16 = 1;
+constexpr int kPrecFp8 = 2;
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
 // plan table layout (bytes)
-constexpr size_t kH256B1Off = 0;                       // [term 2][kt 2][part 2][lane 64][8] FP16
-constexpr size_t kH256TwOff = 8192;                    // [lane 64][kt 2][q 4] float2
+constexpr size_t kH256B1Off = 0;      // FP16: [term 2][kt 2][part 2][lane 64][8] halves
+                                      // FP8:  [kt 2][part 2][lane 64][32] bytes
+constexpr size_t kH256TwOff = 8192;   // [lane 64][kt 2][q 4] float2
 constexpr size_t kH256Bytes = 8192 + 4096;
 
+// realified coefficient of stage 1: output part `part` (0 Re, 1 Im) of k2
+// from input component comp (0 Re, 1 Im) of position a2, W = W_32^{a2 k2} = c + i s,
+//   Re(W x) = c xr - s xi,  Im(W x) = s xr + c xi
+__device__ double h256_coef(int a2, int comp, int k2, int part) {
+  double s, c;
+  sincospi(-2.0 * (double)((a2 * k2) & 31) / 32.0, &s, &c);
+  return part == 0 ? (comp == 0 ? c : -s) : (comp == 0 ? s : c);
+}
+
 // FP64 on the device, rounded once into the operand layouts.
+template <int PREC>
 __global__ void k_mix256_tables(void* tab) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   char* base = static_cast<char*>(tab);
-  // stage-1 operand B[k = 8 g + j][n] of the output part `part` of k2 = 16 kt + n,
-  // input (a2, comp) = (4 g + j / 2, j % 2):  W = c + i s,
-  //   Re(W x) = c xr - s xi,  Im(W x) = s xr + c xi
-  if (i < 2 * 2 * 64 * 8) {
-    const int j = i & 7, lane = (i >> 3) & 63, part = (i >> 9) & 1, kt = (i >> 10) & 1;
-    const int a2 = 4 * (lane >> 4) + (j >> 1), comp = j & 1, k2 = 16 * kt + (lane & 15);
-    double s, c;
-    sincospi(-2.0 * (double)((a2 * k2) & 31) / 32.0, &s, &c);
-    const double v = part == 0 ? (comp == 0 ? c : -s) : (comp == 0 ? s : c);
-    _Float16* t = reinterpret_cast<_Float16*>(base + kH256B1Off);
-    const _Float16 hi = (_Float16)(float)v;
-    t[i] = hi;
-    t[2048 + i] = (_Float16)(float)(v - (double)(float)hi);
+  if constexpr (PREC == kPrecFp16) {
+    // stage-1 operand B[k = 8 g + j][n] of part `part` of k2 = 16 kt + n,
+    // input (a2, comp) = (4 g + j / 2, j % 2), as hi + lo FP16 terms
+    if (i < 2 * 2 * 64 * 8) {
+      const int j = i & 7, lane = (i >> 3) & 63, part = (i >> 9) & 1, kt = (i >> 10) & 1;
+      const double v = h256_coef(4 * (lane >> 4) + (j >> 1), j & 1, 16 * kt + (lane & 15), part);
+      _Float16* t = reinterpret_cast<_Float16*>(base + kH256B1Off);
+      const _Float16 hi = (_Float16)(float)v;
+      t[i] = hi;
+      t[2048 + i] = (_Float16)(float)(v - (double)(float)hi);
+    }
+  } else {
+    // byte j of lane (g, n): term j / 8 (j >= 24: zero) of (a2, comp) =
+    // (4 g + (j % 8) / 2, j % 2), stored times 2^fp8_shift(term)
+    if (i < 2 * 2 * 64 * 8) {
+      const int jj = i & 7, lane = (i >> 3) & 63, part = (i >> 9) & 1, kt = (i >> 10) & 1;
+      double r = h256_coef(4 * (lane >> 4) + (jj >> 1), jj & 1, 16 * kt + (lane & 15), part);
+      uint8_t* t = reinterpret_cast<uint8_t*>(base + kH256B1Off) + (((kt * 2 + part) * 64 + lane) * 32) + jj;
+      for (int p = 0; p < 3; ++p) {
+        const double sc = (double)(1 << fp8_shift(p));
+        const int byte = f32_to_fp8((float)(r * sc));
+        t[8 * p] = (uint8_t)byte;
+        r -= (double)fp8_to_f32(byte) / sc;
+      }
+      t[24] = 0;
+    }
   }
   // twiddles W_512^{a1 k2} of lane (g, n), slot (kt, q): a1 = 4 g + q, k2 = 16 kt + n
   if (i < 64 * 8) {
@@ -250,19 +289,164 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     for (int j = lane; j < keep; j += 64) o[e * keep + j] = lds_i[e * M + (sel ? sel[j] : j)] * a.norm;
 }
 
+
+// FP8: one wavefront per (block, channel, polarisation group).  Lane
+// l = 16 g + n: stage 1 holds a1 = 4 g + q and k2 = 16 kt + n for the beam
+// tile kt of the round; stage 2 takes E-W beam l >> 4 and k2 = 16 kt + (l & 15).
+__global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
+  constexpr int N = 256, M = 512;
+  constexpr int ROW = 18;                     // complex values per (E-W beam, k2) row: 16 a1 + 2 pad
+  constexpr int kUnitScale = 0x7F7F7F7F;      // E8M0 block scale 2^0
+  __shared__ float4 lds_raw[4 * 16 * ROW / 2];
+  cf* const tile = reinterpret_cast<cf*>(lds_raw);
+
+  const int lane = threadIdx.x;
+  const int n = lane & 15, g = lane >> 4;
+  int wg = blockIdx.x;
+  const int pg = wg % a.n_pg;
+  wg /= a.n_pg;
+  const int chan = wg % a.n_chan;
+  const int blk = wg / a.n_chan;
+
+  const char* tab = static_cast<const char*>(a.mat);
+  i32x8 B[2][2];
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+      B[kt][part] = *reinterpret_cast<const i32x8*>(tab + kH256B1Off + ((kt * 2 + part) * 64 + lane) * 32);
+  cf tw[2][4];
+  {
+    const float2* w = reinterpret_cast<const float2*>(tab + kH256TwOff) + lane * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tw[k >> 2][k & 3] = cf{w[k].x, w[k].y};
+  }
+  const int es = lane >> 4, ks = lane & 15;    // stage-2 E-W beam and column within the tile
+
+  float acc[2][16];
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[kt][k] = 0.f;
+
+  const int pol_lo = (a.pol_iter == 1) ? pg : 0;
+  const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
+  const int64_t frame_stride = (int64_t)a.n_chan * a.n_pol * N;   // dwords per sample
+  const int64_t t0 = (int64_t)blk * a.block;
+
+  auto frame = [&](const uint32_t (&dw)[4]) {
+    // data operands of the four E-W antenna columns: (Re, Im) at the lane's
+    // four N-S positions, once per term (times 2^-shift), then zeros
+    i32x8 A[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int v[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[2 * i] = __builtin_amdgcn_sbfe((int)dw[i], 8 * q + 4, 4);
+        v[2 * i + 1] = __builtin_amdgcn_sbfe((int)dw[i], 8 * q, 4);
+      }
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const long w = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
+        A[q][2 * p] = (int)w;
+        A[q][2 * p + 1] = (int)(w >> 32);
+      }
+      A[q][6] = 0;
+      A[q][7] = 0;
+    }
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+      // ---- stage 1 per E-W column, then the E-W DFT and the twiddle, into the tile ----
+      f32x4 y[4][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int part = 0; part < 2; ++part)
+          y[q][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+              A[q], B[kt][part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, kUnitScale, 0, kUnitScale);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // X_e = sum_q Y_q (-i)^{e q}
+        const cf y0{y[0][0][i], y[0][1][i]}, y1{y[1][0][i], y[1][1][i]};
+        const cf y2{y[2][0][i], y[2][1][i]}, y3{y[3][0][i], y[3][1][i]};
+        const cf s02 = cadd(y0, y2), d02 = csub(y0, y2), s13 = cadd(y1, y3), d13 = csub(y1, y3);
+        const cf x[4] = {cadd(s02, s13), cf{d02.r + d13.i, d02.i - d13.r}, csub(s02, s13),
+                         cf{d02.r - d13.i, d02.i + d13.r}};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tile[(e * 16 + n) * ROW + 4 * g + i] = cmul(x[e], tw[kt][i]);
+      }
+      wave_lds_sync();
+      // ---- stage 2: 16-point DFT over a1 for (E-W beam es, k2 = 16 kt + ks) ----
+      cf x[16];
+      {
+        const float4* src = reinterpret_cast<const float4*>(&tile[(es * 16 + ks) * ROW]);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const float4 v = src[m];
+          x[2 * m] = cf{v.x, v.y};
+          x[2 * m + 1] = cf{v.z, v.w};
+        }
+      }
+      wave_lds_sync();
+      dit<16>(x);
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) acc[kt][k1] = cnorm_acc(x[k1], acc[kt][k1]);
+    }
+  };
+
+  for (int pol = pol_lo; pol < pol_hi; ++pol) {
+    const uint32_t* src = a.volts + ((int64_t)chan * a.n_pol + pol) * N + n + 64 * g;
+    const uint32_t* last = src + (t0 + a.block - 1) * frame_stride;
+    uint32_t b0[4], b1[4];
+    const uint32_t* q0 = src + t0 * frame_stride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b0[i] = __builtin_nontemporal_load(q0 + 16 * i);
+    for (int s = 0; s < a.block; s += 2) {
+      const uint32_t* q1 = (s + 1 < a.block) ? q0 + frame_stride : last;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b1[i] = __builtin_nontemporal_load(q1 + 16 * i);
+      frame(b0);
+      if (s + 1 >= a.block) break;
+      q0 = (s + 2 < a.block) ? q1 + frame_stride : last;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b0[i] = __builtin_nontemporal_load(q0 + 16 * i);
+      frame(b1);
+    }
+  }
+
+  // ---- block end: beams A = 16 kt + ks + 32 k1 of E-W beam es, clamp, store ----
+  float* lds_i = reinterpret_cast<float*>(lds_raw);
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) lds_i[es * M + 16 * kt + ks + 32 * k1] = acc[kt][k1];
+  wave_lds_sync();
+  const int keep = a.n_keep;
+  const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
+  float* o = a.out + (((int64_t)blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    for (int j = lane; j < keep; j += 64) o[e * keep + j] = lds_i[e * M + (sel ? sel[j] : j)] * a.norm;
+}
+
 }  // namespace
 
 size_t mix256_table_bytes() { return kH256Bytes; }
 
-hipError_t launch_mix256_tables(void* mat, hipStream_t s) {
-  hipLaunchKernelGGL(k_mix256_tables, dim3(8), dim3(256), 0, s, mat);
+hipError_t launch_mix256_tables(void* mat, int prec, hipStream_t s) {
+  if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix256_tables<kPrecFp16>, dim3(8), dim3(256), 0, s, mat);
+  else if (prec == kPrecFp8) hipLaunchKernelGGL(k_mix256_tables<kPrecFp8>, dim3(8), dim3(256), 0, s, mat);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_mix256(const MixArgs& a, int64_t n_wg, hipStream_t s) {
+hipError_t launch_mix256(const MixArgs& a, int prec, int64_t n_wg, hipStream_t s) {
   if (n_wg == 0) return hipSuccess;
   if (n_wg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_mix256, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix256, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  else if (prec == kPrecFp8) hipLaunchKernelGGL(k_mix256_fp8, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include "../../include/fftbf.h"
 #include "kernels.h"
 #include "serve_sched.h"
+#include "trace.h"
 
 extern "C" __attribute__((visibility("hidden"))) void bf_internal_set_error(const char* msg);
 
@@ -111,6 +112,7 @@ class HipBackend final : public fftbf::serve::Backend {
       d.n_blk = t.n_blk;
       d.pad = 0;
     }
+    FFTBF_TRACE("bf_server batch launch");
     hipError_t e = hipMemcpyAsync(dev_[slot], h, sizeof(fftbf::ServeTile) * n, hipMemcpyHostToDevice, stream_);
     if (e == hipSuccess)
       e = fftbf::launch_serve(dev_[slot], n, static_cast<const uint32_t*>(ring_), ring_samples_, n_chan_, n_pol_, dl_,
@@ -168,6 +170,7 @@ extern "C" {
 
 bf_status bf_server_create(const bf_plan* plan, int64_t ring_samples, int64_t hbm_budget, int32_t blocks_per_tile,
                            int32_t max_tiles_per_launch, bf_server** srv) {
+  FFTBF_TRACE("bf_server_create");
   if (!srv) return sfail(BF_ERR_INVALID_ARGUMENT, "server_create: NULL srv");
   *srv = nullptr;
   if (!plan) return sfail(BF_ERR_INVALID_ARGUMENT, "server_create: NULL plan");
@@ -210,6 +213,7 @@ bf_status bf_server_create(const bf_plan* plan, int64_t ring_samples, int64_t hb
 }
 
 bf_status bf_server_destroy(bf_server* srv) {
+  FFTBF_TRACE("bf_server_destroy");
   delete srv;   // the backend drains its stream before freeing device memory
   return BF_OK;
 }
@@ -223,6 +227,7 @@ bf_status bf_server_ring(bf_server* srv, void** ring, int64_t* ring_samples, int
 }
 
 bf_status bf_server_advance(bf_server* srv, int64_t n_samples, const uint8_t* src, int32_t force, void* stream) {
+  FFTBF_TRACE("bf_server_advance");
   if (!srv || n_samples < 0) return sfail(BF_ERR_INVALID_ARGUMENT, "server_advance: bad argument");
   if (src && n_samples > srv->ring_samples)
     return sfail(BF_ERR_INVALID_ARGUMENT, "server_advance: more samples than the ring holds");
@@ -257,6 +262,7 @@ bf_status bf_server_advance(bf_server* srv, int64_t n_samples, const uint8_t* sr
 
 bf_status bf_server_submit(bf_server* srv, int32_t n_point, int32_t chan_lo, int32_t n_chan, int64_t n_time,
                            const double* dircos, double arrival_s, int64_t* id) {
+  FFTBF_TRACE("bf_server_submit");
   if (!srv || !id) return sfail(BF_ERR_INVALID_ARGUMENT, "server_submit: NULL argument");
   const int r = srv->sched->submit(n_point, chan_lo, n_chan, n_time, dircos, arrival_s, id);
   if (r != fftbf::serve::kOk) return sfail(map_status(r), srv->sched->last_error);
@@ -264,6 +270,7 @@ bf_status bf_server_submit(bf_server* srv, int32_t n_point, int32_t chan_lo, int
 }
 
 bf_status bf_server_pump(bf_server* srv) {
+  FFTBF_TRACE("bf_server_pump");
   if (!srv) return sfail(BF_ERR_INVALID_ARGUMENT, "server_pump: NULL srv");
   const int r = srv->sched->pump();
   if (srv->be.err_ != hipSuccess)
@@ -298,6 +305,7 @@ bf_status bf_server_release(bf_server* srv, int64_t id) {
 }
 
 bf_status bf_server_cancel(bf_server* srv, int64_t id) {
+  FFTBF_TRACE("bf_server_cancel");
   if (!srv) return sfail(BF_ERR_INVALID_ARGUMENT, "server_cancel: NULL srv");
   const int r = srv->sched->cancel(id);
   if (r != fftbf::serve::kOk) return sfail(map_status(r), "server_cancel: unknown request");
@@ -321,6 +329,7 @@ bf_status bf_server_stats_get(bf_server* srv, bf_server_stats* st) {
 double bf_server_now(bf_server* srv) { return srv ? srv->be.now() : 0.0; }
 
 bf_status bf_server_copy_result(bf_server* srv, int64_t id, float* dst, void* stream) {
+  FFTBF_TRACE("bf_server_copy_result");
   float* src = nullptr;
   int64_t n = 0;
   const bf_status st = bf_server_result(srv, id, &src, &n);
