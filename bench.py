@@ -298,6 +298,14 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
                "speedup_vs_fp32": fp32_ms / ms8,
                "mfma_tflops": mf8 / (ms8 / 1e3) / 1e12, "mfma_frac_of_fp8_peak": mf8 / (ms8 / 1e3) / 1e12 / 5000.0}
     checks.add_blocks(fp8_rec, "max_rel_power_err_sampled", out, w)
+    # the per-antenna Gaussian window on the FP16 matrix-core plan (windowed E-W sums split into hi + lo)
+    hwin = np.ascontiguousarray(sg.gaussian_taper(w.n_ew, w.n_ns), dtype=np.float32)
+    hwin_dev = torch.from_numpy(hwin).to(dev)
+    hm_ms = _time_launches(lambda: bf.beamform_fft(plan, volts, out=out, taper=hwin_dev), 5)
+    fp16_window_rec = {"kernel_ms": hm_ms, "antenna_samples_per_s": w.antenna_samples / (hm_ms / 1e3),
+                       "slowdown_vs_no_window": hm_ms / ms, "speedup_vs_fp32_with_window": None}
+    checks.add_blocks(fp16_window_rec, "max_rel_power_err_sampled", out, w, blocks=(0,),
+                      taper=hwin.astype(np.float64))
     # complex per-antenna gains (bf_beamform_fft_gains) on the same voltages, FP32 plan
     plan32 = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=w.m_ew, m_ns=w.m_ns, n_pol=w.n_pol, n_chan=w.n_chan,
                      block=w.block, ns_select=w.ns_select(), d_over_lambda=w.d_over_lambda())
@@ -320,6 +328,7 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
     h_ms = _time_launches(lambda: bf.beamform_fft(plan32, volts, out=out, taper=h_dev), 5)
     window_rec = {"kernel_ms": h_ms, "antenna_samples_per_s": w.antenna_samples / (h_ms / 1e3),
                   "slowdown_vs_no_window": h_ms / fp32_ms}
+    fp16_window_rec["speedup_vs_fp32_with_window"] = h_ms / hm_ms
     checks.add_blocks(window_rec, "max_rel_power_err_sampled", out, w, blocks=(0,),
                       taper=np.asarray(h, dtype=np.float64))
     for _ in range(2):
@@ -341,7 +350,8 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
                 "hbm_alg_gbs": alg / (ms / 1e3) / 1e9, "hbm_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                 "mfma_tflops": mfma_flops / (ms / 1e3) / 1e12,
                 "mfma_frac_of_fp16_peak": mfma_flops / (ms / 1e3) / 1e12 / FP16_MFMA_PEAK_TFLOPS,
-                "fp8_mfma": fp8_rec, "fp32_with_complex_gains": gains_rec, "fp32_with_real_window": window_rec})
+                "fp8_mfma": fp8_rec, "fp16_mfma_with_real_window": fp16_window_rec,
+                "fp32_with_complex_gains": gains_rec, "fp32_with_real_window": window_rec})
     return rec
 
 

@@ -240,8 +240,9 @@ static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, in
                 (long long)n_time, d.block);
   if (kind == BF_OUT_COMPLEX && d.precision != BF_PREC_FP32)
     return fail(BF_ERR_UNSUPPORTED, "beamform_fft: complex beams are produced by FP32 plans only");
-  if (d.precision != BF_PREC_FP32 && taper)
-    return fail(BF_ERR_UNSUPPORTED, "beamform_fft: mixed-precision plans take no window (use an FP32 plan)");
+  if (d.precision != BF_PREC_FP32 && taper && !fftbf::mix_window_supported(d.n_ns, d.precision))
+    return fail(BF_ERR_UNSUPPORTED,
+                "beamform_fft: a window on the matrix cores needs an FP16 plan (use an FP32 plan)");
   if (d.precision != BF_PREC_FP32 && !aligned(volts, 16))
     return fail(BF_ERR_INVALID_ARGUMENT, "beamform_fft: mixed-precision plans need 16-byte aligned volts");
   const hipStream_t s = static_cast<hipStream_t>(stream);

@@ -140,8 +140,15 @@ __device__ __forceinline__ half8 ew_sums_f16(const uint32_t* dw, int w) {
   return A;
 }
 
-template <int PREC>
+// WIN (FP16 only): per-antenna real weights h[a_ns][a_ew] (Sec. "Controlling
+// beam shape with windowing").  The windowed E-W sums are no longer
+// integers, so each is split into FP16 hi + lo and the N-S products take
+// three terms (hi x hi, hi x lo, lo x hi of data and coefficients); the
+// window is scaled per wavefront by a power of two so that its largest
+// weight lies in [1/2, 1), and the block sums are scaled back exactly.
+template <int PREC, bool WIN = false>
 __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
+  static_assert(!WIN || PREC == kPrecFp16, "windows run on the FP16 path");
   constexpr int P = Mix<PREC>::P;
   using op_t = typename Mix<PREC>::op_t;
   __shared__ float lds_i[4 * 32];
@@ -174,6 +181,32 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
   const int keep = a.n_keep;
   const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
 
+  // the window at the lane's N-S positions 8 (g & 1) + j, scaled by 2^-E with
+  // 2^E the power of two just above the wavefront's largest |h|
+  float hw[WIN ? 8 : 1][4];
+  float unscale = 1.f;       // 2^{2E}: undoes the scale on |B|^2
+  if constexpr (WIN) {
+    float m = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float4 v = *reinterpret_cast<const float4*>(a.taper + 4 * (8 * (g & 1) + j));
+      hw[j][0] = v.x;
+      hw[j][1] = v.y;
+      hw[j][2] = v.z;
+      hw[j][3] = v.w;
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) m = fmaxf(m, __shfl_xor(m, d));
+    const int ex = m > 0.f ? ilogbf(m) + 1 : 0;      // m * 2^-ex in [1/2, 1)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hw[j][q] = ldexpf(hw[j][q], -ex);
+    unscale = ldexpf(1.f, 2 * ex);
+  }
+  const bool im_lane = (g >> 1) != 0;         // this lane's component of the data operand
+
   for (int64_t blk = blk0; blk < blk1; ++blk) {
     float ia[4][2];
 #pragma unroll
@@ -186,7 +219,43 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
         const uint4 d0 = fr[2 * (g & 1)], d1 = fr[2 * (g & 1) + 1];
         const uint32_t dw[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
 
-        if constexpr (PREC == kPrecFp16) {
+        if constexpr (WIN) {
+          // windowed E-W sums of every E-W beam at the lane's eight positions,
+          // the lane's component of each, split into FP16 hi + lo
+          float xw[4][8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            cf w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              w[q] = cf{hw[j][q] * (float)(int)__builtin_amdgcn_sbfe((int)dw[j], 8 * q + 4, 4),
+                        hw[j][q] * (float)(int)__builtin_amdgcn_sbfe((int)dw[j], 8 * q, 4)};
+            const cf s02 = cadd(w[0], w[2]), d02 = csub(w[0], w[2]), s13 = cadd(w[1], w[3]), d13 = csub(w[1], w[3]);
+            const cf be[4] = {cadd(s02, s13), cf{d02.r + d13.i, d02.i - d13.r}, csub(s02, s13),
+                              cf{d02.r - d13.i, d02.i + d13.r}};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xw[e][j] = im_lane ? be[e].i : be[e].r;
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            uint32_t hi[4], lo[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) split2(xw[e][2 * j], xw[e][2 * j + 1], hi[j], lo[j]);
+            const half8 Ah = __builtin_bit_cast(half8, hi), Al = __builtin_bit_cast(half8, lo);
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt) {
+              f32x4 y[2];
+#pragma unroll
+              for (int part = 0; part < 2; ++part) {
+                y[part] = mfma<PREC>(Ah, B[0][kt][part], f32x4{0.f, 0.f, 0.f, 0.f});
+                y[part] = mfma<PREC>(Ah, B[1][kt][part], y[part]);
+                y[part] = mfma<PREC>(Al, B[0][kt][part], y[part]);
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i) ia[e][kt] = cnorm_acc(cf{y[0][i], y[1][i]}, ia[e][kt]);
+            }
+          }
+        } else if constexpr (PREC == kPrecFp16) {
           // FP16 holds the E-W sums exactly, so the E-W DFT goes first (as
           // signed 4-bit dot products on the packed bytes) and each E-W
           // beam's N-S products land straight in its |B|^2
@@ -264,7 +333,7 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) lds_i[e * 32 + kt * 16 + n] = ia[e][kt] * a.norm;
+        for (int kt = 0; kt < 2; ++kt) lds_i[e * 32 + kt * 16 + n] = ia[e][kt] * (a.norm * unscale);
     }
     __syncthreads();
     float* o = a.out + ((blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
@@ -277,6 +346,8 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
 }
 
 }  // namespace
+
+bool mix_window_supported(int n_ns, int prec) { return (n_ns == 16 || n_ns == 256) && prec == kPrecFp16; }
 
 bool mix_supported(int n_ns, int prec, int block) {
   if (n_ns == 16) return (prec == kPrecFp16 || prec == kPrecFp8) && block % 16 == 0;
@@ -298,14 +369,16 @@ hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
 }
 
 hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t n_wg_blocks, hipStream_t s) {
-  if (!mix_supported(n_ns, prec, a.block) || a.taper) return hipErrorNotSupported;
+  if (!mix_supported(n_ns, prec, a.block) || (a.taper && !mix_window_supported(n_ns, prec)))
+    return hipErrorNotSupported;
   if (n_ns == 256) return launch_mix256(a, prec, n_wg_blocks, s);
   const int64_t n_blk = a.n_time / a.block;
   const int64_t n_run = (n_blk + kMixBlocksPerWave - 1) / kMixBlocksPerWave;
   const int64_t n_wg = n_run * a.n_chan * a.n_pg;
   if (n_wg == 0) return hipSuccess;
   if (n_wg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
-  if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix16<kPrecFp16>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  if (prec == kPrecFp16 && a.taper) hipLaunchKernelGGL((k_mix16<kPrecFp16, true>), dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  else if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix16<kPrecFp16>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
   else hipLaunchKernelGGL(k_mix16<kPrecFp8>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
   return hipGetLastError();
 }

@@ -153,10 +153,38 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Windowed E-W sums (per-antenna real weights h, Sec. "Controlling beam shape
+// with windowing") of the lane's four N-S positions for all four E-W beams:
+// x[e][2 i], x[e][2 i + 1] = Re, Im of sum_q h_q z_q (-i)^{e q} at position i.
+__device__ __forceinline__ void ew_windowed(const uint32_t* dw, const float (&h)[4][4], float (&x)[4][8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cf w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = cf{h[i][q] * (float)(int)__builtin_amdgcn_sbfe((int)dw[i], 8 * q + 4, 4),
+                h[i][q] * (float)(int)__builtin_amdgcn_sbfe((int)dw[i], 8 * q, 4)};
+    const cf s02 = cadd(w[0], w[2]), d02 = csub(w[0], w[2]), s13 = cadd(w[1], w[3]), d13 = csub(w[1], w[3]);
+    const cf b[4] = {cadd(s02, s13), cf{d02.r + d13.i, d02.i - d13.r}, csub(s02, s13), cf{d02.r - d13.i, d02.i + d13.r}};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      x[e][2 * i] = b[e].r;
+      x[e][2 * i + 1] = b[e].i;
+    }
+  }
+}
+
 // One wavefront per (block, channel, polarisation group).  Lane l = 16 g + n:
 // stage 1 holds a1 = 4 g + q (q < 4) and k2 = 16 kt + n (kt < 2); stage 2
 // takes E-W beam 2 p + (l >> 5) of pair p and k2 = l & 31.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_mix256(MixArgs a) {
+// WIN: per-antenna real weights.  The windowed E-W sums are no longer
+// integers, so each is split into FP16 hi + lo and stage 1 takes three
+// products (hi x hi, hi x lo, lo x hi of data and coefficients).  The
+// window is scaled by a power of two per wavefront so that its largest
+// weight lies in [1/2, 1) and the low terms stay in FP16's normal range;
+// the block sums are scaled back exactly.
+template <bool WIN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WIN ? 2 : 3))) void k_mix256(MixArgs a) {
   constexpr int N = 256, M = 512;
   constexpr int ROW = 18;                     // complex values per (E-W beam, k2) row: 16 a1 + 2 pad
   __shared__ float4 lds_raw[2 * 32 * ROW / 2];
@@ -200,28 +228,71 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[p][k] = 0.f;
 
+  // the window at the lane's N-S positions n + 64 g + 16 i, scaled by 2^-E
+  // with 2^E the power of two just above the wavefront's largest |h|
+  float hw[4][4];
+  float unscale = 1.f;       // 2^{2E}: undoes the scale on |B|^2
+  if constexpr (WIN) {
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 v = *reinterpret_cast<const float4*>(a.taper + 4 * (n + 64 * g + 16 * i));
+      hw[i][0] = v.x;
+      hw[i][1] = v.y;
+      hw[i][2] = v.z;
+      hw[i][3] = v.w;
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) m = fmaxf(m, __shfl_xor(m, d));
+    const int ex = m > 0.f ? ilogbf(m) + 1 : 0;      // m * 2^-ex in [1/2, 1)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hw[i][q] = ldexpf(hw[i][q], -ex);
+    unscale = ldexpf(1.f, 2 * ex);
+  }
+
   const int pol_lo = (a.pol_iter == 1) ? pg : 0;
   const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
   const int64_t frame_stride = (int64_t)a.n_chan * a.n_pol * N;   // dwords per sample
   const int64_t t0 = (int64_t)blk * a.block;
 
   auto frame = [&](const uint32_t (&dw)[4]) {
+    float xw[WIN ? 4 : 1][8];
+    if constexpr (WIN) ew_windowed(dw, hw, xw);
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       // ---- stage 1 and twiddle for E-W beams 2p, 2p + 1, into the tile ----
 #pragma unroll
       for (int ep = 0; ep < 2; ++ep) {
         const int e = 2 * p + ep;
-        const half8 A = ew_pairs_f16(dw, wre[e], wim[e]);
         f32x4 y[2][2];
+        if constexpr (WIN) {
+          uint32_t hi[4], lo[4];
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
+          for (int i = 0; i < 4; ++i) split2(xw[e][2 * i], xw[e][2 * i + 1], hi[i], lo[i]);
+          const half8 Ah = __builtin_bit_cast(half8, hi), Al = __builtin_bit_cast(half8, lo);
 #pragma unroll
-          for (int part = 0; part < 2; ++part) {
-            y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1[0][kt][part], f32x4{0.f, 0.f, 0.f, 0.f},
-                                                                 0, 0, 0);
-            y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1[1][kt][part], y[kt][part], 0, 0, 0);
-          }
+          for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int part = 0; part < 2; ++part) {
+              y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, B1[0][kt][part], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                   0, 0, 0);
+              y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, B1[1][kt][part], y[kt][part], 0, 0, 0);
+              y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Al, B1[0][kt][part], y[kt][part], 0, 0, 0);
+            }
+        } else {
+          const half8 A = ew_pairs_f16(dw, wre[e], wim[e]);
+#pragma unroll
+          for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int part = 0; part < 2; ++part) {
+              y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1[0][kt][part], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                   0, 0, 0);
+              y[kt][part] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1[1][kt][part], y[kt][part], 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt) {
           cf z[4];
@@ -286,9 +357,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   float* o = a.out + (((int64_t)blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
 #pragma unroll
   for (int e = 0; e < 4; ++e)
-    for (int j = lane; j < keep; j += 64) o[e * keep + j] = lds_i[e * M + (sel ? sel[j] : j)] * a.norm;
+    for (int j = lane; j < keep; j += 64) o[e * keep + j] = lds_i[e * M + (sel ? sel[j] : j)] * (a.norm * unscale);
 }
-
 
 // FP8: one wavefront per (block, channel, polarisation group).  Lane
 // l = 16 g + n: stage 1 holds a1 = 4 g + q and k2 = 16 kt + n for the beam
@@ -444,7 +514,9 @@ hipError_t launch_mix256_tables(void* mat, int prec, hipStream_t s) {
 hipError_t launch_mix256(const MixArgs& a, int prec, int64_t n_wg, hipStream_t s) {
   if (n_wg == 0) return hipSuccess;
   if (n_wg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
-  if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix256, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  if (prec == kPrecFp16 && a.taper) hipLaunchKernelGGL(k_mix256<true>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  else if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix256<false>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
+  else if (prec == kPrecFp8 && a.taper) return hipErrorNotSupported;
   else if (prec == kPrecFp8) hipLaunchKernelGGL(k_mix256_fp8, dim3((unsigned)n_wg), dim3(64), 0, s, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();

@@ -138,6 +138,8 @@ hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t n_wg, hipStr
 size_t mix_table_bytes(int n_ns, int prec);
 hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s);
 bool mix_supported(int n_ns, int prec, int block);
+// per-antenna real weights on the matrix cores (windowed data split into FP16 terms)
+bool mix_window_supported(int n_ns, int prec);
 // the 4 x 256 lattice (k_mix256.hip): stage 1 on the matrix cores (FP16 or
 // FP8), stage 2 in FP32
 size_t mix256_table_bytes();

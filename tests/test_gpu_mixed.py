@@ -182,3 +182,89 @@ def test_lattice4x16_scaled_full_size_sampled(prec):
     plan.close()
     del v, out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("scale", [1.0, 40.0, 1e-3])
+def test_mix256_window_parity(scale):
+    """Per-antenna real weights on the FP16 matrix-core path at the 4 x 256
+    lattice (Sec. "Controlling beam shape with windowing"): the windowed E-W
+    sums are split into FP16 hi + lo terms, so the result is held to the FP32
+    bar.  Weights scaled by 40 and 1e-3 test the per-wavefront power-of-two
+    scaling that keeps the low terms in FP16's normal range."""
+    w = sg.custom_workload(n_ew=4, n_ns=256, n_chan=3, n_pol=2, n_time=48, seed=91, n_src=3, snr=12.0,
+                           n_ns_keep=256, dl=(0.4, 0.8))
+    v = sg.volts(w)
+    h = (sg.gaussian_taper(4, 256) * scale).astype(np.float32)
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    vt = torch.from_numpy(v).cuda()
+    ht = torch.from_numpy(h).cuda()
+    h64 = h.astype(np.float64)
+    for pol_sum in (False, True):
+        plan = plan_for(w, precision=1, pol_sum=pol_sum)
+        got = bf.beamform_fft(plan, vt, taper=ht).cpu().numpy()
+        plan.close()
+        ref = orc.beamform_fft(v, 4, 512, 16, taper=h64, ns_select=w.ns_select(), pol_sum=pol_sum)
+        err = rel_err(got, ref)
+        print(f"4x256 FP16 MFMA with window x{scale}, pol_sum={pol_sum}: max rel beam-power error {err:.3e}")
+        assert err < 1e-5
+    plan = plan_for(w, precision=2)
+    with pytest.raises(bf.BFError) as e:
+        bf.beamform_fft(plan, vt, taper=ht)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    plan.close()
+
+
+def test_mix256_window_c2_full_size():
+    """The Gaussian window on the CHIME-shaped workload at full size through the
+    FP16 matrix-core plan, against the oracle over the full-size comparison
+    set, held to the FP32 bar."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c2")
+    plan = plan_for(w, precision=1)
+    h = sg.gaussian_taper(w.n_ew, w.n_ns).astype(np.float32)
+    v = sg.volts(w, backend="torch", device="cuda")
+    out = bf.beamform_fft(plan, v, taper=torch.from_numpy(h).cuda())
+    torch.cuda.synchronize()
+    sel = w.ns_select()
+    h64 = h.astype(np.float64)
+    worst = c2_wide_worst(w, v, out, lambda x, ch: orc.beamform_fft(x, w.m_ew, w.m_ns, 16, taper=h64,
+                                                                      ns_select=sel[ch]))
+    print(f"4x256 FP16 MFMA with window, full size: max rel beam-power error {worst:.3e}")
+    assert worst < 1e-5
+    plan.close()
+    del v, out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("scale", [1.0, 40.0, 1e-3])
+def test_mix16_window_parity(scale):
+    """Per-antenna real weights on the FP16 matrix-core path of the 4 x 16
+    lattice: the C3-shaped Gaussian window (width 0.4 of the aperture) on the
+    tiny workload's bytes, and a half-sine window over several channels, pols
+    and a clamp, held to the FP32 bar; scaled weights test the per-wavefront
+    power-of-two scaling."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.make_workload("c3")
+    v = sg.volts(w)
+    h = (sg.gaussian_taper(4, 16) * scale).astype(np.float32)
+    plan = plan_for(w, precision=1)
+    got = bf.beamform_fft(plan, torch.from_numpy(v).cuda(), taper=torch.from_numpy(h).cuda()).cpu().numpy()
+    plan.close()
+    ref = orc.beamform_fft(v, 4, 32, 16, taper=h.astype(np.float64))
+    err = rel_err(got, ref)
+    print(f"C3 shape, FP16 MFMA with window x{scale}: max rel beam-power error {err:.3e}")
+    assert err < 1e-5
+    w2 = sg.custom_workload(n_ew=4, n_ns=16, n_chan=3, n_pol=2, n_time=96, seed=23, n_src=2, snr=8.0,
+                            n_ns_keep=20, dl=(0.4, 0.8))
+    v2 = sg.volts(w2)
+    h2 = (sg.half_sine_taper(4, 16, shifted=True) * scale).astype(np.float32)
+    for pol_sum in (False, True):
+        plan = plan_for(w2, precision=1, pol_sum=pol_sum)
+        got = bf.beamform_fft(plan, torch.from_numpy(v2).cuda(), taper=torch.from_numpy(h2).cuda()).cpu().numpy()
+        plan.close()
+        ref = orc.beamform_fft(v2, 4, 32, 16, taper=h2.astype(np.float64), ns_select=w2.ns_select(),
+                               pol_sum=pol_sum)
+        assert rel_err(got, ref) < 1e-5
