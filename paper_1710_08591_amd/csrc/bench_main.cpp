@@ -5,6 +5,7 @@
 //               [--precision 0|1|2] [--steps S] [--warmup W] [--random 0|1]
 //   fftbf_bench --copy 1 [--steps S]
 //   fftbf_bench --issue 1
+//   fftbf_bench --mfma K      (K = 0, 1, 2: one MFMA form; 3: all three)
 //
 // Voltages are device-resident, filled with a fixed byte pattern (0x5A) or,
 // with --random 1, with hashed bytes: the memory traffic and the instruction
@@ -143,6 +144,92 @@ done:
   return rc;
 }
 
+// Matrix-core issue probe: each wavefront runs kMfmaChains independent
+// accumulator chains of one MFMA form, `iters` times, so a launch issues a
+// known number of MFMA instructions (blocks x 4 wavefronts x iters x chains):
+// the rate per SIMD and the reading of SQ_INSTS_MFMA can both be checked
+// against it.  kind 0: v_mfma_f32_16x16x32_f16; 1: v_mfma_f32_16x16x32_fp8_fp8;
+// 2: v_mfma_scale_f32_16x16x128_f8f6f4 (FP8 e4m3 operands, unit block scales).
+constexpr int kMfmaChains = 4;
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef int i32x8_t __attribute__((ext_vector_type(8)));
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_mfma_issue(float* out, int iters) {
+  f32x4_t c[kMfmaChains];
+#pragma unroll
+  for (int i = 0; i < kMfmaChains; ++i) c[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int t = (int)threadIdx.x;
+  half8_t ha, hb;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    ha[j] = (_Float16)(1e-3f * (float)((t + j) & 7));
+    hb[j] = (_Float16)(1e-3f * (float)((t * 3 + j) & 7));
+  }
+  const long la = 0x3830282018100800L + t, lb = 0x0810182028303840L - t;   // small e4m3 values
+  i32x8_t wa, wb;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    wa[j] = (int)(la >> (4 * (j & 1))) & 0x3F3F3F3F;
+    wb[j] = (int)(lb >> (4 * (j & 1))) & 0x3F3F3F3F;
+  }
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < kMfmaChains; ++i) {
+      if constexpr (KIND == 0) c[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ha, hb, c[i], 0, 0, 0);
+      else if constexpr (KIND == 1) c[i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(la, lb, c[i], 0, 0, 0);
+      else c[i] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wa, wb, c[i], 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < kMfmaChains; ++i) s += c[i][0] + c[i][1] + c[i][2] + c[i][3];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+int mfma_probe(int only_kind) {
+  const int threads = 256, iters = 4000, cus = 256;
+  float* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = 1;
+  const char* names[3] = {"v_mfma_f32_16x16x32_f16", "v_mfma_f32_16x16x32_fp8_fp8",
+                          "v_mfma_scale_f32_16x16x128_f8f6f4"};
+  const double flop[3] = {16.0 * 16 * 32 * 2, 16.0 * 16 * 32 * 2, 16.0 * 16 * 128 * 2};
+  if (!ok_hip(hipMalloc(&out, sizeof(float) * cus * 8 * threads), "hipMalloc out")) goto done;
+  if (!ok_hip(hipEventCreate(&e0), "hipEventCreate") || !ok_hip(hipEventCreate(&e1), "hipEventCreate")) goto done;
+  for (int kind = 0; kind < 3; ++kind) {
+    if (only_kind >= 0 && kind != only_kind) continue;
+    for (int wps = 1; wps <= 4; wps *= 2) {
+      const int blocks = cus * wps;            // a block is 4 wavefronts, one per SIMD of a compute unit
+      float best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        if (!ok_hip(hipEventRecord(e0, 0), "hipEventRecord")) goto done;
+        if (kind == 0) hipLaunchKernelGGL(k_mfma_issue<0>, dim3(blocks), dim3(threads), 0, 0, out, iters);
+        if (kind == 1) hipLaunchKernelGGL(k_mfma_issue<1>, dim3(blocks), dim3(threads), 0, 0, out, iters);
+        if (kind == 2) hipLaunchKernelGGL(k_mfma_issue<2>, dim3(blocks), dim3(threads), 0, 0, out, iters);
+        if (!ok_hip(hipGetLastError(), "k_mfma_issue") || !ok_hip(hipEventRecord(e1, 0), "hipEventRecord") ||
+            !ok_hip(hipEventSynchronize(e1), "hipEventSynchronize"))
+          goto done;
+        float ms = 0.f;
+        if (!ok_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) goto done;
+        if (ms < best) best = ms;
+      }
+      const double instr = (double)blocks * (threads / 64) * iters * kMfmaChains;
+      const double per_simd_cycle = instr / (best * 1e-3) / (cus * 4) / 2.4e9;
+      std::printf("fftbf_bench: %-34s %d wavefronts per SIMD: %.3f ms, %.0f MFMA per launch, %.4f per SIMD and "
+                  "cycle at 2.4 GHz (%.1f cycles each), %.1f TFLOP/s\n", names[kind], wps, best, instr,
+                  per_simd_cycle, 1.0 / per_simd_cycle, instr * flop[kind] / (best * 1e-3) / 1e12);
+    }
+  }
+  rc = 0;
+done:
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (out) (void)hipFree(out);
+  return rc;
+}
+
 bool ok_bf(bf_status s, const char* what) {
   if (s == BF_OK) return true;
   std::fprintf(stderr, "%s: %s: %s\n", what, bf_status_string(s), bf_last_error());
@@ -163,6 +250,7 @@ int main(int argc, char** argv) {
   const int random = arg_int(argc, argv, "--random", 0);
   const int copy = arg_int(argc, argv, "--copy", 0);
   const int issue = arg_int(argc, argv, "--issue", 0);
+  const int mfma = arg_int(argc, argv, "--mfma", -1);
   if (n_ns <= 0 || n_chan <= 0 || n_pol <= 0 || n_time <= 0 || keep < 0 || keep > 2 * n_ns || steps <= 0 ||
       warmup < 0 || (random != 0 && random != 1) || (copy != 0 && copy != 1) ||
       (issue != 0 && issue != 1)) {
@@ -171,6 +259,7 @@ int main(int argc, char** argv) {
   }
   if (copy) return copy_calibration(steps);
   if (issue) return issue_probe();
+  if (mfma >= 0) return mfma_probe(mfma <= 2 ? mfma : -1);
 
   std::vector<int32_t> sel;
   bf_plan_desc d{};

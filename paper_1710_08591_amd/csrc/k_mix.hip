@@ -77,17 +77,28 @@ __global__ void k_mix_tables(void* tab) {
     t[0 * stride + i] = hi;
     t[1 * stride + i] = lo;
   } else {
-    uint8_t* t = static_cast<uint8_t*>(tab);
-    double r = v;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const double sc = (double)(1 << fp8_shift(p));
-      const int b = f32_to_fp8((float)(r * sc));
-      t[p * stride + i] = (uint8_t)b;
-      r -= (double)fp8_to_f32(b) / sc;
+    // K = 128 operand of v_mfma_scale_f32_16x16x128_f8f6f4: lane (g, n), byte
+    // j = 8 t + 2 q + comp holds term t (t = 3: zero) of the coefficient of
+    // (a_ns = 4 g + q, comp), stored times 2^fp8_shift(t)
+    (void)v;
+    (void)stride;
+    const int q = (j >> 1) & 3, comp = j & 1, g = lane >> 4;
+    double r = mix_coef(kt, part, comp * 16 + 4 * g + q, n);
+    uint8_t* t = static_cast<uint8_t*>(tab) + ((kt * 2 + part) * 64 + lane) * 32 + (j & 7);
+    // this thread fills bytes (j & 7) + 8 t of the lane; j < 8 covers all
+    if (j < 8) {
+      for (int p = 0; p < P; ++p) {
+        const double sc = (double)(1 << fp8_shift(p));
+        const int b = f32_to_fp8((float)(r * sc));
+        t[8 * p] = (uint8_t)b;
+        r -= (double)fp8_to_f32(b) / sc;
+      }
+      t[24] = 0;
     }
   }
 }
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 template <int PREC>
 __device__ __forceinline__ typename Mix<PREC>::op_t load_b(const void* tab, int p, int kt, int part, int lane) {
@@ -164,15 +175,25 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
   const int64_t blk0 = (int64_t)run * kMixBlocksPerWave;
   const int64_t blk1 = blk0 + kMixBlocksPerWave < n_blk ? blk0 + kMixBlocksPerWave : n_blk;
 
-  op_t B[P][2][2];
+  // FP16: B[term][kt][part]; FP8: the three terms stacked along K = 128 in B8[kt][part]
+  op_t B[PREC == kPrecFp16 ? P : 1][2][2];
+  i32x8 B8[PREC == kPrecFp8 ? 2 : 1][2];
+  if constexpr (PREC == kPrecFp16) {
 #pragma unroll
-  for (int p = 0; p < P; ++p)
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int part = 0; part < 2; ++part) B[p][kt][part] = load_b<PREC>(a.mat, p, kt, part, lane);
+  } else {
 #pragma unroll
     for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-      for (int part = 0; part < 2; ++part) B[p][kt][part] = load_b<PREC>(a.mat, p, kt, part, lane);
+      for (int part = 0; part < 2; ++part)
+        B8[kt][part] = *reinterpret_cast<const i32x8*>(static_cast<const uint8_t*>(a.mat) +
+                                                        ((kt * 2 + part) * 64 + lane) * 32);
+  }
 
-  const int sh = (g >> 1) ? 0 : 4;            // real part: high nibble, imaginary: low
   int wts[4];                                 // FP16: E-W dot8 weights of this lane's component
 #pragma unroll
   for (int e = 0; e < 4; ++e) wts[e] = ew_dot_weights(e, g >> 1);
@@ -280,14 +301,28 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
           // products, then the E-W 4-point DFT in FP32 on the accumulators;
           // one beam tile (kt) at a time, so that only half of the
           // accumulators are live
-          op_t A[4][P];
+          // lane (g, n): sample n at N-S positions 4 g + q (the dwords of
+          // fr[g]); per column its 8 (position, re|im) values once per term
+          // (times 2^-shift), then 8 zeros, along K = 128
+          const uint4 d4 = fr[g];
+          const uint32_t dq[4] = {d4.x, d4.y, d4.z, d4.w};
+          i32x8 A[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             int v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = (int)__builtin_amdgcn_sbfe((int)dw[j], 8 * c + sh, 4);
+            for (int q = 0; q < 4; ++q) {
+              v[2 * q] = (int)__builtin_amdgcn_sbfe((int)dq[q], 8 * c + 4, 4);
+              v[2 * q + 1] = (int)__builtin_amdgcn_sbfe((int)dq[q], 8 * c, 4);
+            }
 #pragma unroll
-            for (int p = 0; p < P; ++p) A[c][p] = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
+            for (int p = 0; p < 3; ++p) {
+              const long w = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
+              A[c][2 * p] = (int)w;
+              A[c][2 * p + 1] = (int)(w >> 32);
+            }
+            A[c][6] = 0;
+            A[c][7] = 0;
           }
 #pragma unroll
           for (int kt = 0; kt < 2; ++kt) {
@@ -297,8 +332,8 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
 #pragma unroll
               for (int part = 0; part < 2; ++part) {
                 acc[c][part] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int p = 0; p < P; ++p) acc[c][part] = mfma<PREC>(A[c][p], B[p][kt][part], acc[c][part]);
+                acc[c][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                    A[c], B8[kt][part], acc[c][part], 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
               }
             // E-W 4-point DFT across the four columns, |B|^2, sum of the lane's 4 samples
 #pragma unroll
@@ -357,7 +392,7 @@ bool mix_supported(int n_ns, int prec, int block) {
 
 size_t mix_table_bytes(int n_ns, int prec) {
   if (n_ns == 256) return mix256_table_bytes();
-  return prec == kPrecFp16 ? (size_t)Mix<kPrecFp16>::P * 2048 * 2 : (size_t)Mix<kPrecFp8>::P * 2048;
+  return prec == kPrecFp16 ? (size_t)Mix<kPrecFp16>::P * 2048 * 2 : (size_t)2 * 2 * 64 * 32;
 }
 
 hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
