@@ -661,8 +661,11 @@ def _serve_saturated(srv, reqs) -> dict:
             "requests_per_s": done / span, "beam_samples_per_s": beam_samples / span}
 
 
-def run_serving(dev, n_req: int = 5200, n_warm: int = 200, rate_hz: float = 200.0, n_sat: int = 1000) -> dict:
-    """Open-loop serving of tied-beam requests from a 1 GiB device voltage ring."""
+def run_serving(dev, n_req: int = 5200, n_warm: int = 200, rate_hz: float = 200.0, n_sat: int = 1000,
+                writer_rate: float = 390625.0) -> dict:
+    """Open-loop serving of tied-beam requests from a 1 GiB device voltage ring,
+    with a writer appending voltages at ``writer_rate`` samples/s meanwhile
+    (one sample every 2.56 us, a CHIME-like channelised sample rate)."""
     import numpy as np
     import torch
 
@@ -683,10 +686,31 @@ def run_serving(dev, n_req: int = 5200, n_warm: int = 200, rate_hz: float = 200.
     lat = {}
     rejected = 0
     beam_samples = 0
+    # a live writer appends voltages to the ring at a fixed sample rate, in
+    # chunks, while requests are served; a chunk that would overwrite a leased
+    # window is refused and retried (the writer falls behind), and is forced
+    # (evicting the lease holders) only once the backlog passes half the ring
+    chunk = 1024
+    wsrc = sg.volts(w, 0, chunk, backend="torch", device=dev)
+    torch.cuda.synchronize()
+    writer = {"samples_per_s": writer_rate, "chunk_samples": chunk, "advances": 0, "refused": 0, "forced": 0,
+              "max_backlog_samples": 0}
+    written = 0
     t_base = srv.now() + 0.05
     i = 0
     while i < len(reqs) or pending:
         now = srv.now()
+        backlog = int((now - t_base) * writer_rate) - written if now > t_base else 0
+        writer["max_backlog_samples"] = max(writer["max_backlog_samples"], backlog)
+        if backlog >= chunk:
+            force = backlog > w.n_time // 2
+            st = srv.advance(chunk, wsrc, force=force)
+            if st == bf.BF_OK:
+                written += chunk
+                writer["advances"] += 1
+                writer["forced"] += int(force)
+            else:
+                writer["refused"] += 1
         while i < len(reqs) and t_base + reqs[i].arrival_s <= now:
             r = reqs[i]
             st, rid = srv.try_submit(r.dircos, r.chan_lo, r.n_chan, r.n_time, arrival=t_base + r.arrival_s)
@@ -708,6 +732,8 @@ def run_serving(dev, n_req: int = 5200, n_warm: int = 200, rate_hz: float = 200.
             srv.release(rid)
     t_end = srv.now()
     st = srv.stats()
+    writer["achieved_samples_per_s"] = written / (t_end - t_base)
+    writer["evicted_requests"] = st.get("evicted")
     sat = _serve_saturated(srv, sg.request_stream(n_sat, seed=6, rate_hz=rate_hz, n_chan_total=w.n_chan))
     srv.close()
     measured = [lat[k] for k in sorted(lat) if k >= n_warm]
@@ -715,12 +741,14 @@ def run_serving(dev, n_req: int = 5200, n_warm: int = 200, rate_hz: float = 200.
     span = t_end - min(arr)
     ms = np.array(measured) * 1e3
     return {"workload": "tied-beam requests on a 4x16 lattice ring (65536 samples x 256 chan x 1 pol, 1 GiB); "
-                        "Poisson 200/s; pointings, duration (1024-65536) and channel count (8-256) log-uniform",
+                        "Poisson 200/s; pointings, duration (1024-65536) and channel count (8-256) log-uniform; "
+                        "a live writer appends voltages at one sample per 2.56 us meanwhile",
             "requests": n_req, "warmup_requests": n_warm, "rejected": rejected,
             "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
             "mean_ms": float(ms.mean()), "max_ms": float(ms.max()),
             "requests_per_s": len(measured) / span, "beam_samples_per_s": beam_samples / span,
             "launches": st["launches"], "tiles": st["tiles_done"], "hbm_budget_bytes": budget,
+            "live_writer": writer,
             "max_sustainable": dict(sat, workload="closed loop over the same request mix (seed 6): "
                                                   "each request submitted as soon as memory admits it")}
 
