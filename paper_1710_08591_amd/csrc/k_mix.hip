@@ -380,19 +380,312 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
   }
 }
 
+// ---- 4 x 32, 4 x 64, 4 x 128: polyphase split onto the 16 -> 32 products ----
+//
+// With n = 16 R N-S positions (R = 2, 4, 8) and M = 2 n = 32 R beams:
+//   a = R a' + a0   (a' < 16, a0 < R),   A = m + 32 r   (m < 32, r < R)
+//   D_a0[m]     = sum_{a'} x[R a' + a0] W_32^{a' m}              (matrix cores)
+//   Y[m + 32 r] = sum_{a0} (W_M^{a0 m} D_a0[m]) W_R^{a0 r}        (FP32)
+// since W_M^{a A} = W_32^{a' m} W_M^{a0 m} W_R^{a0 r}.  Each D_a0 is the
+// zero-padded 16 -> 32 transform above, with the same operand tables, on the
+// dwords of one polyphase (stride R); the accumulator layout puts every
+// D_a0[m] of one (sample, m) in one lane, so the twiddles W_M^{a0 m} (FP64-
+// generated, rounded to FP32) and the R-point DFT over a0 run in that lane.
+// |B|^2 is summed over the lane's four samples, then over the four sample
+// groups by cross-lane adds, and each sum lands in the LDS in a slot that one
+// lane owns.
+// FP8: e4m3 holds every integer up to 16 but not every E-W sum, so the data
+// operand takes the first radix-2 stage of the E-W DFT only (x0 +- x2 and
+// x1 +- x3, exact) and the second stage runs in FP32 on the accumulators:
+//   B_0 = S02 + S13,  B_2 = S02 - S13,  B_1 = D02 - i D13,  B_3 = D02 + i D13.
+// Below R = 8 one pass makes both E-W beams of a pair from the same four
+// products; at R = 8 each pass makes one (fewer live registers).
+constexpr size_t kMixTwOff = 8192;   // twiddles after the 16 -> 32 operand table
+
+// W_M^{a0 m} with M = 32 R, as float2 at [m][a0]
+__global__ void k_mixp_twiddles(void* tab, int R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 32 * R) return;
+  const int m = i / R, a0 = i % R;
+  double s, c;
+  sincospi(-2.0 * (double)((a0 * m) % (32 * R)) / (double)(32 * R), &s, &c);
+  reinterpret_cast<float2*>(static_cast<char*>(tab) + kMixTwOff)[i] = make_float2((float)c, (float)s);
+}
+
+// dot8 weights (Re, Im) of the first-stage E-W sums: column 0 x0 + x2,
+// 1 x1 + x3, 2 x0 - x2, 3 x1 - x3
+__device__ __forceinline__ void ew_half_weights(int col, int& wre, int& wim) {
+  const int sgn = col < 2 ? 1 : 0xF;
+  const int q0 = col & 1, q1 = q0 + 2;
+  wre = (1 << (8 * q0 + 4)) | (sgn << (8 * q1 + 4));
+  wim = (1 << (8 * q0)) | (sgn << (8 * q1));
+}
+
+template <int PREC, int R, bool WIN>
+__global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
+  static_assert(!WIN || PREC == kPrecFp16, "windows run on the FP16 path");
+  constexpr int N = 16 * R, M = 2 * N;
+  constexpr bool PAIR = PREC == kPrecFp8 && R <= 4;
+  constexpr int NE = PAIR ? 2 : 1;               // E-W beams per pass
+  constexpr int NPASS = PAIR ? 2 : 4;
+  constexpr int NDW = PREC == kPrecFp16 ? 8 * R : 4 * R;   // dwords per lane per sample
+  constexpr int P = Mix<PREC>::P;
+  using op_t = typename Mix<PREC>::op_t;
+  __shared__ float lds_i[4 * M];
+
+  const int lane = threadIdx.x;
+  const int n = lane & 15, g = lane >> 4;
+  int wg = blockIdx.x;
+  const int pg = wg % a.n_pg;
+  wg /= a.n_pg;
+  const int chan = wg % a.n_chan;
+  const int run = wg / a.n_chan;
+  const int64_t n_blk = a.n_time / a.block;
+  const int64_t blk0 = (int64_t)run * kMixBlocksPerWave;
+  const int64_t blk1 = blk0 + kMixBlocksPerWave < n_blk ? blk0 + kMixBlocksPerWave : n_blk;
+
+  const float2* twt = reinterpret_cast<const float2*>(static_cast<const char*>(a.mat) + kMixTwOff);
+
+  const int comp = g >> 1;                 // FP16: the lane's component of the data operand
+
+  // WIN: component `comp` of (-i)^k z is s_k * (nibble at offset o_k) with
+  // comp 0: (+Re, +Im, -Re, -Im), comp 1: (+Im, -Re, -Im, +Re) for k = 0..3
+  float wsg[4];
+  int woff[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int kk = (k + comp) & 3;         // comp 1 is comp 0 of (-i) w
+    wsg[k] = kk < 2 ? 1.f : -1.f;
+    woff[k] = (kk & 1) ? 0 : 4;
+  }
+  float wscale = 1.f, unscale = 1.f;       // 2^-E on the window, 2^{2E} back on |B|^2
+  if constexpr (WIN) {
+    float mx = 0.f;
+    for (int i = lane; i < 4 * N; i += 64) mx = fmaxf(mx, fabsf(a.taper[i]));
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) mx = fmaxf(mx, __shfl_xor(mx, d));
+    const int ex = mx > 0.f ? ilogbf(mx) + 1 : 0;
+    wscale = ldexpf(1.f, -ex);
+    unscale = ldexpf(1.f, 2 * ex);
+  }
+
+  const int pol_lo = (a.pol_iter == 1) ? pg : 0;
+  const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
+  const int keep = a.n_keep;
+  const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
+
+  for (int i = lane; i < 4 * M; i += 64) lds_i[i] = 0.f;
+  __syncthreads();
+
+  for (int64_t blk = blk0; blk < blk1; ++blk) {
+    for (int pol = pol_lo; pol < pol_hi; ++pol) {
+      for (int sub = 0; sub < a.block; sub += 16) {
+        const int64_t t = blk * a.block + sub + n;
+        const uint32_t* frame = a.volts + ((t * a.n_chan + chan) * a.n_pol + pol) * N;
+        // FP16: positions R a' + a0 with a' in [8 (g & 1), + 8); FP8: a' in [4 g, + 4)
+        const uint4* fr = reinterpret_cast<const uint4*>(frame + (PREC == kPrecFp16 ? 8 * R * (g & 1) : 4 * R * g));
+        uint32_t dw[NDW];
+#pragma unroll
+        for (int k = 0; k < NDW / 4; ++k) {
+          const uint4 d = fr[k];
+          dw[4 * k] = d.x;
+          dw[4 * k + 1] = d.y;
+          dw[4 * k + 2] = d.z;
+          dw[4 * k + 3] = d.w;
+        }
+
+        // one pass per E-W beam (FP8 below R = 8: per pair), not unrolled:
+        // the passes share no values, and one at a time bounds the registers
+#pragma unroll 1
+        for (int ps = 0; ps < NPASS; ++ps) {
+          const int wt = ew_dot_weights(ps, comp);           // FP16: E-W dot8 weights
+          int cwr[2], cwi[2];                                 // FP8: the pair's first-stage sums
+          ew_half_weights(2 * (ps & 1), cwr[0], cwi[0]);
+          ew_half_weights(2 * (ps & 1) + 1, cwr[1], cwi[1]);
+          // the beam tiles m < 16 and m >= 16 in turn (not unrolled either): their
+          // operand columns and twiddles come from the plan table (cached) per tile
+#pragma unroll 1
+          for (int kt = 0; kt < 2; ++kt) {
+            if constexpr (WIN) {
+              // the windowed sums are formed per tile: without this the compiler
+              // converts every nibble of the frame ahead of the loops and holds them
+#pragma unroll
+              for (int k = 0; k < NDW; ++k) asm volatile("" : "+v"(dw[k]));
+            }
+            op_t B[PREC == kPrecFp16 ? P : 1][2];
+            i32x8 B8[2];
+#pragma unroll
+            for (int part = 0; part < 2; ++part) {
+              if constexpr (PREC == kPrecFp16) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) B[p][part] = load_b<PREC>(a.mat, p, kt, part, lane);
+              } else {
+                B8[part] = *reinterpret_cast<const i32x8*>(static_cast<const uint8_t*>(a.mat) +
+                                                            ((kt * 2 + part) * 64 + lane) * 32);
+              }
+            }
+            cf tw[R];                          // W_M^{a0 m} of the lane's m = 16 kt + n
+#pragma unroll
+            for (int a0 = 1; a0 < R; ++a0) {
+              const float2 v = twt[(16 * kt + n) * R + a0];
+              tw[a0] = cf{v.x, v.y};
+            }
+            cf y[NE][R][4];
+#pragma unroll
+            for (int a0 = 0; a0 < R; ++a0) {
+              if constexpr (WIN) __builtin_amdgcn_sched_barrier(0);   // one polyphase's loads at a time
+              if constexpr (PREC == kPrecFp16 && !WIN) {
+                uint32_t sdw[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) sdw[j] = dw[R * j + a0];
+                const half8 A = ew_sums_f16(sdw, wt);
+                f32x4 c[2];
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                  c[part] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                  for (int p = 0; p < P; ++p) c[part] = mfma<PREC>(A, B[p][part], c[part]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) y[0][a0][i] = cf{c[0][i], c[1][i]};
+              } else if constexpr (WIN) {
+                // windowed E-W sum of beam ps, component comp, at the lane's
+                // eight positions of polyphase a0, scaled by 2^-E
+                float xv[8];
+                // the window is loop-invariant: reading it here again (through a
+                // pointer the compiler cannot follow) keeps it out of registers
+                const float* tp = a.taper;
+                asm volatile("" : "+s"(tp));
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                  const int pos = R * (8 * (g & 1) + j) + a0;
+                  const float4 h = *reinterpret_cast<const float4*>(tp + 4 * pos);
+                  const float hq[4] = {h.x, h.y, h.z, h.w};
+                  float s = 0.f;
+#pragma unroll
+                  for (int q = 0; q < 4; ++q) {
+                    const int k = (ps * q) & 3;
+                    const float v = (float)(int)__builtin_amdgcn_sbfe((int)dw[R * j + a0], 8 * q + woff[k], 4);
+                    s = fmaf(hq[q] * wsg[k], v, s);
+                  }
+                  xv[j] = s * wscale;
+                }
+                uint32_t hi[4], lo[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) split2(xv[2 * j], xv[2 * j + 1], hi[j], lo[j]);
+                const half8 Ah = __builtin_bit_cast(half8, hi), Al = __builtin_bit_cast(half8, lo);
+                f32x4 c[2];
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                  c[part] = mfma<PREC>(Ah, B[0][part], f32x4{0.f, 0.f, 0.f, 0.f});
+                  c[part] = mfma<PREC>(Ah, B[1][part], c[part]);
+                  c[part] = mfma<PREC>(Al, B[0][part], c[part]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) y[0][a0][i] = cf{c[0][i], c[1][i]};
+              } else {
+                // FP8: the two first-stage columns of pair ep at the lane's
+                // four positions R (4 g + q) + a0, three scaled terms along K
+                const int ep = ps & 1;
+                f32x4 c[2][2];
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                  int v[8];
+#pragma unroll
+                  for (int q = 0; q < 4; ++q) {
+                    v[2 * q] = sdot8((int)dw[R * q + a0], cwr[cc]);
+                    v[2 * q + 1] = sdot8((int)dw[R * q + a0], cwi[cc]);
+                  }
+                  i32x8 A;
+#pragma unroll
+                  for (int p = 0; p < 3; ++p) {
+                    const long w = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
+                    A[2 * p] = (int)w;
+                    A[2 * p + 1] = (int)(w >> 32);
+                  }
+                  A[6] = 0;
+                  A[7] = 0;
+#pragma unroll
+                  for (int part = 0; part < 2; ++part)
+                    c[cc][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        A, B8[part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
+                }
+                // second E-W stage: pair 0 gives beams 0 (sum) and 2 (difference),
+                // pair 1 beams 1 (D02 - i D13) and 3 (D02 + i D13)
+#pragma unroll
+                for (int w = 0; w < NE; ++w) {
+                  const int up = PAIR ? w : (ps >> 1);     // 0: beam ep, 1: beam ep + 2
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) {
+                    const float ar = c[0][0][i], ai = c[0][1][i], br = c[1][0][i], bi = c[1][1][i];
+                    if (ep == 0) y[w][a0][i] = up ? cf{ar - br, ai - bi} : cf{ar + br, ai + bi};
+                    else y[w][a0][i] = up ? cf{ar - bi, ai + br} : cf{ar + bi, ai - br};
+                  }
+                }
+              }
+            }
+            // twiddle, R-point DFT over a0, |B|^2 over the lane's four samples
+#pragma unroll
+            for (int w = 0; w < NE; ++w) {
+              const int e = PAIR ? (ps & 1) + 2 * w : ps;
+              float v[R];
+#pragma unroll
+              for (int r = 0; r < R; ++r) v[r] = 0.f;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                cf z[R];
+                z[0] = y[w][0][i];
+#pragma unroll
+                for (int a0 = 1; a0 < R; ++a0) z[a0] = cmul(y[w][a0][i], tw[a0]);
+                dit<R>(z);
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = cnorm_acc(z[r], v[r]);
+              }
+              // sum the four sample groups; lane group g owns r = g, g + 4, ...
+              // (masked per r, so that no register array is indexed at run time)
+#pragma unroll
+              for (int r = 0; r < R; ++r) {
+                v[r] += __shfl_xor(v[r], 16);
+                v[r] += __shfl_xor(v[r], 32);
+                if ((r & 3) == g) lds_i[e * M + 16 * kt + n + 32 * r] += v[r];
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    float* o = a.out + ((blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
+    for (int idx = lane; idx < 4 * keep; idx += 64) {
+      const int e = idx / keep, j = idx - e * keep;
+      o[idx] = lds_i[e * M + (sel ? sel[j] : j)] * (a.norm * unscale);
+    }
+    __syncthreads();
+    for (int i = lane; i < 4 * M; i += 64) lds_i[i] = 0.f;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
-bool mix_window_supported(int n_ns, int prec) { return (n_ns == 16 || n_ns == 256) && prec == kPrecFp16; }
+// polyphase factor R of the 4 x 16 R lattices (0: not one of them)
+static int mixp_r(int n_ns) { return n_ns == 32 ? 2 : n_ns == 64 ? 4 : n_ns == 128 ? 8 : 0; }
+
+bool mix_window_supported(int n_ns, int prec) {
+  return (n_ns == 16 || mixp_r(n_ns) || n_ns == 256) && prec == kPrecFp16;
+}
 
 bool mix_supported(int n_ns, int prec, int block) {
-  if (n_ns == 16) return (prec == kPrecFp16 || prec == kPrecFp8) && block % 16 == 0;
+  if (n_ns == 16 || mixp_r(n_ns)) return (prec == kPrecFp16 || prec == kPrecFp8) && block % 16 == 0;
   if (n_ns == 256) return (prec == kPrecFp16 || prec == kPrecFp8) && block >= 1;
   return false;
 }
 
 size_t mix_table_bytes(int n_ns, int prec) {
   if (n_ns == 256) return mix256_table_bytes();
-  return prec == kPrecFp16 ? (size_t)Mix<kPrecFp16>::P * 2048 * 2 : (size_t)2 * 2 * 64 * 32;
+  const size_t base = prec == kPrecFp16 ? (size_t)Mix<kPrecFp16>::P * 2048 * 2 : (size_t)2 * 2 * 64 * 32;
+  static_assert(kMixTwOff == 8192, "twiddles follow the operand table of either precision");
+  return mixp_r(n_ns) ? kMixTwOff + sizeof(float2) * 32 * mixp_r(n_ns) : base;
 }
 
 hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
@@ -400,7 +693,15 @@ hipError_t launch_mix_tables(void* mat, int n_ns, int prec, hipStream_t s) {
   if (n_ns == 256) return launch_mix256_tables(mat, prec, s);
   if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix_tables<kPrecFp16>, dim3(8), dim3(256), 0, s, mat);
   else hipLaunchKernelGGL(k_mix_tables<kPrecFp8>, dim3(8), dim3(256), 0, s, mat);
+  if (const int r = mixp_r(n_ns)) hipLaunchKernelGGL(k_mixp_twiddles, dim3(1), dim3(256), 0, s, mat, r);
   return hipGetLastError();
+}
+
+template <int R>
+static void launch_mixp(const MixArgs& a, int prec, unsigned n_wg, hipStream_t s) {
+  if (prec == kPrecFp16 && a.taper) hipLaunchKernelGGL((k_mixp<kPrecFp16, R, true>), dim3(n_wg), dim3(64), 0, s, a);
+  else if (prec == kPrecFp16) hipLaunchKernelGGL((k_mixp<kPrecFp16, R, false>), dim3(n_wg), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_mixp<kPrecFp8, R, false>), dim3(n_wg), dim3(64), 0, s, a);
 }
 
 hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t n_wg_blocks, hipStream_t s) {
@@ -412,6 +713,12 @@ hipError_t launch_mix(const MixArgs& a, int n_ns, int prec, int64_t n_wg_blocks,
   const int64_t n_wg = n_run * a.n_chan * a.n_pg;
   if (n_wg == 0) return hipSuccess;
   if (n_wg > 0x7FFFFFFF) return hipErrorInvalidConfiguration;
+  switch (n_ns) {
+    case 32: launch_mixp<2>(a, prec, (unsigned)n_wg, s); return hipGetLastError();
+    case 64: launch_mixp<4>(a, prec, (unsigned)n_wg, s); return hipGetLastError();
+    case 128: launch_mixp<8>(a, prec, (unsigned)n_wg, s); return hipGetLastError();
+    default: break;
+  }
   if (prec == kPrecFp16 && a.taper) hipLaunchKernelGGL((k_mix16<kPrecFp16, true>), dim3((unsigned)n_wg), dim3(64), 0, s, a);
   else if (prec == kPrecFp16) hipLaunchKernelGGL(k_mix16<kPrecFp16>, dim3((unsigned)n_wg), dim3(64), 0, s, a);
   else hipLaunchKernelGGL(k_mix16<kPrecFp8>, dim3((unsigned)n_wg), dim3(64), 0, s, a);

@@ -88,7 +88,10 @@ def test_mixed_repeatable_and_unsupported():
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
     plan.close()
     with pytest.raises(bf.BFError) as e:
-        bf.Plan(n_ns=32, precision=1)
+        bf.Plan(n_ns=32, m_ew=8, precision=1)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    with pytest.raises(bf.BFError) as e:
+        bf.Plan(n_ns=64, m_ns=32, precision=2)
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
 
 
@@ -268,3 +271,83 @@ def test_mix16_window_parity(scale):
         ref = orc.beamform_fft(v2, 4, 32, 16, taper=h2.astype(np.float64), ns_select=w2.ns_select(),
                                pol_sum=pol_sum)
         assert rel_err(got, ref) < 1e-5
+
+
+# ---- 4 x 32, 4 x 64, 4 x 128: polyphase split onto the 16 -> 32 products ----
+
+@pytest.mark.parametrize("n_ns", [32, 64, 128])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixp_lattice_parity(n_ns, prec):
+    """n = 16 R positions (R = 2, 4, 8) on the matrix cores: R zero-padded
+    16 -> 32 products per E-W beam (FP16: exact E-W sums, two-term
+    coefficients; FP8: exact first-stage E-W sums, three stacked terms), the
+    twiddles W_M^{a0 m} and the R-point DFT in FP32 (eq. e:fftbeamform).
+    Several channels with their own clamp tables, both pols and summed pols,
+    6 blocks of 16 (a run of 4 and a ragged run of 2) and 3 blocks of 32."""
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=3, n_pol=2, n_time=96, seed=40 + n_ns, n_src=3, snr=8.0,
+                           n_ns_keep=n_ns + n_ns // 4, dl=(0.4, 0.8))
+    v = sg.volts(w)
+    m = 2 * n_ns
+    tol = 1e-5 if prec == 1 else TOL_MIXED
+    for pol_sum in (False, True):
+        ref = orc.beamform_fft(v, 4, m, 16, ns_select=w.ns_select(), pol_sum=pol_sum)
+        err = rel_err(_run(w, v, prec, pol_sum=pol_sum), ref)
+        print(f"4x{n_ns} precision {prec}, pol_sum={pol_sum}: max rel beam-power error {err:.3e}")
+        assert err < tol
+    ref32 = orc.beamform_fft(v, 4, m, 32, ns_select=w.ns_select())
+    assert rel_err(_run(w, v, prec, block=32), ref32) < tol
+    # no clamp: every one of the 2 n beams
+    w1 = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=2, n_pol=1, n_time=48, seed=7 + n_ns, n_src=2, snr=10.0)
+    v1 = sg.volts(w1)
+    assert rel_err(_run(w1, v1, prec, clamp=False), orc.beamform_fft(v1, 4, m, 16)) < tol
+
+
+@pytest.mark.parametrize("n_ns", [32, 64, 128])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixp_point_source_and_extremes(n_ns, prec):
+    """Lattice-aligned point sources and constant extreme bytes (-8 / +7
+    nibbles) through the polyphase matrix-core kernels."""
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_time=32, n_src=0)
+    tol = 1e-5 if prec == 1 else TOL_MIXED
+    for q in [(0, 0), (1, 2), (3, 3)]:
+        v = sg.point_source_volts(4, n_ns, q[0], q[1], 32, 7)
+        got = _run(w, v, prec, clamp=False)
+        ref = orc.beamform_fft(v, 4, 2 * n_ns, 16)
+        assert np.max(np.abs(got - ref)) / ref.max() < tol
+    for b in (0x88, 0x77, 0x8F):
+        v = np.full((16, 1, 1, n_ns, 4), b, dtype=np.uint8)
+        got = _run(w, v, prec, clamp=False)
+        ref = orc.beamform_fft(v, 4, 2 * n_ns, 16)
+        assert np.max(np.abs(got - ref)) / ref.max() < tol
+
+
+@pytest.mark.parametrize("n_ns", [32, 64, 128])
+@pytest.mark.parametrize("scale", [1.0, 1e-3])
+def test_mixp_window_parity(n_ns, scale):
+    """Per-antenna real weights on the FP16 polyphase path (Sec. "Controlling
+    beam shape with windowing"): windowed E-W sums split into FP16 hi + lo,
+    three products per tile, per-wavefront power-of-two scaling; held to the
+    FP32 bar.  An FP8 plan refuses a window."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=2, n_pol=2, n_time=64, seed=60 + n_ns, n_src=2, snr=10.0,
+                           n_ns_keep=n_ns, dl=(0.45, 0.9))
+    v = sg.volts(w)
+    vt = torch.from_numpy(v).cuda()
+    for h in (sg.gaussian_taper(4, n_ns) * scale, sg.half_sine_taper(4, n_ns, shifted=True) * scale):
+        h = h.astype(np.float32)
+        ht = torch.from_numpy(h).cuda()
+        for pol_sum in (False, True):
+            plan = plan_for(w, precision=1, pol_sum=pol_sum)
+            got = bf.beamform_fft(plan, vt, taper=ht).cpu().numpy()
+            plan.close()
+            ref = orc.beamform_fft(v, 4, 2 * n_ns, 16, taper=h.astype(np.float64), ns_select=w.ns_select(),
+                                   pol_sum=pol_sum)
+            err = rel_err(got, ref)
+            print(f"4x{n_ns} FP16 MFMA with window x{scale}, pol_sum={pol_sum}: {err:.3e}")
+            assert err < 1e-5
+    plan = plan_for(w, precision=2)
+    with pytest.raises(bf.BFError) as e:
+        bf.beamform_fft(plan, vt, taper=ht)
+    assert e.value.status == bf.BF_ERR_UNSUPPORTED
+    plan.close()
