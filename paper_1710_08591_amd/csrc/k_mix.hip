@@ -422,7 +422,7 @@ __device__ __forceinline__ void ew_half_weights(int col, int& wre, int& wim) {
 }
 
 template <int PREC, int R, bool WIN>
-__global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_mixp(MixArgs a) {
   static_assert(!WIN || PREC == kPrecFp16, "windows run on the FP16 path");
   constexpr int N = 16 * R, M = 2 * N;
   constexpr bool PAIR = PREC == kPrecFp8 && R <= 4;
@@ -444,7 +444,28 @@ __global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
   const int64_t blk0 = (int64_t)run * kMixBlocksPerWave;
   const int64_t blk1 = blk0 + kMixBlocksPerWave < n_blk ? blk0 + kMixBlocksPerWave : n_blk;
 
-  const float2* twt = reinterpret_cast<const float2*>(static_cast<const char*>(a.mat) + kMixTwOff);
+  // operand columns of both beam tiles (m = 16 kt + n) in registers, the
+  // twiddles W_M^{a0 m} in the LDS
+  __shared__ float2 lds_tw[32 * R];
+  op_t B[2][PREC == kPrecFp16 ? P : 1][2];
+  i32x8 B8[2][2];
+  {
+    const float2* twt = reinterpret_cast<const float2*>(static_cast<const char*>(a.mat) + kMixTwOff);
+    for (int i = lane; i < 32 * R; i += 64) lds_tw[i] = twt[i];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        if constexpr (PREC == kPrecFp16) {
+#pragma unroll
+          for (int p = 0; p < P; ++p) B[kt][p][part] = load_b<PREC>(a.mat, p, kt, part, lane);
+        } else {
+          B8[kt][part] = *reinterpret_cast<const i32x8*>(static_cast<const uint8_t*>(a.mat) +
+                                                          ((kt * 2 + part) * 64 + lane) * 32);
+        }
+      }
+    }
+  }
 
   const int comp = g >> 1;                 // FP16: the lane's component of the data operand
 
@@ -502,8 +523,8 @@ __global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
           int cwr[2], cwi[2];                                 // FP8: the pair's first-stage sums
           ew_half_weights(2 * (ps & 1), cwr[0], cwi[0]);
           ew_half_weights(2 * (ps & 1) + 1, cwr[1], cwi[1]);
-          // the beam tiles m < 16 and m >= 16 in turn (not unrolled either): their
-          // operand columns and twiddles come from the plan table (cached) per tile
+          // the beam tiles m < 16 and m >= 16 in turn (not unrolled either; the
+          // tile's operands are picked from the registers by a uniform select)
 #pragma unroll 1
           for (int kt = 0; kt < 2; ++kt) {
             if constexpr (WIN) {
@@ -512,23 +533,13 @@ __global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
 #pragma unroll
               for (int k = 0; k < NDW; ++k) asm volatile("" : "+v"(dw[k]));
             }
-            op_t B[PREC == kPrecFp16 ? P : 1][2];
-            i32x8 B8[2];
-#pragma unroll
-            for (int part = 0; part < 2; ++part) {
-              if constexpr (PREC == kPrecFp16) {
-#pragma unroll
-                for (int p = 0; p < P; ++p) B[p][part] = load_b<PREC>(a.mat, p, kt, part, lane);
-              } else {
-                B8[part] = *reinterpret_cast<const i32x8*>(static_cast<const uint8_t*>(a.mat) +
-                                                            ((kt * 2 + part) * 64 + lane) * 32);
-              }
-            }
-            cf tw[R];                          // W_M^{a0 m} of the lane's m = 16 kt + n
+            const auto& Bt = kt ? B[1] : B[0];
+            const auto& B8t = kt ? B8[1] : B8[0];
+            cf twk[R];
 #pragma unroll
             for (int a0 = 1; a0 < R; ++a0) {
-              const float2 v = twt[(16 * kt + n) * R + a0];
-              tw[a0] = cf{v.x, v.y};
+              const float2 v = lds_tw[(16 * kt + n) * R + a0];
+              twk[a0] = cf{v.x, v.y};
             }
             cf y[NE][R][4];
 #pragma unroll
@@ -544,7 +555,7 @@ __global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
                 for (int part = 0; part < 2; ++part) {
                   c[part] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                  for (int p = 0; p < P; ++p) c[part] = mfma<PREC>(A, B[p][part], c[part]);
+                  for (int p = 0; p < P; ++p) c[part] = mfma<PREC>(A, Bt[p][part], c[part]);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) y[0][a0][i] = cf{c[0][i], c[1][i]};
@@ -577,9 +588,9 @@ __global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
                 f32x4 c[2];
 #pragma unroll
                 for (int part = 0; part < 2; ++part) {
-                  c[part] = mfma<PREC>(Ah, B[0][part], f32x4{0.f, 0.f, 0.f, 0.f});
-                  c[part] = mfma<PREC>(Ah, B[1][part], c[part]);
-                  c[part] = mfma<PREC>(Al, B[0][part], c[part]);
+                  c[part] = mfma<PREC>(Ah, Bt[0][part], f32x4{0.f, 0.f, 0.f, 0.f});
+                  c[part] = mfma<PREC>(Ah, Bt[1][part], c[part]);
+                  c[part] = mfma<PREC>(Al, Bt[0][part], c[part]);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) y[0][a0][i] = cf{c[0][i], c[1][i]};
@@ -608,7 +619,7 @@ __global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
 #pragma unroll
                   for (int part = 0; part < 2; ++part)
                     c[cc][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                        A, B8[part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
+                        A, B8t[part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
                 }
                 // second E-W stage: pair 0 gives beams 0 (sum) and 2 (difference),
                 // pair 1 beams 1 (D02 - i D13) and 3 (D02 + i D13)
@@ -636,18 +647,19 @@ __global__ __launch_bounds__(64) void k_mixp(MixArgs a) {
                 cf z[R];
                 z[0] = y[w][0][i];
 #pragma unroll
-                for (int a0 = 1; a0 < R; ++a0) z[a0] = cmul(y[w][a0][i], tw[a0]);
+                for (int a0 = 1; a0 < R; ++a0) z[a0] = cmul(y[w][a0][i], twk[a0]);
                 dit<R>(z);
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[r] = cnorm_acc(z[r], v[r]);
               }
-              // sum the four sample groups; lane group g owns r = g, g + 4, ...
-              // (masked per r, so that no register array is indexed at run time)
+              // sum the four sample groups; lane group g adds r = g, g + 4, ... to
+              // the LDS (masked per r, so that no register array is indexed at
+              // run time; one lane per slot, so the adds need no ordering)
 #pragma unroll
               for (int r = 0; r < R; ++r) {
                 v[r] += __shfl_xor(v[r], 16);
                 v[r] += __shfl_xor(v[r], 32);
-                if ((r & 3) == g) lds_i[e * M + 16 * kt + n + 32 * r] += v[r];
+                if ((r & 3) == g) atomicAdd(&lds_i[e * M + 16 * kt + n + 32 * r], v[r]);   // no return value
               }
             }
           }
