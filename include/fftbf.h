@@ -126,7 +126,10 @@ bf_status bf_plan_get_desc(const bf_plan *plan, bf_plan_desc *desc);
  *            [n_time][n_chan][n_pol][m_ew][m_ns], every beam, unclamped.
  * The mixed-precision plans take the int4 samples exactly into FP16 / FP8
  * operands and round the DFT coefficients (split into a high and a low
- * part) to the working precision, accumulating in FP32.
+ * part) to the working precision, accumulating in FP32; they produce
+ * intensities only.  With a taper, FP16 plans split the windowed E-W sums
+ * into FP16 high and low parts (taper 16-byte aligned); FP8 plans return
+ * BF_ERR_UNSUPPORTED.  Mixed-precision plans need 16-byte aligned volts.
  */
 bf_status bf_beamform_fft(const bf_plan *plan, const uint8_t *volts, int64_t n_time,
                           const float *taper, int32_t kind, void *out, void *stream);
