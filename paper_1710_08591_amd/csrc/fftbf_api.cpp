@@ -355,8 +355,10 @@ bf_status bf_form_tied_beams(const bf_plan* plan, const void* fft_beams, int64_t
     return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: n_time not a multiple of block");
   if (kind == BF_OUT_COMPLEX && d.pol_sum)
     return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: complex output cannot sum polarisations");
-  if ((d.m_ns != 32 && d.m_ns != 64) || d.m_ew != 4 || d.m_ns < d.n_ns)
-    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams: m_ns must be 32 or 64 (and >= n_ns) and m_ew 4");
+  if (d.m_ns < 32 || d.m_ns > 512 || d.m_ew != 4 || d.m_ns < d.n_ns)
+    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams: m_ns must be in [32, 512] (and >= n_ns) and m_ew 4");
+  if (d.m_ns >= 128 && !aligned(fft_beams, 16))
+    return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams: fft_beams must be 16-byte aligned for m_ns >= 128");
   fftbf::TiedArgs a{};
   a.beams = static_cast<const float2*>(fft_beams);
   a.n_time = n_time;

@@ -659,7 +659,167 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
   }
 }
 
+// ---- larger lattices (m_ns = 128, 256, 512): FP32 matrix cores ----
+//
+// Per (16-pointing tile, channel, pol) the interpolation is a complex product
+//   Z[p][(t, e)] = sum_A c_A(y_ns,p) B[t][e][A],   B_p[t] = sum_e c_e(y_ew,p) Z[p][(t, e)]
+// run on v_mfma_f32_16x16x4_f32 (FP32 operands and accumulation, so the
+// result is FP32-grade without split terms): rows = the 16 pointings, columns
+// = 4 samples x 4 E-W beams, K = 4 beams A per instruction, the complex
+// product as four real products (Re c Re B, Im c Im B, Re c Im B, Im c Re B
+// into three accumulators).  Lane (g, n) takes A = g (M/4) + kb at step kb,
+// so its beam reads walk contiguous memory (16-byte loads, two steps each)
+// and its weights sit in one LDS row.  The N-S weights of the tile's
+// pointings are generated once per workgroup in FP64 (closed form below) and
+// held in LDS as FP32; the E-W weights of the lane's four pointings (rows
+// 4 g + i) and E-W beam (n mod 4) in registers.  The E-W sum is a sum over
+// the four lanes of a column quad; |B_p|^2 is summed over the quad's samples
+// by two more cross-lane adds.  Each wavefront owns whole output units
+// (blocks of the intensity, or quads of samples for complex output).
+constexpr int kTmfP = 16;                  // pointings per workgroup
+
+// c_A(y) = (1/M) sum_{a<n} e^{+i 2 pi a u}, u = A/M - y, in closed form:
+// e^{i pi (n-1) u} sin(n pi u) / (M sin(pi u)), with the limit n / M where
+// sin(pi u) = 0.  Numerator and denominator are taken from the same u, so
+// the ratio stays accurate as u approaches an integer.
+__device__ __forceinline__ void interp_weight_closed(int A, int m, int n, double y, double* wr, double* wi) {
+  const double u = (double)A / (double)m - y;
+  double s1, c1, sn, cn, sp, cp;
+  sincospi(u, &s1, &c1);
+  sincospi((double)n * u, &sn, &cn);
+  sincospi((double)(n - 1) * u, &sp, &cp);
+  const double amp = fabs(s1) > 1e-300 ? sn / (s1 * (double)m) : (double)n / (double)m * (c1 > 0.0 ? 1.0 : ((n - 1) & 1 ? -1.0 : 1.0));
+  *wr = amp * cp;
+  *wi = amp * sp;
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_tied_mf(TiedArgs a) {
+  constexpr int KS = M / 4;                  // MFMA steps; A = g KS + kb
+  constexpr int ROW = 2 * KS + 4;            // floats per (pointing, g) row; 16-byte pad against bank conflicts
+  __shared__ __attribute__((aligned(16))) float lds_w[kTmfP * 4 * ROW];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int e = n & 3, s = n >> 2;           // the lane's column: sample s of the quad, E-W beam e
+  const int n_ptile = (a.n_point + kTmfP - 1) / kTmfP;
+  const int ptile = blockIdx.x % n_ptile, run = blockIdx.x / n_ptile;
+  const int cs = blockIdx.y, pg = blockIdx.z;
+  const int chan = a.chan_lo + cs;
+  const double dl_ew = a.dl[2 * chan], dl_ns = a.dl[2 * chan + 1];
+
+  for (int i = tid; i < kTmfP * M; i += 256) {
+    const int pl = i / M, A = i - pl * M;
+    const int p = min(ptile * kTmfP + pl, a.n_point - 1);
+    double wr, wi;
+    interp_weight_closed(A, M, a.n_ns, dl_ns * a.dircos[2 * p + 1], &wr, &wi);
+    const int gg = A / KS, kb = A - gg * KS;
+    float* row = lds_w + (pl * 4 + gg) * ROW;
+    row[2 * kb] = (float)wr;
+    row[2 * kb + 1] = (float)wi;
+  }
+  cf cew[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int p = min(ptile * kTmfP + 4 * g + i, a.n_point - 1);
+    double wr, wi;
+    interp_weight_d(e, 4, a.n_ew, dl_ew * a.dircos[2 * p], &wr, &wi);
+    cew[i] = cf{(float)wr, (float)wi};
+  }
+  __syncthreads();
+
+  // output units: intensity blocks, or quads of samples for complex output
+  const int unit = a.complex_out ? 4 : a.block;
+  const int64_t n_unit = (a.n_time + unit - 1) / unit;
+  const int64_t u0 = (int64_t)run * a.run_units;
+  const int64_t u1 = u0 + a.run_units < n_unit ? u0 + a.run_units : n_unit;
+  const int n_pg = a.pol_sum ? 1 : a.n_pol;
+  const int pol_lo = a.pol_sum ? 0 : pg, pol_hi = a.pol_sum ? a.n_pol : pg + 1;
+  const float* wrow = lds_w + (n * 4 + g) * ROW;
+  const float* beams = reinterpret_cast<const float*>(a.beams);
+
+  for (int64_t u = u0 + wave; u < u1; u += 4) {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int pol = pol_lo; pol < pol_hi; ++pol) {
+      for (int q = 0; q < unit; q += 4) {
+        const int64_t t = u * unit + q + s;
+        const int64_t tc = t < a.n_time ? t : a.n_time - 1;
+        const float* bp = beams + ((((tc * a.n_chan + chan) * a.n_pol + pol) * 4 + e) * M + (int64_t)g * KS) * 2;
+        f32x4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, zi = p1;
+#pragma unroll 4
+        for (int kb = 0; kb < KS; kb += 2) {
+          const float4 b = *reinterpret_cast<const float4*>(bp + 2 * kb);
+          const float4 w = *reinterpret_cast<const float4*>(wrow + 2 * kb);
+          p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, b.x, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, b.y, p2, 0, 0, 0);
+          zi = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, b.y, zi, 0, 0, 0);
+          zi = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, b.x, zi, 0, 0, 0);
+          p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, b.z, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, b.w, p2, 0, 0, 0);
+          zi = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, b.w, zi, 0, 0, 0);
+          zi = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, b.z, zi, 0, 0, 0);
+        }
+        // E-W weights, then the sum over the column quad's four E-W beams
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          cf b = cmul(cf{p1[i] - p2[i], zi[i]}, cew[i]);
+          b.r += __shfl_xor(b.r, 1);
+          b.i += __shfl_xor(b.i, 1);
+          b.r += __shfl_xor(b.r, 2);
+          b.i += __shfl_xor(b.i, 2);
+          if (a.complex_out) {
+            const int p = ptile * kTmfP + 4 * g + i;
+            if (e == 0 && t < a.n_time && p < a.n_point)
+              static_cast<float2*>(a.out)[((t * a.n_chan_sub + cs) * a.n_pol + pol) * (int64_t)a.n_point + p] =
+                  make_float2(b.r, b.i);
+          } else {
+            float v = cnorm(b);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            acc[i] += v;
+          }
+        }
+      }
+    }
+    if (!a.complex_out && n == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int p = ptile * kTmfP + 4 * g + i;
+        if (p < a.n_point) static_cast<float*>(a.out)[((u * a.n_chan_sub + cs) * n_pg + pg) * (int64_t)a.n_point + p] = acc[i];
+      }
+    }
+  }
+}
+
 }  // namespace
+
+// m_ns = 128, 256, 512 (16-byte aligned beams): enough runs of output units
+// per (pointing tile, channel, pol group) that the grid holds about 8192
+// workgroups, each run a multiple of the four wavefronts' units
+static hipError_t launch_tied_mf(TiedArgs a, hipStream_t s) {
+  if ((a.m_ns != 128 && a.m_ns != 256 && a.m_ns != 512) || a.m_ew != 4 ||
+      (reinterpret_cast<uintptr_t>(a.beams) & 15) != 0)
+    return hipErrorNotSupported;
+  const int n_ptile = (a.n_point + kTmfP - 1) / kTmfP;
+  const int n_pg = (a.pol_sum && !a.complex_out) ? 1 : a.n_pol;
+  const int unit = a.complex_out ? 4 : a.block;
+  const int64_t n_unit = (a.n_time + unit - 1) / unit;
+  const int64_t base = (int64_t)n_ptile * a.n_chan_sub * n_pg;
+  int64_t runs = (8192 + base - 1) / base;
+  const int64_t max_runs = (n_unit + 3) / 4;
+  if (runs > max_runs) runs = max_runs;
+  if (runs < 1) runs = 1;
+  int64_t per = (n_unit + runs - 1) / runs;
+  per = (per + 3) / 4 * 4;
+  runs = (n_unit + per - 1) / per;
+  if (per > 0x7FFFFFFF || (int64_t)n_ptile * runs > 0x7FFFFFFF || a.n_chan_sub > 65535)
+    return hipErrorInvalidConfiguration;
+  a.run_units = (int)per;
+  dim3 grid((unsigned)(n_ptile * runs), (unsigned)a.n_chan_sub, (unsigned)n_pg);
+  if (a.m_ns == 128) hipLaunchKernelGGL(k_tied_mf<128>, grid, dim3(256), 0, s, a);
+  else if (a.m_ns == 256) hipLaunchKernelGGL(k_tied_mf<256>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_tied_mf<512>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_tied(const TiedArgs& a, hipStream_t s) {
   const int n_ptile = (a.n_point + 63) / 64;
@@ -681,7 +841,7 @@ hipError_t launch_tied(const TiedArgs& a, hipStream_t s) {
   dim3 grid((unsigned)(n_ptile * n_run), (unsigned)a.n_chan_sub, (unsigned)n_pg);
   if (a.m_ns == 32) hipLaunchKernelGGL(k_tied<32>, grid, dim3(64), 0, s, a);
   else if (a.m_ns == 64) hipLaunchKernelGGL(k_tied<64>, grid, dim3(64), 0, s, a);
-  else return hipErrorNotSupported;
+  else return launch_tied_mf(a, s);
   return hipGetLastError();
 }
 

@@ -68,6 +68,7 @@ struct TiedArgs {
   int pol_sum;
   int complex_out;
   void* out;
+  int run_units;           // output units per workgroup run (set by the launcher)
 };
 hipError_t launch_tied(const TiedArgs& a, hipStream_t s);
 

@@ -203,3 +203,57 @@ def test_tied_beams_benchmark_configuration_sampled():
     plan.close()
     del vt, beams, got_v, got_b
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n_ns", [64, 128, 256])
+def test_tied_from_fft_beams_large_lattices(n_ns):
+    """Tied beams from stored complex FFT beams of the 4 x 64, 4 x 128 and
+    4 x 256 lattices (m_ns = 128, 256, 512) on the FP32 matrix cores, against
+    the oracle's direct phased sums (eq. e:c_pointed; exact for M >= n):
+    ragged pointing tiles, on-grid pointings that must reproduce FFT beams,
+    a channel subset, per-pol and summed intensities, blocks of 16 and 32,
+    complex output with a sample count that is not a multiple of 4."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    m = 2 * n_ns
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=4, n_pol=2, n_time=96, seed=80 + n_ns, n_src=3, snr=15.0,
+                           dl=(0.4, 0.8))
+    v = sg.volts(w)
+    dl = w.d_over_lambda()
+    c = 2
+    grid = [(1, 3), (0, 0), (3, m - 1), (2, m // 2)]
+    dirs = np.array([[a / 4 / dl[c, 0], b / m / dl[c, 1]] for a, b in grid])
+    dirs = np.concatenate([dirs, sg.pointings(29, 81)], axis=0)           # 33 pointings: 3 tiles of 16
+    d = torch.from_numpy(dirs).cuda()
+    vt = torch.from_numpy(v).cuda()
+    plan = plan_for(w, clamp=False)
+    beams = bf.beamform_fft(plan, vt, kind=bf.BF_OUT_COMPLEX)
+    assert beams.data_ptr() % 16 == 0
+    got = bf.form_tied_beams(plan, beams, 1, 3, d).cpu().numpy()         # channels 1..3
+    ref = orc.tied_intensity(v[:, 1:4], dirs, dl, 16, chans=[1, 2, 3])
+    err = rel_err(got, ref)
+    print(f"4x{n_ns} tied from stored beams: {err:.3e}")
+    assert got.shape == ref.shape
+    assert err < TOL_FP32
+    fb = orc.beamform_fft(v, 4, m, 16)
+    for i, (a, b) in enumerate(grid):
+        assert rel_err(got[:, c - 1, :, i], fb[:, c, :, a, b]) < TOL_FP32
+    gotc = bf.form_tied_beams(plan, beams[:93], 0, 4, d, kind=bf.BF_OUT_COMPLEX).cpu().numpy()
+    refc = orc.tied_beams(v[:93], dirs, dl)
+    assert np.max(np.abs(gotc - refc)) / np.max(np.abs(refc)) < 1e-5
+    plan.close()
+    for block in (16, 32):
+        plan = plan_for(w, clamp=False, pol_sum=True, block=block)
+        got = bf.form_tied_beams(plan, beams, 0, 4, d).cpu().numpy()
+        ref = orc.tied_intensity(v, dirs, dl, block).sum(axis=2)
+        assert got.shape == ref.shape
+        assert rel_err(got, ref) < TOL_FP32
+        plan.close()
+    # the 16-byte alignment these lattices need
+    buf = torch.empty(beams.numel() + 1, dtype=torch.complex64, device="cuda")
+    shifted = buf[1:].view(beams.shape)
+    plan = plan_for(w, clamp=False)
+    with pytest.raises(bf.BFError) as e:
+        bf.form_tied_beams(plan, shifted, 0, 1, d)
+    assert e.value.status == bf.BF_ERR_INVALID_ARGUMENT
+    plan.close()
