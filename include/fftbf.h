@@ -163,7 +163,10 @@ bf_status bf_beamform_fft_gains(const bf_plan *plan, const uint8_t *volts, int64
  *   kind       BF_OUT_INTENSITY: out float [n_time/block][n_chan_sub][n_pol][n_point]
  *              (pol_sum: [n_time/block][n_chan_sub][n_point]);
  *              BF_OUT_COMPLEX: out float2 [n_time][n_chan_sub][n_pol][n_point]
- * Per-channel d/lambda comes from the plan.
+ * Per-channel d/lambda comes from the plan.  Plans with m_ew = 4 and
+ * 32 <= m_ns <= 512, m_ns >= n_ns (BF_ERR_UNSUPPORTED otherwise); for
+ * m_ns >= 128 fft_beams must be 16-byte aligned (BF_ERR_INVALID_ARGUMENT).
+ * At most 4096 pointings per call.
  */
 bf_status bf_form_tied_beams(const bf_plan *plan, const void *fft_beams, int64_t n_time,
                              int32_t chan_lo, int32_t n_chan_sub, const double *dircos,
@@ -177,10 +180,41 @@ bf_status bf_form_tied_beams(const bf_plan *plan, const void *fft_beams, int64_t
  *   volts     device uint8 [n_time][n_chan][n_pol][n_ns][n_ew] (full channel set)
  *   taper     device float [n_ns][n_ew] or NULL
  *   other arguments as bf_form_tied_beams (intensity output only).
+ * The 4 x 16 lattice with block a multiple of 16 (BF_ERR_UNSUPPORTED
+ * otherwise: other lattices take bf_form_tied_beams_v_ws).
  */
 bf_status bf_form_tied_beams_v(const bf_plan *plan, const uint8_t *volts, int64_t n_time,
                                const float *taper, int32_t chan_lo, int32_t n_chan_sub,
                                const double *dircos, int32_t n_point, void *out, void *stream);
+
+/*
+ * Bytes of caller workspace that bf_form_tied_beams_v_ws uses to take
+ * chunk_samples samples of n_chan_sub channels at a time: their complex FFT
+ * beams, chunk_samples * n_chan_sub * n_pol * m_ew * m_ns * 8.  0 for a
+ * NULL plan or negative sizes.
+ */
+size_t bf_tied_workspace_size(const bf_plan *plan, int32_t n_chan_sub, int64_t chunk_samples);
+
+/*
+ * bf_form_tied_beams_v for every lattice a tied-beam plan takes (m_ew = 4,
+ * 32 <= m_ns <= 512, m_ns >= n_ns): the samples go in chunks of whole
+ * blocks; per chunk the complex FFT beams of the channel range are written to
+ * the caller's workspace by the FFT beamformer (FP32, with the taper) and
+ * interpolated from there by the bf_form_tied_beams kernels, both on
+ * `stream`, so the method is the same as on the 4 x 16 lattice (interpolated
+ * FFT beams) with the beams passing through HBM.  The chunk is the largest
+ * whole number of blocks whose beams fit in workspace_bytes (at most n_time).
+ * On the 4 x 16 lattice with block a multiple of 16 this is
+ * bf_form_tied_beams_v and the workspace is not used (it may be NULL).
+ *   workspace  device memory, 16-byte aligned, owned by the caller; the call
+ *              overwrites it, so calls that share one must not overlap.
+ * Errors: as bf_form_tied_beams_v; BF_ERR_INVALID_ARGUMENT when the
+ * workspace is NULL, misaligned or smaller than one block's beams.
+ */
+bf_status bf_form_tied_beams_v_ws(const bf_plan *plan, const uint8_t *volts, int64_t n_time,
+                                  const float *taper, int32_t chan_lo, int32_t n_chan_sub,
+                                  const double *dircos, int32_t n_point, void *workspace,
+                                  size_t workspace_bytes, void *out, void *stream);
 
 /*
  * Standalone intensity accumulation (the |B|^2 time sum of eq. e:bf):

@@ -201,9 +201,19 @@ def form_tied_beams(plan: Plan, fft_beams, chan_lo: int, n_chan_sub: int, dircos
     return out
 
 
+def tied_workspace_size(plan: Plan, n_chan_sub: int, chunk_samples: int) -> int:
+    """Bytes of workspace form_tied_beams_v needs per chunk of samples (other lattices than 4 x 16)."""
+    return int(lib().bf_tied_workspace_size(plan.handle, n_chan_sub, chunk_samples))
+
+
 def form_tied_beams_v(plan: Plan, volts, chan_lo: int, n_chan_sub: int, dircos, taper=None, out=None,
-                      stream=None):
-    """Tied-array beam intensities straight from voltages (FFT beams formed on chip)."""
+                      stream=None, workspace=None):
+    """Tied-array beam intensities straight from voltages (FFT beams formed on chip).
+
+    The 4 x 16 lattice (block a multiple of 16) runs one fused kernel.  Other
+    lattices pass each chunk's complex FFT beams through ``workspace`` (a
+    device tensor; by default one of up to 256 MiB, at least one block, is
+    allocated here)."""
     torch = _torch()
     _need(volts, torch.uint8, "volts")
     n_time = volts.shape[0]
@@ -220,9 +230,21 @@ def form_tied_beams_v(plan: Plan, volts, chan_lo: int, n_chan_sub: int, dircos, 
         out = torch.empty(shape, dtype=torch.float32, device=volts.device)
     else:
         _need(out, torch.float32, "out")
-    check(lib().bf_form_tied_beams_v(plan.handle, _ptr(volts), n_time, _ptr(taper), chan_lo, n_chan_sub,
-                                     _ptr(dircos), n_point, _ptr(out), _stream_handle(stream)),
-          "bf_form_tied_beams_v")
+    if plan.n_ns == 16 and plan.m_ew == 4 and plan.block % 16 == 0:
+        check(lib().bf_form_tied_beams_v(plan.handle, _ptr(volts), n_time, _ptr(taper), chan_lo, n_chan_sub,
+                                         _ptr(dircos), n_point, _ptr(out), _stream_handle(stream)),
+              "bf_form_tied_beams_v")
+        return out
+    if workspace is None:
+        per_block = tied_workspace_size(plan, n_chan_sub, plan.block)
+        n_blk = max(1, n_time // plan.block)
+        nbytes = per_block * max(1, min(n_blk, (256 << 20) // max(per_block, 1)))
+        workspace = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=volts.device)
+    check(lib().bf_form_tied_beams_v_ws(plan.handle, _ptr(volts), n_time, _ptr(taper), chan_lo, n_chan_sub,
+                                        _ptr(dircos), n_point, _ptr(workspace),
+                                        workspace.numel() * workspace.element_size(), _ptr(out),
+                                        _stream_handle(stream)),
+          "bf_form_tied_beams_v_ws")
     return out
 
 

@@ -419,6 +419,88 @@ bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_
   return BF_OK;
 }
 
+size_t bf_tied_workspace_size(const bf_plan* plan, int32_t n_chan_sub, int64_t chunk_samples) {
+  if (!plan || n_chan_sub < 0 || chunk_samples < 0) return 0;
+  const bf_plan_desc& d = plan->d;
+  return (size_t)chunk_samples * (size_t)n_chan_sub * (size_t)d.n_pol * (size_t)d.m_ew * (size_t)d.m_ns * 8u;
+}
+
+bf_status bf_form_tied_beams_v_ws(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
+                                  int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
+                                  void* workspace, size_t workspace_bytes, void* out, void* stream) {
+  FFTBF_TRACE("bf_form_tied_beams_v_ws");
+  bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams_v_ws");
+  if (st != BF_OK) return st;
+  const bf_plan_desc& d = plan->d;
+  if (d.n_ns == 16 && d.m_ew == 4 && d.block % 16 == 0)
+    return bf_form_tied_beams_v(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, out, stream);
+  if (n_time == 0 || n_point == 0 || n_chan_sub == 0) return BF_OK;
+  if (!volts || !aligned(volts, 4)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v_ws: NULL or misaligned volts");
+  if (taper && !aligned(taper, 16)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v_ws: taper misaligned");
+  if (n_time % d.block) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v_ws: n_time not a multiple of block");
+  if (d.precision != BF_PREC_FP32 || d.m_ew != 4 || d.m_ns < 32 || d.m_ns > 512 || d.m_ns < d.n_ns)
+    return fail(BF_ERR_UNSUPPORTED, "form_tied_beams_v_ws: needs an FP32 plan with m_ew 4 and m_ns in [32, 512], >= n_ns");
+  const size_t per_block = bf_tied_workspace_size(plan, n_chan_sub, d.block);
+  if (!workspace || !aligned(workspace, 16) || workspace_bytes < per_block)
+    return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v_ws: workspace NULL, misaligned or below %zu bytes (one block)",
+                per_block);
+  int64_t chunk = (int64_t)(workspace_bytes / per_block) * d.block;
+  if (chunk > n_time) chunk = n_time;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n_pg = d.pol_sum ? 1 : d.n_pol;
+  for (int64_t t0 = 0; t0 < n_time; t0 += chunk) {
+    const int64_t len = n_time - t0 < chunk ? n_time - t0 : chunk;
+    // complex FFT beams of samples [t0, t0 + len), channels [chan_lo, chan_lo + n_chan_sub)
+    fftbf::Fft32Args f{};
+    f.volts = reinterpret_cast<const uint32_t*>(volts) + (t0 * d.n_chan + chan_lo) * (int64_t)d.n_pol * d.n_ns;
+    f.n_time = len;
+    f.n_chan = n_chan_sub;
+    f.chan_stride = d.n_chan;
+    f.n_pol = d.n_pol;
+    f.n_pg = d.n_pol;
+    f.pol_iter = 1;
+    f.block = d.block;
+    f.tw = plan->tw;
+    f.mult = plan->mult;
+    f.taper = taper;
+    f.sel = nullptr;
+    f.n_keep = d.m_ns;
+    f.fold = 1;
+    f.out = workspace;
+    f.norm = 1.0f / std::sqrt(float(d.n_ew * d.n_ns));
+    f.ew_rows = 4;
+    f.ew_mul = 1;
+    f.ew_off = 0;
+    f.gain_src = taper ? 1 : 0;
+    f.twist = 0;
+    const int64_t n_wg = (len + d.block - 1) / d.block * n_chan_sub * d.n_pol;
+    hipError_t e = fftbf::launch_fft32(f, d.n_ns, taper ? 1 : 0, true, n_wg, s);
+    if (e != hipSuccess) return dev_fail(e, "form_tied_beams_v_ws: FFT launch");
+    // tied beams of the chunk from those beams
+    fftbf::TiedArgs a{};
+    a.beams = static_cast<const float2*>(workspace);
+    a.n_time = len;
+    a.n_chan = n_chan_sub;
+    a.n_pol = d.n_pol;
+    a.chan_lo = 0;
+    a.n_chan_sub = n_chan_sub;
+    a.n_ew = d.n_ew;
+    a.n_ns = d.n_ns;
+    a.m_ew = d.m_ew;
+    a.m_ns = d.m_ns;
+    a.dircos = dircos;
+    a.dl = plan->dl + 2 * (int64_t)chan_lo;
+    a.n_point = n_point;
+    a.block = d.block;
+    a.pol_sum = d.pol_sum;
+    a.complex_out = 0;
+    a.out = static_cast<float*>(out) + (t0 / d.block) * (int64_t)n_chan_sub * n_pg * n_point;
+    e = fftbf::launch_tied(a, s);
+    if (e != hipSuccess) return dev_fail(e, "form_tied_beams_v_ws: interpolation launch");
+  }
+  return BF_OK;
+}
+
 }  // extern "C"
 
 struct bf_regrid {

@@ -281,7 +281,7 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
 
   const int64_t t_base = (int64_t)blk * p.block;
   const int n_it = p.block / F;
-  const int64_t frame_stride = (int64_t)p.n_chan * p.n_pol * NA;  // dwords per sample
+  const int64_t frame_stride = (int64_t)(p.chan_stride ? p.chan_stride : p.n_chan) * p.n_pol * NA;  // dwords per sample
 
   // Frames of this block that hold data: all of them, except in a short
   // final block (complex output with n_time not a multiple of the block).

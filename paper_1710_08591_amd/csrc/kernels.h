@@ -34,6 +34,9 @@ struct Fft32Args {
   int fold;
   // (block, channel, polarisation group) tasks, one per wave; set by the launch
   int64_t n_wg;
+  // channels per sample in the voltage buffer, when the call covers a subset of
+  // them (volts then points at the first channel of the subset); 0: n_chan
+  int chan_stride;
 };
 
 // group size G of the transform of length n_ns (fold: n_ns / m_ns of a

@@ -257,3 +257,49 @@ def test_tied_from_fft_beams_large_lattices(n_ns):
         bf.form_tied_beams(plan, shifted, 0, 1, d)
     assert e.value.status == bf.BF_ERR_INVALID_ARGUMENT
     plan.close()
+
+
+@pytest.mark.parametrize("n_ns", [32, 64, 256])
+def test_tied_from_voltages_other_lattices(n_ns):
+    """Tied beams from voltages on the 4 x 32, 4 x 64 and 4 x 256 lattices:
+    each chunk of whole blocks is beamformed (FP32, complex, with the window)
+    into the caller's workspace and interpolated from there.  A workspace of
+    one or two blocks forces several chunks; a channel subset, summed pols,
+    blocks of 32 and the too-small-workspace error."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=4, n_pol=2, n_time=96, seed=90 + n_ns, n_src=3, snr=15.0,
+                           dl=(0.4, 0.8))
+    v = sg.volts(w)
+    dl = w.d_over_lambda()
+    vt = torch.from_numpy(v).cuda()
+    dirs = np.concatenate([sg.pointings(20, 91), [[0.0, 0.0]]], axis=0)
+    d = torch.from_numpy(dirs).cuda()
+    h = sg.gaussian_taper(4, n_ns)
+    ht = torch.from_numpy(h).cuda()
+    plan = plan_for(w, clamp=False)
+    ref = orc.tied_intensity(v[:, 1:4], dirs, dl, 16, chans=[1, 2, 3])
+    got = bf.form_tied_beams_v(plan, vt, 1, 3, d).cpu().numpy()                 # one chunk
+    assert got.shape == ref.shape
+    err = rel_err(got, ref)
+    print(f"4x{n_ns} tied from voltages: {err:.3e}")
+    assert err < TOL_FP32
+    one = bf.tied_workspace_size(plan, 3, 16)
+    for blocks in (1, 2):
+        ws = torch.empty(blocks * one + 8, dtype=torch.uint8, device="cuda")     # 6 or 3 chunks
+        got = bf.form_tied_beams_v(plan, vt, 1, 3, d, workspace=ws).cpu().numpy()
+        assert rel_err(got, ref) < TOL_FP32
+    refh = orc.tied_intensity(v, dirs, dl, 16, taper=h)
+    goth = bf.form_tied_beams_v(plan, vt, 0, 4, d, taper=ht).cpu().numpy()
+    assert rel_err(goth, refh) < TOL_FP32
+    with pytest.raises(bf.BFError) as e:
+        bf.form_tied_beams_v(plan, vt, 1, 3, d, workspace=torch.empty(one - 16, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == bf.BF_ERR_INVALID_ARGUMENT
+    plan.close()
+    plan = plan_for(w, clamp=False, pol_sum=True, block=32)
+    ws = torch.empty(bf.tied_workspace_size(plan, 4, 32), dtype=torch.uint8, device="cuda")
+    got = bf.form_tied_beams_v(plan, vt, 0, 4, d, workspace=ws).cpu().numpy()
+    ref = orc.tied_intensity(v, dirs, dl, 32).sum(axis=2)
+    assert got.shape == ref.shape
+    assert rel_err(got, ref) < TOL_FP32
+    plan.close()
