@@ -621,8 +621,78 @@ def run_extras(dev, checks: OracleChecks) -> dict:
     plan.close()
     del vt
     torch.cuda.empty_cache()
+    ex["larger_lattices"] = _leg(run_larger_lattices, dev, checks)
     ex["serving"] = _leg(run_serving, dev)
     return ex
+
+
+def run_larger_lattices(dev, checks: OracleChecks) -> dict:
+    """FP32 vs FP16 / FP8 matrix cores (polyphase split) on the 4 x 64 and
+    4 x 128 lattices at the CHIME channel count and duration, and tied beams
+    on the 4 x 256 lattice from voltages (FFT beams through a workspace) and
+    from stored complex beams, each with sampled outputs for the oracle."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08591_amd as bf
+    import synthgen as sg
+    rec = {}
+    for n_ns in (64, 128):
+        w = sg.Workload(f"lattice4x{n_ns}_scaled", 4, n_ns, 256, 2, 16384, 4, 2 * n_ns, 16, 8 + n_ns,
+                        src_dircos=((0.3, -0.2), (-0.7, 0.5)), src_snr=(10.0, 30.0), dl_lo=0.4, dl_hi=0.8)
+        volts = sg.volts(w, backend="torch", device=dev)
+        rng = np.random.default_rng(n_ns)
+        picks = [(int(rng.integers(w.n_time // 16)), int(rng.integers(w.n_chan)), int(rng.integers(w.n_pol)))
+                 for _ in range(2)]
+        variants = {}
+        for prec, name in ((0, "fp32_fft"), (1, "fp16_mfma"), (2, "fp8_mfma")):
+            plan = bf.Plan(n_ew=4, n_ns=n_ns, n_pol=2, n_chan=256, block=16, precision=prec)
+            out = torch.empty(plan.out_shape(w.n_time), dtype=torch.float32, device=dev)
+            ms = _time_launches(lambda: bf.beamform_fft(plan, volts, out=out), 5)
+            variants[name] = {"antenna_samples_per_s": w.antenna_samples / (ms / 1e3), "kernel_ms": ms}
+            for b, c, p in picks:
+                checks.add(variants[name], "max_rel_power_err_sampled", "fft_rel", out[b, c, p].cpu().numpy(),
+                           v=sg.volts(w, b * 16, 16, chans=[c], pols=[p]), m_ew=4, m_ns=2 * n_ns, index=(0, 0, 0))
+            plan.close()
+            del out
+        rec[f"4x{n_ns}"] = {"workload": f"4x{n_ns} lattice, 2 pol, 256 chan, 16384 samples, M_ns = {2 * n_ns}, "
+                                        "|B|^2 over 16", "variants": variants}
+        del volts
+        torch.cuda.empty_cache()
+    # tied beams on the 4 x 256 lattice: 64 pointings, 16 channels, 2048 samples
+    wt = sg.Workload("tied4x256", 4, 256, 16, 1, 2048, 4, 512, 16, 21,
+                     src_dircos=((0.3, -0.2),), src_snr=(20.0,), dl_lo=0.4, dl_hi=0.8)
+    vt = sg.volts(wt, backend="torch", device=dev)
+    plan = bf.Plan(n_ew=4, n_ns=256, n_chan=16, block=16, d_over_lambda=wt.d_over_lambda())
+    dirs = sg.pointings(64, 23)
+    d = torch.from_numpy(dirs).to(dev)
+    ws = torch.empty(bf.tied_workspace_size(plan, 16, wt.n_time), dtype=torch.uint8, device=dev)
+    out = torch.empty((wt.n_time // 16, 16, 1, 64), dtype=torch.float32, device=dev)
+    ms_v = _time_launches(lambda: bf.form_tied_beams_v(plan, vt, 0, 16, d, out=out, workspace=ws), 5)
+    n_bs = 64 * 16 * wt.n_time
+    tv = {"workload": "4x256 lattice, 16 chan, 1 pol, 2048 samples, 64 pointings, |B|^2 over 16; FFT beams "
+                      f"({ws.numel() / 2**20:.0f} MiB) through a workspace", "kernel_ms": ms_v,
+          "beam_samples_per_s": n_bs / (ms_v / 1e3)}
+    dl = wt.d_over_lambda()
+    rng = np.random.default_rng(24)
+    for b, c in [(0, 0), (int(rng.integers(wt.n_time // 16)), int(rng.integers(16)))]:
+        checks.add(tv, "max_rel_power_err_sampled", "tied_rel", out[b, c].cpu().numpy(),
+                   v=sg.volts(wt, 16 * b, 16, chans=[c]), dircos=dirs, dl=dl, c=c)
+    beams = ws.view(torch.complex64)[: wt.n_time * 16 * 4 * 512].view(wt.n_time, 16, 1, 4, 512)
+    bf.beamform_fft(plan, vt, kind=bf.BF_OUT_COMPLEX, out=beams)
+    ms_b = _time_launches(lambda: bf.form_tied_beams(plan, beams, 0, 16, d, out=out), 5)
+    tb = {"workload": "the same, from the stored complex 4 x 512 FFT beams (FP32 matrix cores)",
+          "kernel_ms": ms_b, "beam_samples_per_s": n_bs / (ms_b / 1e3),
+          "mfma_fp32_tflops": n_bs * 8 * 4 * 512 / (ms_b / 1e3) / 1e12}
+    for b, c in [(wt.n_time // 16 - 1, 15)]:
+        checks.add(tb, "max_rel_power_err_sampled", "tied_rel", out[b, c].cpu().numpy(),
+                   v=sg.volts(wt, 16 * b, 16, chans=[c]), dircos=dirs, dl=dl, c=c)
+    rec["tied_4x256_from_voltages"] = tv
+    rec["tied_4x256_from_fft_beams"] = tb
+    plan.close()
+    del vt, ws, beams, out
+    torch.cuda.empty_cache()
+    return rec
 
 
 def _serve_saturated(srv, reqs) -> dict:
