@@ -910,7 +910,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "k_fft32<256,16>", "kernel_ms": ms_avg,
+                     "kernel": "k_fft32_h (4 x 256, half-size tiles)", "kernel_ms": ms_avg,
                      "kernel_ms_p10_p50_p90": [float(np.percentile(kern_ms, q)) for q in (10, 50, 90)],
                      "valu_insts_per_launch": valu,
                      "valu_insts_per_simd_cycle": valu_rate,

@@ -460,6 +460,182 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
   }
 }
 
+// ---- the 4 x 256 lattice: the pass-1 output in two halves ----
+// The zero-padded 32-point DFT over a2 splits into its even outputs (the
+// 16-point DFT of x) and its odd outputs (the 16-point DFT of x_j W_32^j,
+// pre-twiddles in tangent form with their factors carried through the DIT).
+// Each half is twiddled, transposed through an LDS tile of half the size and
+// transformed by pass 2 before the other half is formed: 8.7 KB of tile per
+// wavefront.  Lane (e, a1) of pass 1 is lane (e, m = a1) of pass 2, which
+// takes column k2 = 2 m + h of half h.  The pass-1 tangent values and the
+// pass-2 multipliers live in one LDS copy per workgroup (its four waves
+// share it), not in registers, and the next frame's voltages are loaded
+// during the second half only: 128 registers and about 10 KB of LDS per
+// wavefront, so four wavefronts fit per SIMD (two for the kernel above).
+// Unwindowed intensities; the window, gain and complex-output variants of
+// this lattice take the kernel above.
+constexpr int kHWpg = 4;                 // wavefronts per workgroup
+constexpr int kHRow = 44;                // LDS floats per (half, a1) row: 16 tangents, 25 multipliers, pad
+
+template <int L>
+__device__ __forceinline__ void padded_odd_t(const cf* x, cf* xo) {
+  PadPreT<L, 0>::run(x, xo);
+  cf z[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) z[i] = xo[bitrev(i, L)];
+  DitPad<L, 2, 0, 0>::run(z);
+#pragma unroll
+  for (int i = 0; i < L; ++i) xo[i] = z[i];
+}
+
+// half h of pass 1's output, twiddled, into the lane's LDS row: k2 = 2 m + h
+template <int H, int MI>
+struct HalfTw {
+  static __device__ __forceinline__ void run(const cf* y, const float* t1, cf c16, cf* row) {
+    constexpr int K = 2 * MI + H;
+    if constexpr (K == 0) row[MI] = y[MI];
+    else if constexpr (cmul_col(K, 16, 512)) row[MI] = cmul(y[MI], c16);
+    else row[MI] = cf{fmaf(-t1[MI], y[MI].i, y[MI].r), fmaf(t1[MI], y[MI].r, y[MI].i)};
+    if constexpr (MI + 1 < 16) HalfTw<H, MI + 1>::run(y, t1, c16, row);
+  }
+};
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_h(Fft32Args p) {
+  constexpr int N = 256, G = 16, L = 16, M = 512;
+  constexpr int NSL = dit_slots(G);
+  constexpr int YS = L + 1;
+  static_assert(L + NSL <= kHRow && kHRow % 4 == 0 && (kHRow / 4) % 2 == 1, "table rows");
+  static_assert((4 * M + 34) * 4 <= 64 * YS * 8, "block-end sums must fit the tile");
+  __shared__ cf lds_tiles[kHWpg * 64 * YS];
+  // [h][a1][44]: floats 0-15 the tangents of W_512^{a1 (2m + h)}, 16-40
+  // the pass-2 multipliers of column k2 = 2 a1 + h; rows of 11 float4 chunks
+  // put the 16 rows a lane group reads on different bank groups
+  __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
+  __shared__ cf lds_c16[G];                                           // whole twiddle of column k2 = 16
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  cf* const lds_y = lds_tiles + wave * 64 * YS;
+  const int e1 = lane >> 4, a1 = lane & 15;
+
+  for (int i = threadIdx.x; i < 2 * G * L; i += 64 * kHWpg) {
+    const int h = i / (G * L), r = i % (G * L), aa = r / L, m = r % L;
+    lds_tab[h][aa][m] = p.tw[aa * 32 + 2 * m + h].x;
+  }
+  for (int i = threadIdx.x; i < 32 * NSL; i += 64 * kHWpg) {
+    const int k2 = i / NSL;
+    lds_tab[k2 & 1][k2 >> 1][L + i % NSL] = p.mult[i];
+  }
+  if (threadIdx.x < G) {
+    const float2 w = p.tw[threadIdx.x * 32 + 16];
+    lds_c16[threadIdx.x] = cf{w.x, w.y};
+  }
+  __syncthreads();
+  const int64_t task = (int64_t)blockIdx.x * kHWpg + wave;
+  if (task >= p.n_wg) return;
+  int wg = (int)task;
+  const int pg = wg % p.n_pg;
+  wg /= p.n_pg;
+  const int chan = wg % p.n_chan;
+  const int blk = wg / p.n_chan;
+
+  int wre = 0, wim = 0;
+  ew_weights(e1, wre, wim);
+
+  float acc[2][G];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc[h][k] = 0.f;
+
+  const int64_t t_base = (int64_t)blk * p.block;
+  const int n_it = p.block;
+  const int64_t frame_stride = (int64_t)(p.chan_stride ? p.chan_stride : p.n_chan) * p.n_pol * N;
+  const int n_valid = (int)((p.n_time - t_base) < p.block ? (p.n_time - t_base) : p.block);
+  cf* const row = &lds_y[lane * YS];
+  const cf c16 = lds_c16[a1];
+
+  for (int pi = 0; pi < p.pol_iter; ++pi) {
+    const int pol = (p.pol_iter == 1) ? pg : pi;
+    const uint32_t* src = p.volts + ((int64_t)chan * p.n_pol + pol) * N + a1;
+    const uint32_t* q = src + t_base * frame_stride;
+    uint32_t b[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + G * j);
+    for (int it = 0; it < n_it; ++it) {
+      cf x[L];
+#pragma unroll
+      for (int j = 0; j < L; ++j) x[j] = cf{(float)sdot8((int)b[j], wre), (float)sdot8((int)b[j], wim)};
+      cf xo[L];
+      padded_odd_t<L>(x, xo);
+      dit<L>(x);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const cf* y = h ? xo : x;
+        if (h == 1) {
+          // the next frame's loads, in flight through this half (past the
+          // block: the buffer's first frame, cached)
+          q = (it + 1 >= n_it) ? p.volts + a1 : ((it + 1 < n_valid) ? q + frame_stride : q);
+#pragma unroll
+          for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + G * j);
+        }
+        {
+          float t1[L];
+          const float4* tp = reinterpret_cast<const float4*>(&lds_tab[h][a1][0]);
+#pragma unroll
+          for (int k = 0; k < L / 4; ++k) {
+            const float4 v = tp[k];
+            t1[4 * k] = v.x;
+            t1[4 * k + 1] = v.y;
+            t1[4 * k + 2] = v.z;
+            t1[4 * k + 3] = v.w;
+          }
+          if (h == 0) HalfTw<0, 0>::run(y, t1, c16, row);
+          else HalfTw<1, 0>::run(y, t1, c16, row);
+        }
+        wave_lds_sync();
+        cf z[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) z[j] = lds_y[(e1 * 16 + j) * YS + a1];
+        wave_lds_sync();
+        float mu[28];
+        const float4* mp = reinterpret_cast<const float4*>(&lds_tab[h][a1][L]);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          const float4 v = mp[k];
+          mu[4 * k] = v.x;
+          mu[4 * k + 1] = v.y;
+          mu[4 * k + 2] = v.z;
+          mu[4 * k + 3] = v.w;
+        }
+        dit_rs<G>(z, mu);
+#pragma unroll
+        for (int k1 = 0; k1 < G; ++k1) acc[h][k1] = cnorm_acc(z[k1], acc[h][k1]);
+      }
+    }
+  }
+
+  // ---- block end: the kept beams of the channel, coalesced stores ----
+  // E-W beam e's sums start at 512 e + (e & 1) + 32 (e >> 1): the four lane
+  // groups of one store then cover all 64 banks
+  float* lds_i = reinterpret_cast<float*>(lds_y);
+  auto ebase = [](int e) { return e * M + (e & 1) + 32 * (e >> 1); };
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int k1 = 0; k1 < G; ++k1) lds_i[ebase(e1) + 2 * a1 + h + 32 * k1] = acc[h][k1];
+  wave_lds_sync();
+  const int keep = p.n_keep;
+  const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
+  float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    for (int j = lane; j < keep; j += 64) {
+      const int A = sel ? sel[j] : j;
+      o[(e * p.ew_mul + p.ew_off) * keep + j] = lds_i[ebase(e) + A] * p.norm;
+    }
+}
+
 template <int N, int G, int T, int FOLD = 1>
 void launch_nt(const Fft32Args& a, bool cplx, hipStream_t s) {
   constexpr int W = fft32_wpg<N, G, T, FOLD>();
@@ -496,6 +672,13 @@ hipError_t launch_fold(const Fft32Args& a, int taper, bool cplx, hipStream_t s) 
 template <int N>
 hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
   constexpr int G = fft32_g(N, 1);
+  if constexpr (N == 256) {
+    if (taper == 0 && !cplx) {       // the 4 x 256 intensities: half-size tiles, four waves per SIMD
+      const dim3 grid((unsigned)((a.n_wg + kHWpg - 1) / kHWpg)), threads(64 * kHWpg);
+      hipLaunchKernelGGL(k_fft32_h, grid, threads, 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (taper == 3) launch_nt<N, G, 3>(a, cplx, s);
   else if (taper == 2) launch_nt<N, G, 2>(a, cplx, s);
   else if (taper == 1) launch_nt<N, G, 1>(a, cplx, s);
