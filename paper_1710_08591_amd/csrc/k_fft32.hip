@@ -553,7 +553,6 @@ __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4)))
   const int64_t frame_stride = (int64_t)(p.chan_stride ? p.chan_stride : p.n_chan) * p.n_pol * N;
   const int n_valid = (int)((p.n_time - t_base) < p.block ? (p.n_time - t_base) : p.block);
   cf* const row = &lds_y[lane * YS];
-  const cf c16 = lds_c16[a1];
 
   for (int pi = 0; pi < p.pol_iter; ++pi) {
     const int pol = (p.pol_iter == 1) ? pg : pi;
@@ -590,8 +589,10 @@ __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4)))
             t1[4 * k + 2] = v.z;
             t1[4 * k + 3] = v.w;
           }
-          if (h == 0) HalfTw<0, 0>::run(y, t1, c16, row);
-          else HalfTw<1, 0>::run(y, t1, c16, row);
+          // (the whole twiddle of column 16 is read per frame: held across
+          // the frame loop it would take the last free register)
+          if (h == 0) HalfTw<0, 0>::run(y, t1, lds_c16[a1], row);
+          else HalfTw<1, 0>::run(y, t1, cf{}, row);
         }
         wave_lds_sync();
         cf z[G];
