@@ -382,10 +382,9 @@ bf_status bf_form_tied_beams(const bf_plan* plan, const void* fft_beams, int64_t
   return BF_OK;
 }
 
-bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
-                               int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
-                               void* out, void* stream) {
-  FFTBF_TRACE("bf_form_tied_beams_v");
+static bf_status tied_v_impl(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
+                             int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point, void* out,
+                             void* stream) {
   bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams_v");
   if (st != BF_OK) return st;
   const bf_plan_desc& d = plan->d;
@@ -419,21 +418,27 @@ bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_
   return BF_OK;
 }
 
+bf_status bf_form_tied_beams_v(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
+                               int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
+                               void* out, void* stream) {
+  FFTBF_TRACE("bf_form_tied_beams_v");
+  return tied_v_impl(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, out, stream);
+}
+
 size_t bf_tied_workspace_size(const bf_plan* plan, int32_t n_chan_sub, int64_t chunk_samples) {
   if (!plan || n_chan_sub < 0 || chunk_samples < 0) return 0;
   const bf_plan_desc& d = plan->d;
   return (size_t)chunk_samples * (size_t)n_chan_sub * (size_t)d.n_pol * (size_t)d.m_ew * (size_t)d.m_ns * 8u;
 }
 
-bf_status bf_form_tied_beams_v_ws(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
-                                  int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
-                                  void* workspace, size_t workspace_bytes, void* out, void* stream) {
-  FFTBF_TRACE("bf_form_tied_beams_v_ws");
+static bf_status tied_v_ws_impl(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
+                                int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
+                                void* workspace, size_t workspace_bytes, void* out, void* stream) {
   bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams_v_ws");
   if (st != BF_OK) return st;
   const bf_plan_desc& d = plan->d;
   if (d.n_ns == 16 && d.m_ew == 4 && d.block % 16 == 0)
-    return bf_form_tied_beams_v(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, out, stream);
+    return tied_v_impl(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, out, stream);
   if (n_time == 0 || n_point == 0 || n_chan_sub == 0) return BF_OK;
   if (!volts || !aligned(volts, 4)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v_ws: NULL or misaligned volts");
   if (taper && !aligned(taper, 16)) return fail(BF_ERR_INVALID_ARGUMENT, "form_tied_beams_v_ws: taper misaligned");
@@ -474,6 +479,7 @@ bf_status bf_form_tied_beams_v_ws(const bf_plan* plan, const uint8_t* volts, int
     f.gain_src = taper ? 1 : 0;
     f.twist = 0;
     const int64_t n_wg = (len + d.block - 1) / d.block * n_chan_sub * d.n_pol;
+    if (n_wg > 0x7FFFFFFFLL) return fail(BF_ERR_UNSUPPORTED, "form_tied_beams_v_ws: chunk grid too large, split the call");
     hipError_t e = fftbf::launch_fft32(f, d.n_ns, taper ? 1 : 0, true, n_wg, s);
     if (e != hipSuccess) return dev_fail(e, "form_tied_beams_v_ws: FFT launch");
     // tied beams of the chunk from those beams
@@ -499,6 +505,14 @@ bf_status bf_form_tied_beams_v_ws(const bf_plan* plan, const uint8_t* volts, int
     if (e != hipSuccess) return dev_fail(e, "form_tied_beams_v_ws: interpolation launch");
   }
   return BF_OK;
+}
+
+bf_status bf_form_tied_beams_v_ws(const bf_plan* plan, const uint8_t* volts, int64_t n_time, const float* taper,
+                                  int32_t chan_lo, int32_t n_chan_sub, const double* dircos, int32_t n_point,
+                                  void* workspace, size_t workspace_bytes, void* out, void* stream) {
+  FFTBF_TRACE("bf_form_tied_beams_v_ws");
+  return tied_v_ws_impl(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, workspace,
+                        workspace_bytes, out, stream);
 }
 
 }  // extern "C"
