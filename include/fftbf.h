@@ -217,6 +217,23 @@ bf_status bf_form_tied_beams_v_ws(const bf_plan *plan, const uint8_t *volts, int
                                   size_t workspace_bytes, void *out, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * bf_form_tied_beams_v_ws with the workspace taken from a static device
+ * array of the library (64 MiB, one per GPU, held until the process ends)
+ * instead of an argument.  The call itself allocates nothing.  Every call on
+ * one GPU shares that array and leaves its last contents there; calls that
+ * overlap on one GPU (concurrent streams or threads) race on it.
+ * Errors: as bf_form_tied_beams_v_ws; BF_ERR_INVALID_ARGUMENT when one block
+ * of the channel range needs more than the 64 MiB (n_chan_sub * n_pol *
+ * block * m_ew * m_ns * 8 bytes).  On the 4 x 16 lattice with block a
+ * multiple of 16 it is bf_form_tied_beams_v (no workspace).
+ */
+bf_status bf_form_tied_beams_v_noalloc(const bf_plan *plan, const uint8_t *volts, int64_t n_time,
+                                       const float *taper, int32_t chan_lo, int32_t n_chan_sub,
+                                       const double *dircos, int32_t n_point, void *out, void *stream);
+
+/*
  * Standalone intensity accumulation (the |B|^2 time sum of eq. e:bf):
  *   out[b][s] (+)= sum_{t in block b} |z[t][s]|^2
  *   z    device float2 [n_time][n_series]

@@ -201,6 +201,30 @@ def form_tied_beams(plan: Plan, fft_beams, chan_lo: int, n_chan_sub: int, dircos
     return out
 
 
+def form_tied_beams_v_noalloc(plan: Plan, volts, chan_lo: int, n_chan_sub: int, dircos, out, taper=None,
+                              stream=None):
+    """form_tied_beams_v through bf_form_tied_beams_v_noalloc: the library's
+    static device scratch as the workspace, no allocation in the call
+    (``out`` must be given)."""
+    torch = _torch()
+    _need(volts, torch.uint8, "volts")
+    n_time = volts.shape[0]
+    if tuple(volts.shape) != plan.volts_shape(n_time):
+        raise ValueError("volts shape does not match the plan")
+    if taper is not None:
+        _need(taper, torch.float32, "taper")
+    n_point = _dircos(dircos)
+    shape = ((n_time // plan.block, n_chan_sub, n_point) if plan.pol_sum
+             else (n_time // plan.block, n_chan_sub, plan.n_pol, n_point))
+    _need(out, torch.float32, "out")
+    if tuple(out.shape) != shape:
+        raise ValueError(f"out shape {tuple(out.shape)} != {shape}")
+    check(lib().bf_form_tied_beams_v_noalloc(plan.handle, _ptr(volts), n_time, _ptr(taper), chan_lo, n_chan_sub,
+                                             _ptr(dircos), n_point, _ptr(out), _stream_handle(stream)),
+          "bf_form_tied_beams_v_noalloc")
+    return out
+
+
 def tied_workspace_size(plan: Plan, n_chan_sub: int, chunk_samples: int) -> int:
     """Bytes of workspace form_tied_beams_v needs per chunk of samples (other lattices than 4 x 16)."""
     return int(lib().bf_tied_workspace_size(plan.handle, n_chan_sub, chunk_samples))

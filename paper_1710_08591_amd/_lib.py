@@ -63,6 +63,8 @@ _SIGS = {
     "bf_tied_workspace_size": (C.c_size_t, [_P, C.c_int32, C.c_int64]),
     "bf_form_tied_beams_v_ws": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, C.c_int32, _P, C.c_int32,
                                             _P, C.c_size_t, _P, _P]),
+    "bf_form_tied_beams_v_noalloc": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int32, C.c_int32, _P, C.c_int32,
+                                                 _P, _P]),
     "bf_accumulate_intensity": (C.c_int32, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P, _P]),
     "bf_regrid_create": (C.c_int32, [_P, _P, C.c_int32, _P, C.c_int32, C.POINTER(_P)]),
     "bf_regrid_create_2d": (C.c_int32, [_P, _P, C.c_int32, C.POINTER(_P)]),

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -513,6 +514,58 @@ bf_status bf_form_tied_beams_v_ws(const bf_plan* plan, const uint8_t* volts, int
   FFTBF_TRACE("bf_form_tied_beams_v_ws");
   return tied_v_ws_impl(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, workspace,
                         workspace_bytes, out, stream);
+}
+
+}  // extern "C"
+
+// The workspace of bf_form_tied_beams_v_noalloc: a file-scope device array,
+// one copy per GPU the library runs on, held until the process ends.  In
+// host code `scratch` is a host-side stand-in, not a device address: its
+// address on the current device comes from hipGetSymbolAddress (taken once
+// per device) and only that address is handed to the kernels.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static bf_status static_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_fail(e, "form_tied_beams_v_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(BF_ERR_UNSUPPORTED, "form_tied_beams_v_noalloc: device %d", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return dev_fail(e, "form_tied_beams_v_noalloc: hipGetSymbolAddress");
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return BF_OK;
+}
+
+extern "C" {
+
+bf_status bf_form_tied_beams_v_noalloc(const bf_plan* plan, const uint8_t* volts, int64_t n_time,
+                                       const float* taper, int32_t chan_lo, int32_t n_chan_sub,
+                                       const double* dircos, int32_t n_point, void* out, void* stream) {
+  bf_status st = tied_common(plan, n_time, chan_lo, n_chan_sub, dircos, n_point, out, "form_tied_beams_v_noalloc");
+  if (st != BF_OK) return st;
+  const bf_plan_desc& d = plan->d;
+  if (d.n_ns == 16 && d.m_ew == 4 && d.block % 16 == 0)      // the fused kernel uses no workspace
+    return tied_v_impl(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, out, stream);
+  const size_t per_block = bf_tied_workspace_size(plan, n_chan_sub, d.block);
+  if (per_block > kStaticScratchBytes)
+    return fail(BF_ERR_INVALID_ARGUMENT,
+                "form_tied_beams_v_noalloc: one block of %d channels needs %zu bytes of workspace, above the "
+                "%zu-byte static scratch (fewer channels per call, or bf_form_tied_beams_v_ws)",
+                n_chan_sub, per_block, kStaticScratchBytes);
+  void* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != BF_OK) return st;
+  return tied_v_ws_impl(plan, volts, n_time, taper, chan_lo, n_chan_sub, dircos, n_point, ws, kStaticScratchBytes,
+                        out, stream);
 }
 
 }  // extern "C"
