@@ -6,6 +6,7 @@
 //   fftbf_bench --copy 1 [--steps S]
 //   fftbf_bench --issue 1
 //   fftbf_bench --mfma K      (K = 0, 1, 2: one MFMA form; 3: all three)
+//   fftbf_bench --n-ns 16 --n-pol 1 --tied P   (tied beams from voltages, P pointings)
 //
 // Voltages are device-resident, filled with a fixed byte pattern (0x5A) or,
 // with --random 1, with hashed bytes: the memory traffic and the instruction
@@ -251,9 +252,10 @@ int main(int argc, char** argv) {
   const int copy = arg_int(argc, argv, "--copy", 0);
   const int issue = arg_int(argc, argv, "--issue", 0);
   const int mfma = arg_int(argc, argv, "--mfma", -1);
+  const int tied = arg_int(argc, argv, "--tied", 0);
   if (n_ns <= 0 || n_chan <= 0 || n_pol <= 0 || n_time <= 0 || keep < 0 || keep > 2 * n_ns || steps <= 0 ||
       warmup < 0 || (random != 0 && random != 1) || (copy != 0 && copy != 1) ||
-      (issue != 0 && issue != 1)) {
+      (issue != 0 && issue != 1) || tied < 0 || tied > 4096) {
     std::fprintf(stderr, "invalid arguments\n");
     return 2;
   }
@@ -282,8 +284,14 @@ int main(int argc, char** argv) {
   const int kept = d.n_ns_keep ? d.n_ns_keep : d.m_ns;
 
   const size_t in_bytes = (size_t)n_time * n_chan * n_pol * n_ns * 4;
-  const size_t out_bytes = (size_t)(n_time / 16) * n_chan * n_pol * 4 * kept * sizeof(float);
-  void *volts = nullptr, *out = nullptr;
+  const size_t out_bytes = tied ? (size_t)(n_time / 16) * n_chan * n_pol * tied * sizeof(float)
+                                : (size_t)(n_time / 16) * n_chan * n_pol * 4 * kept * sizeof(float);
+  std::vector<double> dirs((size_t)2 * (tied ? tied : 1));
+  for (int p = 0; p < tied; ++p) {          // a spread of directions inside the field of view
+    dirs[2 * p] = -0.8 + 1.6 * ((p * 37) % 97) / 96.0;
+    dirs[2 * p + 1] = -0.8 + 1.6 * ((p * 61) % 89) / 88.0;
+  }
+  void *volts = nullptr, *out = nullptr, *dircos = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = 1;
@@ -298,6 +306,27 @@ int main(int argc, char** argv) {
   }
   if (!ok_hip(hipStreamCreate(&s), "hipStreamCreate")) goto done;
   if (!ok_hip(hipEventCreate(&e0), "hipEventCreate") || !ok_hip(hipEventCreate(&e1), "hipEventCreate")) goto done;
+  if (tied) {
+    if (!ok_hip(hipMalloc(&dircos, dirs.size() * sizeof(double)), "hipMalloc dircos") ||
+        !ok_hip(hipMemcpy(dircos, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy"))
+      goto done;
+    for (int i = 0; i < warmup + steps; ++i) {
+      if (i == warmup && !ok_hip(hipEventRecord(e0, s), "hipEventRecord")) goto done;
+      if (!ok_bf(bf_form_tied_beams_v(plan, static_cast<uint8_t*>(volts), n_time, nullptr, 0, n_chan,
+                                      static_cast<double*>(dircos), tied, out, s),
+                 "bf_form_tied_beams_v"))
+        goto done;
+    }
+    if (!ok_hip(hipEventRecord(e1, s), "hipEventRecord") || !ok_hip(hipEventSynchronize(e1), "hipEventSynchronize") ||
+        !ok_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime"))
+      goto done;
+    std::printf("fftbf_bench: tied beams from voltages, 4x%d lattice, %d chan, %d pol, %d samples, %d pointings: "
+                "%.4f ms per launch, %.4g beam-samples/s (%s voltages)\n",
+                n_ns, n_chan, n_pol, n_time, tied, ms / steps,
+                (double)n_time * n_chan * n_pol * tied / (ms / steps * 1e-3), random ? "hashed" : "constant");
+    rc = 0;
+    goto done;
+  }
   for (int i = 0; i < warmup; ++i)
     if (!ok_bf(bf_beamform_fft(plan, static_cast<uint8_t*>(volts), n_time, nullptr, BF_OUT_INTENSITY, out, s),
                "bf_beamform_fft"))
@@ -320,6 +349,7 @@ done:
   if (e1) (void)hipEventDestroy(e1);
   if (s) (void)hipStreamDestroy(s);
   if (out) (void)hipFree(out);
+  if (dircos) (void)hipFree(dircos);
   if (volts) (void)hipFree(volts);
   bf_plan_destroy(plan);
   return rc;

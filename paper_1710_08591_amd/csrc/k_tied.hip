@@ -187,6 +187,21 @@ __device__ __forceinline__ void v16_load(const uint32_t* __restrict__ src, uint3
 // FFT beams of the 16 samples whose frames the lanes hold (lane = sample
 // l.ts, E-W beam l.e), normalised by 1/sqrt(64), scaled by 2^ds and split
 // into the FP16 operand layout above.
+// LDS position (16-byte chunk) of the operand vector (term, kb, g, sample s)
+// of one group.  The sample index is XOR-swizzled so that the 16 lanes of
+// one LDS pass land on 16 different bank groups, for the readers (16
+// consecutive s, fixed (kb, g)) and for the writer of each layout:
+//   v16 (FFT beams formed on chip): the writers of a pass differ in E-W beam,
+//     kb = 2 e + c / 4, so s ^ 4 (kb >> 1) spreads them;
+//   b16 (stored beams): the writers of a pass differ in (kb, g), so
+//     s ^ ((4 kb + g) mod 16) spreads them.
+__device__ __forceinline__ int v16_chunk(int term, int kb, int g, int s) {
+  return ((term * 8 + kb) * 4 + g) * 16 + (s ^ ((kb >> 1) << 2));
+}
+__device__ __forceinline__ int b16_chunk(int term, int kb, int g, int s) {
+  return ((term * 8 + kb) * 4 + g) * 16 + (s ^ ((4 * kb + g) & 15));
+}
+
 template <bool TAPER>
 __device__ __forceinline__ void v16_fft_to_lds(const uint32_t (&dw)[kV16N], const V16Lane& l,
                                                const float* lds_h, _Float16* lds_g, int ds) {
@@ -223,8 +238,8 @@ __device__ __forceinline__ void v16_fft_to_lds(const uint32_t (&dw)[kV16N], cons
 #pragma unroll
     for (int q = 0; q < 4; ++q) split2(y[4 * c + q].r * nrm, y[4 * c + q].i * nrm, hw[q], lw[q]);
     const int kb = 2 * l.e + c / 4, g = c % 4;
-    *reinterpret_cast<half8*>(lds_g + (((0 * 8 + kb) * 4 + g) * 16 + l.ts) * 8) = __builtin_bit_cast(half8, hw);
-    *reinterpret_cast<half8*>(lds_g + (((1 * 8 + kb) * 4 + g) * 16 + l.ts) * 8) = __builtin_bit_cast(half8, lw);
+    *reinterpret_cast<half8*>(lds_g + v16_chunk(0, kb, g, l.ts) * 8) = __builtin_bit_cast(half8, hw);
+    *reinterpret_cast<half8*>(lds_g + v16_chunk(1, kb, g, l.ts) * 8) = __builtin_bit_cast(half8, lw);
   }
 }
 
@@ -288,8 +303,8 @@ __device__ __forceinline__ float tied_block_mfma(const _Float16* lds_g, const Ti
   f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int kb = 0; kb < 8; ++kb) {
-    const half8 ah = *reinterpret_cast<const half8*>(lds_g + (((0 * 8 + kb) * 4 + g) * 16 + s) * 8);
-    const half8 al = *reinterpret_cast<const half8*>(lds_g + (((1 * 8 + kb) * 4 + g) * 16 + s) * 8);
+    const half8 ah = *reinterpret_cast<const half8*>(lds_g + v16_chunk(0, kb, g, s) * 8);
+    const half8 al = *reinterpret_cast<const half8*>(lds_g + v16_chunk(1, kb, g, s) * 8);
     cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.rh[kb], cre, 0, 0, 0);
     cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.ih[kb], cim, 0, 0, 0);
     cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, w.rh[kb], cre, 0, 0, 0);
@@ -314,8 +329,8 @@ __device__ __forceinline__ float tied_block_mfma_rows(const _Float16* lds_g, con
   f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int kb = 0; kb < 8; ++kb) {
-    const half8 ah = *reinterpret_cast<const half8*>(lds_g + (((0 * 8 + kb) * 4 + g) * 16 + s) * 8);
-    const half8 al = *reinterpret_cast<const half8*>(lds_g + (((1 * 8 + kb) * 4 + g) * 16 + s) * 8);
+    const half8 ah = *reinterpret_cast<const half8*>(lds_g + b16_chunk(0, kb, g, s) * 8);
+    const half8 al = *reinterpret_cast<const half8*>(lds_g + b16_chunk(1, kb, g, s) * 8);
     cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.rh[kb], cre, 0, 0, 0);
     cim = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, w.ih[kb], cim, 0, 0, 0);
     cre = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, w.rh[kb], cre, 0, 0, 0);
@@ -422,8 +437,8 @@ __global__ __launch_bounds__(256) void k_tied_b16(TiedArgs a) {
           split2(v0[2] * sc, v0[3] * sc, hw[1], lw[1]);
           split2(v1[0] * sc, v1[1] * sc, hw[2], lw[2]);
           split2(v1[2] * sc, v1[3] * sc, hw[3], lw[3]);
-          *reinterpret_cast<half8*>(lds_g + (((0 * 8 + kb) * 4 + gq) * 16 + s) * 8) = __builtin_bit_cast(half8, hw);
-          *reinterpret_cast<half8*>(lds_g + (((1 * 8 + kb) * 4 + gq) * 16 + s) * 8) = __builtin_bit_cast(half8, lw);
+          *reinterpret_cast<half8*>(lds_g + b16_chunk(0, kb, gq, s) * 8) = __builtin_bit_cast(half8, hw);
+          *reinterpret_cast<half8*>(lds_g + b16_chunk(1, kb, gq, s) * 8) = __builtin_bit_cast(half8, lw);
         }
       }
       __syncthreads();
