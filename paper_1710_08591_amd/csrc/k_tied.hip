@@ -188,18 +188,18 @@ __device__ __forceinline__ void v16_load(const uint32_t* __restrict__ src, uint3
 // l.ts, E-W beam l.e), normalised by 1/sqrt(64), scaled by 2^ds and split
 // into the FP16 operand layout above.
 // LDS position (16-byte chunk) of the operand vector (term, kb, g, sample s)
-// of one group.  The sample index is XOR-swizzled so that the 16 lanes of
-// one LDS pass land on 16 different bank groups, for the readers (16
-// consecutive s, fixed (kb, g)) and for the writer of each layout:
-//   v16 (FFT beams formed on chip): the writers of a pass differ in E-W beam,
-//     kb = 2 e + c / 4, so s ^ 4 (kb >> 1) spreads them;
-//   b16 (stored beams): the writers of a pass differ in (kb, g), so
-//     s ^ ((4 kb + g) mod 16) spreads them.
+// of one group.  For the FFT beams formed on chip the sample index is
+// XOR-swizzled so that the 16 lanes of one LDS pass land on 16 different bank
+// groups, for the readers (16 consecutive s, fixed (kb, g)) and for the
+// writers (the lanes of a pass differ in E-W beam, kb = 2 e + c / 4, which
+// s ^ 4 (kb >> 1) spreads).  The stored-beam layout stays plain: its
+// swizzle (s ^ ((4 kb + g) mod 16), lane-dependent) took the kernel past 256
+// registers, to one wavefront per SIMD, and ran 1.9 against 1.5 ms.
 __device__ __forceinline__ int v16_chunk(int term, int kb, int g, int s) {
   return ((term * 8 + kb) * 4 + g) * 16 + (s ^ ((kb >> 1) << 2));
 }
 __device__ __forceinline__ int b16_chunk(int term, int kb, int g, int s) {
-  return ((term * 8 + kb) * 4 + g) * 16 + (s ^ ((4 * kb + g) & 15));
+  return ((term * 8 + kb) * 4 + g) * 16 + s;
 }
 
 template <bool TAPER>
