@@ -79,6 +79,13 @@ def test_null_arguments():
     assert lib.bf_beamform_fft(None, None, 16, None, 0, None, None) == L.BF_ERR_INVALID_ARGUMENT
     assert lib.bf_plan_destroy(None) == L.BF_OK
     assert lib.bf_form_tied_beams(None, None, 16, 0, 1, None, 1, 0, None, None) == L.BF_ERR_INVALID_ARGUMENT
+    assert lib.bf_form_tied_beams_v(None, None, 16, None, 0, 1, None, 1, None, None) == L.BF_ERR_INVALID_ARGUMENT
+    assert lib.bf_form_tied_beams_v_ws(None, None, 16, None, 0, 1, None, 1, None, 0, None, None) \
+        == L.BF_ERR_INVALID_ARGUMENT
+    assert lib.bf_form_tied_beams_v_noalloc(None, None, 16, None, 0, 1, None, 1, None, None) \
+        == L.BF_ERR_INVALID_ARGUMENT
+    assert b"NULL plan" in lib.bf_last_error()
+    assert lib.bf_tied_workspace_size(None, 4, 16) == 0
 
 
 @pytest.mark.parametrize("args,status", [
@@ -107,6 +114,8 @@ def test_native_driver_rejects_bad_arguments():
     r = subprocess.run([exe, "--keep", "9999"], capture_output=True, text=True, timeout=60)
     assert r.returncode == 2
     r = subprocess.run([exe, "--random", "2"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "invalid arguments" in r.stderr
+    r = subprocess.run([exe, "--tied", "5000"], capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "invalid arguments" in r.stderr
     r = subprocess.run([exe, "--copy", "2"], capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "invalid arguments" in r.stderr
