@@ -303,3 +303,38 @@ def test_tied_from_voltages_other_lattices(n_ns):
     assert got.shape == ref.shape
     assert rel_err(got, ref) < TOL_FP32
     plan.close()
+
+
+def test_tied_from_voltages_workspace_empty_and_errors():
+    """Empty calls return without launching; shape and workspace errors are
+    reported before any launch (4 x 64 lattice, workspace path)."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    import paper_1710_08591_amd._lib as L
+    w = sg.custom_workload(n_ew=4, n_ns=64, n_chan=2, n_pol=1, n_time=32, seed=3)
+    plan = plan_for(w, clamp=False)
+    vt = torch.from_numpy(sg.volts(w)).cuda()
+    d = torch.zeros((2, 2), dtype=torch.float64, device="cuda")
+    out = torch.full((2, 2, 1, 2), 7.0, dtype=torch.float32, device="cuda")
+    ws = torch.empty(bf.tied_workspace_size(plan, 2, 32), dtype=torch.uint8, device="cuda")
+    lib = L.lib()
+    ptr = lambda t: bf._ptr(t)  # noqa: E731
+    # n_time, n_point or n_chan_sub zero: OK, nothing written
+    for nt, npnt, ncs in ((0, 2, 2), (32, 0, 2), (32, 2, 0)):
+        st = lib.bf_form_tied_beams_v_ws(plan.handle, ptr(vt), nt, None, 0, ncs, ptr(d), npnt, ptr(ws),
+                                         ws.numel(), ptr(out), None)
+        assert st == bf.BF_OK
+        st = lib.bf_form_tied_beams_v_noalloc(plan.handle, ptr(vt), nt, None, 0, ncs, ptr(d), npnt, ptr(out), None)
+        assert st == bf.BF_OK
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    # a sample count that is not a multiple of the block, a workspace below one block
+    assert lib.bf_form_tied_beams_v_ws(plan.handle, ptr(vt), 24, None, 0, 2, ptr(d), 2, ptr(ws), ws.numel(),
+                                       ptr(out), None) == bf.BF_ERR_INVALID_ARGUMENT
+    assert lib.bf_form_tied_beams_v_ws(plan.handle, ptr(vt), 32, None, 0, 2, ptr(d), 2, ptr(ws),
+                                       bf.tied_workspace_size(plan, 2, 16) - 8, ptr(out), None) \
+        == bf.BF_ERR_INVALID_ARGUMENT
+    # channel range outside the plan
+    assert lib.bf_form_tied_beams_v_noalloc(plan.handle, ptr(vt), 32, None, 1, 2, ptr(d), 2, ptr(out), None) \
+        == bf.BF_ERR_INVALID_ARGUMENT
+    plan.close()
