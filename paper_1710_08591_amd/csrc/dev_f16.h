@@ -37,14 +37,31 @@ __host__ __device__ constexpr int fp8_shift(int p) { return p == 0 ? 0 : (p == 1
 __device__ __forceinline__ float fp8_to_f32(int byte) { return __builtin_amdgcn_cvt_f32_fp8(byte, 0); }
 __device__ __forceinline__ int f32_to_fp8(float v) { return __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xFF; }
 
+// dot8 weights (Re, Im) of the first-stage E-W sums: column 0 x0 + x2,
+// 1 x1 + x3, 2 x0 - x2, 3 x1 - x3
+__device__ __forceinline__ void ew_half_weights(int col, int& wre, int& wim) {
+  const int sgn = col < 2 ? 1 : 0xF;
+  const int q0 = col & 1, q1 = q0 + 2;
+  wre = (1 << (8 * q0 + 4)) | (sgn << (8 * q1 + 4));
+  wim = (1 << (8 * q0)) | (sgn << (8 * q1));
+}
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
 // eight small integers times a power-of-two scale as e4m3 bytes (exact for
-// the int4 voltages and the scales of fp8_shift), byte j = v[j]
+// the int4 voltages, their first-stage E-W sums and the scales of fp8_shift),
+// byte j = v[j].  gfx950's scaled conversion takes two values per
+// instruction and applies the scale itself: it divides by the power of two
+// in its scale operand, so 1/scale is passed.  The integer-to-float
+// conversions are shared by every term of the same values.
 __device__ __forceinline__ long to_fp8(const int* v, float scale) {
-  int w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[0] * scale, (float)v[1] * scale, 0, false);
-  w0 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[2] * scale, (float)v[3] * scale, w0, true);
-  int w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[4] * scale, (float)v[5] * scale, 0, false);
-  w1 = __builtin_amdgcn_cvt_pk_fp8_f32((float)v[6] * scale, (float)v[7] * scale, w1, true);
-  return (long)(unsigned)w0 | ((long)(unsigned)w1 << 32);
+  const float div = 1.0f / scale;
+  short2v w0 = {0, 0}, w1 = {0, 0};
+  w0 = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w0, (float)v[0], (float)v[1], div, false);
+  w0 = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w0, (float)v[2], (float)v[3], div, true);
+  w1 = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w1, (float)v[4], (float)v[5], div, false);
+  w1 = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w1, (float)v[6], (float)v[7], div, true);
+  return (long)(unsigned)__builtin_bit_cast(int, w0) | ((long)(unsigned)__builtin_bit_cast(int, w1) << 32);
 }
 
 }  // namespace fftbf

@@ -9,20 +9,22 @@
 // A holds exact integers: in FP16 the E-W sums of one E-W beam (the 4-point
 // E-W DFT has twiddles +-1, +-i, so the sums are integers of magnitude at
 // most 32, formed by signed 4-bit dot products on the packed bytes); in FP8
-// the raw int4 voltages of one E-W column, because e4m3 does not hold every
-// E-W sum (17, for one).  B holds the realified DFT coefficients, split into
+// the first radix-2 stage of the E-W DFT only (x0 +- x2, x1 +- x3, at most
+// 16 in magnitude), because e4m3 does not hold every full E-W sum (17, for
+// one).  B holds the realified DFT coefficients, split into
 // terms of the working precision that accumulate into the same FP32
 // accumulators:
 //   FP16:  W = hi + lo                               (two passes)
 //   FP8:   W = hi + 2^-5 lo1 + 2^-9 lo2              (three passes; the
 //          power-of-two factor moves onto the exact data operand so that
 //          every coefficient term sits in the normal range of e4m3)
-// FP16 then needs only |B|^2 and the block sum; FP8 runs the E-W 4-point
-// DFT in FP32 on the accumulators, in-lane, before them.
+// FP16 then needs only |B|^2 and the block sum; FP8 runs the second E-W
+// stage in FP32 on the accumulators, in-lane, before them.
 //
-// v_mfma_f32_16x16x32_{f16,fp8_fp8} operands (lane l): A row = l % 16 (one
-// sample), B column = l % 16 (one beam), both holding k in
-// [8 (l/16), 8 (l/16) + 8); C holds column l % 16, rows 4 (l/16) + i.
+// v_mfma_f32_16x16x32_f16 operands (lane l): A row = l % 16 (one sample),
+// B column = l % 16 (one beam), both holding k in [8 (l/16), 8 (l/16) + 8);
+// C holds column l % 16, rows 4 (l/16) + i.  FP8 stacks its three terms
+// along K of one v_mfma_scale_f32_16x16x128_f8f6f4 (32 K values per lane).
 #include "dev_common.h"
 #include "dev_f16.h"
 #include "kernels.h"
@@ -297,10 +299,12 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
             }
           }
         } else {
-          // FP8: the raw int4 of each E-W column (e4m3-exact) through the N-S
-          // products, then the E-W 4-point DFT in FP32 on the accumulators;
-          // one beam tile (kt) at a time, so that only half of the
-          // accumulators are live
+          // FP8: e4m3 holds every integer up to 16 but not every E-W sum, so
+          // the data operand takes the first radix-2 stage of the E-W DFT
+          // (x0 + x2, x1 + x3, x0 - x2, x1 - x3: exact, as signed 4-bit dot
+          // products) through the N-S products, and the second stage runs in
+          // FP32 on the accumulators; one beam tile (kt) at a time, so that
+          // only half of the accumulators are live
           // lane (g, n): sample n at N-S positions 4 g + q (the dwords of
           // fr[g]); per column its 8 (position, re|im) values once per term
           // (times 2^-shift), then 8 zeros, along K = 128
@@ -309,11 +313,13 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
           i32x8 A[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
+            int wre, wim;
+            ew_half_weights(c, wre, wim);
             int v[8];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              v[2 * q] = (int)__builtin_amdgcn_sbfe((int)dq[q], 8 * c + 4, 4);
-              v[2 * q + 1] = (int)__builtin_amdgcn_sbfe((int)dq[q], 8 * c, 4);
+              v[2 * q] = sdot8((int)dq[q], wre);
+              v[2 * q + 1] = sdot8((int)dq[q], wim);
             }
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
@@ -335,15 +341,15 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
                 acc[c][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
                     A[c], B8[kt][part], acc[c][part], 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
               }
-            // E-W 4-point DFT across the four columns, |B|^2, sum of the lane's 4 samples
+            // second E-W stage on the columns S02, S13, D02, D13:
+            // B_0 = S02 + S13, B_2 = S02 - S13, B_1 = D02 - i D13, B_3 = D02 + i D13;
+            // |B|^2, sum of the lane's 4 samples
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float y0r = acc[0][0][i], y0i = acc[0][1][i];
-              const float y1r = acc[1][0][i], y1i = acc[1][1][i];
-              const float y2r = acc[2][0][i], y2i = acc[2][1][i];
-              const float y3r = acc[3][0][i], y3i = acc[3][1][i];
-              const float s02r = y0r + y2r, s02i = y0i + y2i, d02r = y0r - y2r, d02i = y0i - y2i;
-              const float s13r = y1r + y3r, s13i = y1i + y3i, d13r = y1r - y3r, d13i = y1i - y3i;
+              const float s02r = acc[0][0][i], s02i = acc[0][1][i];
+              const float s13r = acc[1][0][i], s13i = acc[1][1][i];
+              const float d02r = acc[2][0][i], d02i = acc[2][1][i];
+              const float d13r = acc[3][0][i], d13i = acc[3][1][i];
               ia[0][kt] = cnorm_acc(cf{s02r + s13r, s02i + s13i}, ia[0][kt]);
               ia[2][kt] = cnorm_acc(cf{s02r - s13r, s02i - s13i}, ia[2][kt]);
               ia[1][kt] = cnorm_acc(cf{d02r + d13i, d02i - d13r}, ia[1][kt]);
@@ -410,15 +416,6 @@ __global__ void k_mixp_twiddles(void* tab, int R) {
   double s, c;
   sincospi(-2.0 * (double)((a0 * m) % (32 * R)) / (double)(32 * R), &s, &c);
   reinterpret_cast<float2*>(static_cast<char*>(tab) + kMixTwOff)[i] = make_float2((float)c, (float)s);
-}
-
-// dot8 weights (Re, Im) of the first-stage E-W sums: column 0 x0 + x2,
-// 1 x1 + x3, 2 x0 - x2, 3 x1 - x3
-__device__ __forceinline__ void ew_half_weights(int col, int& wre, int& wim) {
-  const int sgn = col < 2 ? 1 : 0xF;
-  const int q0 = col & 1, q1 = q0 + 2;
-  wre = (1 << (8 * q0 + 4)) | (sgn << (8 * q1 + 4));
-  wim = (1 << (8 * q0)) | (sgn << (8 * q1));
 }
 
 template <int PREC, int R, bool WIN>

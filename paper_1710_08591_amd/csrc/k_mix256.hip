@@ -31,8 +31,9 @@
 // table can be stored with coalesced writes.
 //
 // FP8 variant: e4m3 does not hold every E-W sum (17, for one), so the data
-// operand holds the raw int4 of one E-W antenna column (exact), and the E-W
-// 4-point DFT runs in FP32 on the stage-1 outputs, before the twiddle.  The
+// operand holds only the first radix-2 stage of the E-W DFT (x0 +- x2,
+// x1 +- x3: at most 16 in magnitude, exact), and the second stage runs in
+// FP32 on the stage-1 outputs, before the twiddle.  The
 // coefficients are split into three e4m3 terms, W = hi + 2^-5 lo1 + 2^-9 lo2,
 // stacked along K of one v_mfma_scale_f32_16x16x128_f8f6f4 (unit block
 // scales): lane group g holds in its 32 K values the (a2, re|im) of a2 in
@@ -405,16 +406,19 @@ __global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
   const int64_t t0 = (int64_t)blk * a.block;
 
   auto frame = [&](const uint32_t (&dw)[4]) {
-    // data operands of the four E-W antenna columns: (Re, Im) at the lane's
-    // four N-S positions, once per term (times 2^-shift), then zeros
+    // data operands of the first E-W radix-2 stage (x0 + x2, x1 + x3,
+    // x0 - x2, x1 - x3; exact in e4m3): (Re, Im) at the lane's four N-S
+    // positions, once per term (times 2^-shift), then zeros
     i32x8 A[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      int wre, wim;
+      ew_half_weights(q, wre, wim);
       int v[8];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        v[2 * i] = __builtin_amdgcn_sbfe((int)dw[i], 8 * q + 4, 4);
-        v[2 * i + 1] = __builtin_amdgcn_sbfe((int)dw[i], 8 * q, 4);
+        v[2 * i] = sdot8((int)dw[i], wre);
+        v[2 * i + 1] = sdot8((int)dw[i], wim);
       }
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
@@ -427,7 +431,7 @@ __global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
     }
 #pragma unroll
     for (int kt = 0; kt < 2; ++kt) {
-      // ---- stage 1 per E-W column, then the E-W DFT and the twiddle, into the tile ----
+      // ---- stage 1 per first-stage E-W column, then the second E-W stage and the twiddle, into the tile ----
       f32x4 y[4][2];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -437,10 +441,10 @@ __global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
               A[q], B[kt][part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, kUnitScale, 0, kUnitScale);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        // X_e = sum_q Y_q (-i)^{e q}
-        const cf y0{y[0][0][i], y[0][1][i]}, y1{y[1][0][i], y[1][1][i]};
-        const cf y2{y[2][0][i], y[2][1][i]}, y3{y[3][0][i], y[3][1][i]};
-        const cf s02 = cadd(y0, y2), d02 = csub(y0, y2), s13 = cadd(y1, y3), d13 = csub(y1, y3);
+        // second E-W stage: X_0 = S02 + S13, X_1 = D02 - i D13,
+        // X_2 = S02 - S13, X_3 = D02 + i D13
+        const cf s02{y[0][0][i], y[0][1][i]}, s13{y[1][0][i], y[1][1][i]};
+        const cf d02{y[2][0][i], y[2][1][i]}, d13{y[3][0][i], y[3][1][i]};
         const cf x[4] = {cadd(s02, s13), cf{d02.r + d13.i, d02.i - d13.r}, csub(s02, s13),
                          cf{d02.r - d13.i, d02.i + d13.r}};
 #pragma unroll
