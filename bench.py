@@ -246,20 +246,23 @@ def _leg(fn, *args):
         return {"error": f"{type(e).__name__}: {e}"}
 
 
-def _time_launches(fn, n: int, warmup: int = 2) -> float:
-    """Average milliseconds of fn() (one launch on the current stream)."""
+def _time_launches(fn, n: int, warmup: int = 2, each: list = None) -> float:
+    """Average milliseconds of fn() (one launch on the current stream);
+    with ``each`` the time of every launch is appended to it."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(s)
-    for _ in range(n):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    ev[0].record(s)
+    for i in range(n):
         fn()
-    b.record(s)
+        ev[i + 1].record(s)
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / n
+    if each is not None:
+        each.extend(round(ev[i].elapsed_time(ev[i + 1]), 4) for i in range(n))
+    return ev[0].elapsed_time(ev[n]) / n
 
 
 def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict:
@@ -648,8 +651,10 @@ def run_larger_lattices(dev, checks: OracleChecks) -> dict:
         for prec, name in ((0, "fp32_fft"), (1, "fp16_mfma"), (2, "fp8_mfma")):
             plan = bf.Plan(n_ew=4, n_ns=n_ns, n_pol=2, n_chan=256, block=16, precision=prec)
             out = torch.empty(plan.out_shape(w.n_time), dtype=torch.float32, device=dev)
-            ms = _time_launches(lambda: bf.beamform_fft(plan, volts, out=out), 5)
-            variants[name] = {"antenna_samples_per_s": w.antenna_samples / (ms / 1e3), "kernel_ms": ms}
+            each = []
+            ms = _time_launches(lambda: bf.beamform_fft(plan, volts, out=out), 5, warmup=3, each=each)
+            variants[name] = {"antenna_samples_per_s": w.antenna_samples / (ms / 1e3), "kernel_ms": ms,
+                              "kernel_ms_each": each}
             for b, c, p in picks:
                 checks.add(variants[name], "max_rel_power_err_sampled", "fft_rel", out[b, c, p].cpu().numpy(),
                            v=sg.volts(w, b * 16, 16, chans=[c], pols=[p]), m_ew=4, m_ns=2 * n_ns, index=(0, 0, 0))

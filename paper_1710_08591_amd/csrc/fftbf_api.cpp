@@ -278,7 +278,9 @@ static bf_status beamform_fft_impl(const bf_plan* plan, const uint8_t* volts, in
     if (plan->fold > 1 && taper && (taper_kind != 1 || plan->fold > 8))
       return fail(BF_ERR_UNSUPPORTED, "beamform_fft: cyclic co-adding takes a real window only, up to 8-fold");
     e = fftbf::launch_fft32(a, d.n_ns / plan->fold, taper ? taper_kind : 0, kind == BF_OUT_COMPLEX, n_wg, s);
-    if (e == hipSuccess && d.m_ew == 8) {
+    const bool fused = fftbf::fft32_fuses_ew8(d.n_ns / plan->fold, taper ? taper_kind : 0, kind == BF_OUT_COMPLEX,
+                                              plan->fold);
+    if (e == hipSuccess && d.m_ew == 8 && !fused) {
       // odd E-W beams of the zero-padded 8-point E-W transform: the 4-point
       // DFT of x_a W_8^{a_ew} (with the window or gains, if any)
       a.ew_off = 1;

@@ -473,7 +473,9 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
 // during the second half only: 128 registers and about 10 KB of LDS per
 // wavefront, so four wavefronts fit per SIMD (two for the kernel above).
 // Unwindowed intensities; the window, gain and complex-output variants of
-// this lattice take the kernel above.
+// this lattice take the kernel above.  k_fft32_ew8 is the same kernel for
+// an E-W axis zero-padded to 8 beams: each wavefront runs its block twice,
+// for the even and then the odd E-W beams, so one launch writes all eight.
 constexpr int kHWpg = 4;                 // wavefronts per workgroup
 constexpr int kHRow = 44;                // LDS floats per (half, a1) row: 16 tangents, 25 multipliers, pad
 
@@ -500,7 +502,18 @@ struct HalfTw {
   }
 };
 
-__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_h(Fft32Args p) {
+template <bool B> struct BoolC {
+  static constexpr bool value = B;
+};
+
+// EW8: the E-W axis zero-padded to 8 beams in one launch.  After the even
+// beams (the 4-point DFT, rows 2e) of a block, the wavefront runs the block
+// again for the odd beams (rows 2e + 1: the 4-point DFT of x_a W_8^{a_ew}),
+// reading its voltages a second time.  The odd pass forms four dot products
+// per position instead of two and keeps three values in scratch memory
+// across its frame loop (three scratch accesses per frame).
+template <bool EW8>
+__device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   constexpr int N = 256, G = 16, L = 16, M = 512;
   constexpr int NSL = dit_slots(G);
   constexpr int YS = L + 1;
@@ -512,11 +525,17 @@ __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4)))
   // put the 16 rows a lane group reads on different bank groups
   __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
   __shared__ cf lds_c16[G];                                           // whole twiddle of column k2 = 16
+  __shared__ int4 lds_w8[EW8 ? 4 : 1];                                // odd E-W beams' dot8 weights
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cf* const lds_y = lds_tiles + wave * 64 * YS;
   const int e1 = lane >> 4, a1 = lane & 15;
+  if (EW8 && threadIdx.x < 4) {
+    int4 w;
+    ew8_odd_weights((int)threadIdx.x, w.x, w.y, w.z, w.w);
+    lds_w8[threadIdx.x] = w;
+  }
 
   for (int i = threadIdx.x; i < 2 * G * L; i += 64 * kHWpg) {
     const int h = i / (G * L), r = i % (G * L), aa = r / L, m = r % L;
@@ -539,102 +558,135 @@ __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4)))
   const int chan = wg % p.n_chan;
   const int blk = wg / p.n_chan;
 
-  int wre = 0, wim = 0;
-  ew_weights(e1, wre, wim);
-
-  float acc[2][G];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int k = 0; k < G; ++k) acc[h][k] = 0.f;
-
   const int64_t t_base = (int64_t)blk * p.block;
   const int n_it = p.block;
   const int64_t frame_stride = (int64_t)(p.chan_stride ? p.chan_stride : p.n_chan) * p.n_pol * N;
   const int n_valid = (int)((p.n_time - t_base) < p.block ? (p.n_time - t_base) : p.block);
   cf* const row = &lds_y[lane * YS];
 
-  for (int pi = 0; pi < p.pol_iter; ++pi) {
-    const int pol = (p.pol_iter == 1) ? pg : pi;
-    const uint32_t* src = p.volts + ((int64_t)chan * p.n_pol + pol) * N + a1;
-    const uint32_t* q = src + t_base * frame_stride;
-    uint32_t b[L];
+  auto pass = [&](auto odd_c) {
+    constexpr bool ODD = decltype(odd_c)::value;
+    int wre = 0, wim = 0;
+    if constexpr (!ODD) ew_weights(e1, wre, wim);
+
+    float acc[2][G];
 #pragma unroll
-    for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + G * j);
-    for (int it = 0; it < n_it; ++it) {
-      cf x[L];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int j = 0; j < L; ++j) x[j] = cf{(float)sdot8((int)b[j], wre), (float)sdot8((int)b[j], wim)};
-      cf xo[L];
-      padded_odd_t<L>(x, xo);
-      dit<L>(x);
+      for (int k = 0; k < G; ++k) acc[h][k] = 0.f;
+
+    for (int pi = 0; pi < p.pol_iter; ++pi) {
+      const int pol = (p.pol_iter == 1) ? pg : pi;
+      // the frame pointer is the wavefront's (scalar); the lane adds a1
+      const uint32_t* q = p.volts + ((int64_t)chan * p.n_pol + pol) * N + t_base * frame_stride;
+      uint32_t b[L];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const cf* y = h ? xo : x;
-        if (h == 1) {
-          // the next frame's loads, in flight through this half (past the
-          // block: the buffer's first frame, cached)
-          q = (it + 1 >= n_it) ? p.volts + a1 : ((it + 1 < n_valid) ? q + frame_stride : q);
+      for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + a1 + G * j);
+      for (int it = 0; it < n_it; ++it) {
+        cf x[L];
+        if constexpr (ODD) {
+          // P + Q / sqrt(2) (the weights are read from the LDS per frame:
+          // held across the loop they would cost two more registers)
+          constexpr float kS = 0.70710678118654752f;
+          const int4 w8 = lds_w8[e1];
+          const int wpr = w8.x, wpi = w8.y, wqr = w8.z, wqi = w8.w;
 #pragma unroll
-          for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + G * j);
-        }
-        {
-          float t1[L];
-          const float4* tp = reinterpret_cast<const float4*>(&lds_tab[h][a1][0]);
-#pragma unroll
-          for (int k = 0; k < L / 4; ++k) {
-            const float4 v = tp[k];
-            t1[4 * k] = v.x;
-            t1[4 * k + 1] = v.y;
-            t1[4 * k + 2] = v.z;
-            t1[4 * k + 3] = v.w;
+          for (int j = 0; j < L; ++j) {
+            const float pr = (float)sdot8((int)b[j], wpr), pim = (float)sdot8((int)b[j], wpi);
+            const float qr = (float)sdot8((int)b[j], wqr), qi = (float)sdot8((int)b[j], wqi);
+            x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pim)};
           }
-          // (the whole twiddle of column 16 is read per frame: held across
-          // the frame loop it would take the last free register)
-          if (h == 0) HalfTw<0, 0>::run(y, t1, lds_c16[a1], row);
-          else HalfTw<1, 0>::run(y, t1, cf{}, row);
+        } else {
+#pragma unroll
+          for (int j = 0; j < L; ++j) x[j] = cf{(float)sdot8((int)b[j], wre), (float)sdot8((int)b[j], wim)};
         }
-        wave_lds_sync();
-        cf z[G];
+        cf xo[L];
+        padded_odd_t<L>(x, xo);
+        dit<L>(x);
 #pragma unroll
-        for (int j = 0; j < G; ++j) z[j] = lds_y[(e1 * 16 + j) * YS + a1];
-        wave_lds_sync();
-        float mu[28];
-        const float4* mp = reinterpret_cast<const float4*>(&lds_tab[h][a1][L]);
+        for (int h = 0; h < 2; ++h) {
+          const cf* y = h ? xo : x;
+          if (h == 1) {
+            // the next frame's loads, in flight through this half (past the
+            // block: the buffer's first frame, cached)
+            q = (it + 1 >= n_it) ? p.volts : ((it + 1 < n_valid) ? q + frame_stride : q);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-          const float4 v = mp[k];
-          mu[4 * k] = v.x;
-          mu[4 * k + 1] = v.y;
-          mu[4 * k + 2] = v.z;
-          mu[4 * k + 3] = v.w;
+            for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + a1 + G * j);
+          }
+          {
+            float t1[L];
+            const float4* tp = reinterpret_cast<const float4*>(&lds_tab[h][a1][0]);
+#pragma unroll
+            for (int k = 0; k < L / 4; ++k) {
+              const float4 v = tp[k];
+              t1[4 * k] = v.x;
+              t1[4 * k + 1] = v.y;
+              t1[4 * k + 2] = v.z;
+              t1[4 * k + 3] = v.w;
+            }
+            // (the whole twiddle of column 16 is read per frame: held across
+            // the frame loop it would take the last free register)
+            if (h == 0) HalfTw<0, 0>::run(y, t1, lds_c16[a1], row);
+            else HalfTw<1, 0>::run(y, t1, cf{}, row);
+          }
+          wave_lds_sync();
+          cf z[G];
+#pragma unroll
+          for (int j = 0; j < G; ++j) z[j] = lds_y[(e1 * 16 + j) * YS + a1];
+          wave_lds_sync();
+          float mu[28];
+          const float4* mp = reinterpret_cast<const float4*>(&lds_tab[h][a1][L]);
+#pragma unroll
+          for (int k = 0; k < 7; ++k) {
+            const float4 v = mp[k];
+            mu[4 * k] = v.x;
+            mu[4 * k + 1] = v.y;
+            mu[4 * k + 2] = v.z;
+            mu[4 * k + 3] = v.w;
+          }
+          dit_rs<G>(z, mu);
+#pragma unroll
+          for (int k1 = 0; k1 < G; ++k1) acc[h][k1] = cnorm_acc(z[k1], acc[h][k1]);
         }
-        dit_rs<G>(z, mu);
-#pragma unroll
-        for (int k1 = 0; k1 < G; ++k1) acc[h][k1] = cnorm_acc(z[k1], acc[h][k1]);
       }
     }
-  }
 
-  // ---- block end: the kept beams of the channel, coalesced stores ----
-  // E-W beam e's sums start at 512 e + (e & 1) + 32 (e >> 1): the four lane
-  // groups of one store then cover all 64 banks
-  float* lds_i = reinterpret_cast<float*>(lds_y);
-  auto ebase = [](int e) { return e * M + (e & 1) + 32 * (e >> 1); };
+    // ---- block end: the kept beams of the channel, coalesced stores ----
+    // E-W beam e's sums start at 512 e + (e & 1) + 32 (e >> 1): the four lane
+    // groups of one store then cover all 64 banks
+    float* lds_i = reinterpret_cast<float*>(lds_y);
+    auto ebase = [](int e) { return e * M + (e & 1) + 32 * (e >> 1); };
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int k1 = 0; k1 < G; ++k1) lds_i[ebase(e1) + 2 * a1 + h + 32 * k1] = acc[h][k1];
-  wave_lds_sync();
-  const int keep = p.n_keep;
-  const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
-  float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
+      for (int k1 = 0; k1 < G; ++k1) lds_i[ebase(e1) + 2 * a1 + h + 32 * k1] = acc[h][k1];
+    wave_lds_sync();
+    const int keep = p.n_keep;
+    const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
+    float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
-    for (int j = lane; j < keep; j += 64) {
-      const int A = sel ? sel[j] : j;
-      o[(e * p.ew_mul + p.ew_off) * keep + j] = lds_i[ebase(e) + A] * p.norm;
+    for (int e = 0; e < 4; ++e) {
+      const int r = EW8 ? 2 * e + (ODD ? 1 : 0) : e * p.ew_mul + p.ew_off;
+      for (int j = lane; j < keep; j += 64) {
+        const int A = sel ? sel[j] : j;
+        o[r * keep + j] = lds_i[ebase(e) + A] * p.norm;
+      }
     }
+  };
+
+  pass(BoolC<false>{});
+  if constexpr (EW8) {
+    wave_lds_sync();          // the block-end reads of the tile before the odd pass writes it
+    pass(BoolC<true>{});
+  }
+}
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_h(Fft32Args p) {
+  fft32_h_run<false>(p);
+}
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_ew8(Fft32Args p) {
+  fft32_h_run<true>(p);
 }
 
 template <int N, int G, int T, int FOLD = 1>
@@ -676,7 +728,8 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
   if constexpr (N == 256) {
     if (taper == 0 && !cplx) {       // the 4 x 256 intensities: half-size tiles, four waves per SIMD
       const dim3 grid((unsigned)((a.n_wg + kHWpg - 1) / kHWpg)), threads(64 * kHWpg);
-      hipLaunchKernelGGL(k_fft32_h, grid, threads, 0, s, a);
+      if (a.ew_rows == 8) hipLaunchKernelGGL(k_fft32_ew8, grid, threads, 0, s, a);   // even and odd E-W beams
+      else hipLaunchKernelGGL(k_fft32_h, grid, threads, 0, s, a);
       return hipGetLastError();
     }
   }
@@ -690,6 +743,10 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
 }  // namespace
 
 int fft32_group(int n_ns, int fold) { return fft32_g(n_ns, fold); }
+
+bool fft32_fuses_ew8(int n_ns, int taper, bool cplx, int fold) {
+  return n_ns == 256 && taper == 0 && !cplx && fold == 1;
+}
 
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s) {

@@ -44,9 +44,11 @@ struct Fft32Args {
 int fft32_group(int n_ns, int fold = 1);
 // n_ns: the transform's N (m_ns / 2, or m_ns when folding); taper: 0 none,
 // 1 real weights, 2 complex gains, 3 none with the odd E-W beams of the
-// zero-padded 8-point E-W transform
+// zero-padded 8-point E-W transform.  With a.ew_rows == 8 and
+// fft32_fuses_ew8(...) one launch writes the even and the odd E-W beams.
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
                         hipStream_t s);
+bool fft32_fuses_ew8(int n_ns, int taper, bool cplx, int fold);
 
 // FP64 table generation on the device
 int twiddle_mult_count(int g, int l2);

@@ -50,15 +50,18 @@ def test_ew8_beams_parity(n_ns, window):
     plan.close()
 
 
-def test_ew8_clamp_and_pol_sum():
+@pytest.mark.parametrize("n_ns,keep,pol_sum", [(32, 20, True), (256, 200, True), (256, 256, False)])
+def test_ew8_clamp_and_pol_sum(n_ns, keep, pol_sum):
+    """Clamped and polarisation-summed padded-E-W intensities; at n_ns = 256
+    one launch forms the even and the odd E-W beams."""
     torch = _torch()
     import paper_1710_08591_amd as bf
-    w = sg.custom_workload(n_ew=4, n_ns=32, n_chan=2, n_pol=2, n_time=64, seed=9, n_ns_keep=20)
+    w = sg.custom_workload(n_ew=4, n_ns=n_ns, n_chan=3, n_pol=2, n_time=64, seed=9 + n_ns, n_ns_keep=keep)
     v = sg.volts(w)
-    plan = _plan(bf, w, pol_sum=True, sel=w.ns_select())
+    plan = _plan(bf, w, pol_sum=pol_sum, sel=w.ns_select())
     got = bf.beamform_fft(plan, torch.from_numpy(v).cuda()).cpu().numpy()
-    ref = orc.beamform_fft(v, 8, 64, 16, ns_select=w.ns_select(), pol_sum=True)
-    assert got.shape == ref.shape == (4, 2, 8, 20)
+    ref = orc.beamform_fft(v, 8, 2 * n_ns, 16, ns_select=w.ns_select(), pol_sum=pol_sum)
+    assert got.shape == ref.shape == ((4, 3, 8, keep) if pol_sum else (4, 3, 2, 8, keep))
     assert rel_err(got, ref) < TOL_FP32
     plan.close()
 
