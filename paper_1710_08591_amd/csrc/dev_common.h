@@ -364,6 +364,23 @@ constexpr bool cmul_col(int k, int g, int m) {
   return false;
 }
 
+// Task w of n_wg single-wavefront workgroups -> (polarisation group pg,
+// rest = the task's other indices).  A 4 x 16 frame is 64 bytes, half a
+// 128-byte line whose other half is the other polarisation, and consecutive
+// workgroups go to different XCDs (separate L2 caches), so with two
+// polarisation groups the pair is placed 8 apart (same XCD, close in time)
+// and shares the line; a tail that is not a multiple of 16 keeps the plain
+// order.
+__device__ __forceinline__ int pol_pair_task(int w, int n_wg, int n_pg, int& pg) {
+  if (n_pg == 2 && w < n_wg - n_wg % 16) {
+    const int slot = w >> 3;
+    pg = slot & 1;
+    return ((slot >> 1) << 3) | (w & 7);
+  }
+  pg = w % n_pg;
+  return w / n_pg;
+}
+
 // Signed 4-bit dot product of the eight nibbles of a and b, accumulator 0
 // (the three-operand VOP3P form, so no register has to be zeroed first).
 __device__ __forceinline__ int sdot8(int a, int b) {

@@ -212,9 +212,14 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
   cf* const lds_y = lds_tiles + wave * TILE;
   const int f1 = lane / (4 * G), e1 = (lane / G) & 3, a1 = lane % G;
 
-  int wg = (int)((int64_t)blockIdx.x * WPG + wave);
-  const int pg = wg % p.n_pg;
-  wg /= p.n_pg;
+  int pg, wg;
+  if constexpr (WPG == 1 && N * FOLD == 16) {
+    wg = pol_pair_task((int)blockIdx.x, (int)p.n_wg, p.n_pg, pg);
+  } else {
+    wg = (int)((int64_t)blockIdx.x * WPG + wave);
+    pg = wg % p.n_pg;
+    wg /= p.n_pg;
+  }
   const int chan = wg % p.n_chan;
   const int blk = wg / p.n_chan;
 

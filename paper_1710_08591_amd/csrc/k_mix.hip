@@ -168,9 +168,8 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
 
   const int lane = threadIdx.x;
   const int n = lane & 15, g = lane >> 4;
-  int wg = blockIdx.x;
-  const int pg = wg % a.n_pg;
-  wg /= a.n_pg;
+  int pg;
+  const int wg = pol_pair_task((int)blockIdx.x, (int)gridDim.x, a.n_pg, pg);
   const int chan = wg % a.n_chan;
   const int run = wg / a.n_chan;
   const int64_t n_blk = a.n_time / a.block;
@@ -239,7 +238,9 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
       for (int sub = 0; sub < a.block; sub += 16) {
         const int64_t t = blk * a.block + sub + n;
         const uint4* fr = reinterpret_cast<const uint4*>(a.volts + ((t * a.n_chan + chan) * a.n_pol + pol) * 16);
-        const uint4 d0 = fr[2 * (g & 1)], d1 = fr[2 * (g & 1) + 1];
+        // FP16: positions 8 (g & 1) to + 8; FP8: positions 4 g to + 4
+        const uint4 d0 = fr[PREC == kPrecFp8 && !WIN ? g : 2 * (g & 1)];
+        const uint4 d1 = PREC == kPrecFp8 && !WIN ? uint4{0, 0, 0, 0} : fr[2 * (g & 1) + 1];
         const uint32_t dw[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
 
         if constexpr (WIN) {
@@ -308,52 +309,55 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
           // lane (g, n): sample n at N-S positions 4 g + q (the dwords of
           // fr[g]); per column its 8 (position, re|im) values once per term
           // (times 2^-shift), then 8 zeros, along K = 128
-          const uint4 d4 = fr[g];
-          const uint32_t dq[4] = {d4.x, d4.y, d4.z, d4.w};
-          i32x8 A[4];
+          const uint32_t dq[4] = {d0.x, d0.y, d0.z, d0.w};
+          // column pair cp: (S02, S13) gives beams 0 and 2, (D02, D13) beams 1
+          // and 3, so only one pair's operands and products are live at a time
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            int wre, wim;
-            ew_half_weights(c, wre, wim);
-            int v[8];
+          for (int cp = 0; cp < 2; ++cp) {
+            i32x8 A[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              v[2 * q] = sdot8((int)dq[q], wre);
-              v[2 * q + 1] = sdot8((int)dq[q], wim);
-            }
+            for (int h = 0; h < 2; ++h) {
+              int wre, wim;
+              ew_half_weights(2 * cp + h, wre, wim);
+              int v[8];
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
-              const long w = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
-              A[c][2 * p] = (int)w;
-              A[c][2 * p + 1] = (int)(w >> 32);
-            }
-            A[c][6] = 0;
-            A[c][7] = 0;
-          }
-#pragma unroll
-          for (int kt = 0; kt < 2; ++kt) {
-            f32x4 acc[4][2];
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-              for (int part = 0; part < 2; ++part) {
-                acc[c][part] = f32x4{0.f, 0.f, 0.f, 0.f};
-                acc[c][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                    A[c], B8[kt][part], acc[c][part], 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
+              for (int q = 0; q < 4; ++q) {
+                v[2 * q] = sdot8((int)dq[q], wre);
+                v[2 * q + 1] = sdot8((int)dq[q], wim);
               }
-            // second E-W stage on the columns S02, S13, D02, D13:
-            // B_0 = S02 + S13, B_2 = S02 - S13, B_1 = D02 - i D13, B_3 = D02 + i D13;
-            // |B|^2, sum of the lane's 4 samples
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float s02r = acc[0][0][i], s02i = acc[0][1][i];
-              const float s13r = acc[1][0][i], s13i = acc[1][1][i];
-              const float d02r = acc[2][0][i], d02i = acc[2][1][i];
-              const float d13r = acc[3][0][i], d13i = acc[3][1][i];
-              ia[0][kt] = cnorm_acc(cf{s02r + s13r, s02i + s13i}, ia[0][kt]);
-              ia[2][kt] = cnorm_acc(cf{s02r - s13r, s02i - s13i}, ia[2][kt]);
-              ia[1][kt] = cnorm_acc(cf{d02r + d13i, d02i - d13r}, ia[1][kt]);
-              ia[3][kt] = cnorm_acc(cf{d02r - d13i, d02i + d13r}, ia[3][kt]);
+              for (int p = 0; p < 3; ++p) {
+                const long w = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
+                A[h][2 * p] = (int)w;
+                A[h][2 * p + 1] = (int)(w >> 32);
+              }
+              A[h][6] = 0;
+              A[h][7] = 0;
+            }
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt) {
+              f32x4 acc[2][2];
+#pragma unroll
+              for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int part = 0; part < 2; ++part)
+                  acc[h][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                      A[h], B8[kt][part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, 0x7F7F7F7F, 0, 0x7F7F7F7F);
+              // second E-W stage: B_0 = S02 + S13, B_2 = S02 - S13 (cp = 0),
+              // B_1 = D02 - i D13, B_3 = D02 + i D13 (cp = 1); |B|^2, sum of
+              // the lane's 4 samples
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const float ar = acc[0][0][i], ai = acc[0][1][i];
+                const float br = acc[1][0][i], bi = acc[1][1][i];
+                if (cp == 0) {
+                  ia[0][kt] = cnorm_acc(cf{ar + br, ai + bi}, ia[0][kt]);
+                  ia[2][kt] = cnorm_acc(cf{ar - br, ai - bi}, ia[2][kt]);
+                } else {
+                  ia[1][kt] = cnorm_acc(cf{ar + bi, ai - br}, ia[1][kt]);
+                  ia[3][kt] = cnorm_acc(cf{ar - bi, ai + br}, ia[3][kt]);
+                }
+              }
             }
           }
         }
