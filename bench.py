@@ -11,6 +11,8 @@ FP32 intensities).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import hashlib
 import json
 import math
@@ -246,6 +248,19 @@ def _leg(fn, *args):
         return {"error": f"{type(e).__name__}: {e}"}
 
 
+@contextlib.contextmanager
+def _no_gc():
+    """Python's cyclic garbage collector held off inside a timed region: a
+    collection pauses the host, and once the launch queue has drained the
+    GPU idles between the events that bracket the launches."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
+
+
 def _time_launches(fn, n: int, warmup: int = 2, each: list = None) -> float:
     """Average milliseconds of fn() (one launch on the current stream);
     with ``each`` the time of every launch is appended to it."""
@@ -255,11 +270,12 @@ def _time_launches(fn, n: int, warmup: int = 2, each: list = None) -> float:
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
-    ev[0].record(s)
-    for i in range(n):
-        fn()
-        ev[i + 1].record(s)
-    torch.cuda.synchronize()
+    with _no_gc():
+        ev[0].record(s)
+        for i in range(n):
+            fn()
+            ev[i + 1].record(s)
+        torch.cuda.synchronize()
     if each is not None:
         each.extend(round(ev[i].elapsed_time(ev[i + 1]), 4) for i in range(n))
     return ev[0].elapsed_time(ev[n]) / n
@@ -868,13 +884,14 @@ def main():
     # launch so the average kernel duration is measured live.
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        bf.beamform_fft(plan, volts, out=out)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
+    with _no_gc():
+        t_start = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            bf.beamform_fft(plan, volts, out=out)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
     kern_ms = [a.elapsed_time(b) for a, b in ev]
     ms_avg = float(np.mean(kern_ms))
     ms_step = wall * 1000.0 / args.steps

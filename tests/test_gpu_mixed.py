@@ -351,3 +351,20 @@ def test_mixp_window_parity(n_ns, scale):
         bf.beamform_fft(plan, vt, taper=ht)
     assert e.value.status == bf.BF_ERR_UNSUPPORTED
     plan.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_lattice4x16_pol_pairs_across_workgroups(prec):
+    """The 4 x 16 kernels place the two polarisations of a frame line 8
+    workgroups apart; with 5 channels and 20 blocks the grid has a part
+    that is a multiple of 16 and a tail in plain order (50 workgroups for
+    the matrix-core kernels, 200 for FP32), and every (block, channel, pol)
+    must still land in its own slot."""
+    w = sg.custom_workload(n_ew=4, n_ns=16, n_chan=5, n_pol=2, n_time=320, seed=77, n_src=2, snr=5.0)
+    v = sg.volts(w)
+    ref = orc.beamform_fft(v, 4, 32, 16)
+    got = _run(w, v, prec, clamp=False)
+    assert got.shape == ref.shape == (20, 5, 2, 4, 32)
+    assert rel_err(got, ref) < (1e-5 if prec < 2 else TOL_MIXED)
+    # each polarisation slot differs from the other (a swapped pair would match the wrong one)
+    assert rel_err(got[:, :, 0], ref[:, :, 1]) > 1e-2
