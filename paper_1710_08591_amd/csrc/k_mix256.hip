@@ -38,8 +38,10 @@
 // stacked along K of one v_mfma_scale_f32_16x16x128_f8f6f4 (unit block
 // scales): lane group g holds in its 32 K values the (a2, re|im) of a2 in
 // [4g, 4g + 4) once per term (8 values each) and 8 zeros, and the power of
-// two of each term sits on the exact data bytes (x, 2^-5 x, 2^-9 x).  The
-// LDS tile then holds all four E-W beams of one beam tile (16 k2) at a time.
+// two of each term sits on the exact data bytes (x, 2^-5 x, 2^-9 x).  One
+// pair of first-stage columns is formed at a time ((S02, S13) gives E-W
+// beams 0 and 2, (D02, D13) beams 1 and 3), and the LDS tile holds that
+// E-W beam pair over both beam tiles, as in the FP16 kernel.
 #include "dev_common.h"
 #include "dev_f16.h"
 #include "kernels.h"
@@ -392,13 +394,13 @@ __global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) tw[k >> 2][k & 3] = cf{w[k].x, w[k].y};
   }
-  const int es = lane >> 4, ks = lane & 15;    // stage-2 E-W beam and column within the tile
+  const int bs = lane >> 5, k2s = lane & 31;   // stage-2 beam of the pair and column k2
 
   float acc[2][16];
 #pragma unroll
-  for (int kt = 0; kt < 2; ++kt)
+  for (int cp = 0; cp < 2; ++cp)
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[kt][k] = 0.f;
+    for (int k = 0; k < 16; ++k) acc[cp][k] = 0.f;
 
   const int pol_lo = (a.pol_iter == 1) ? pg : 0;
   const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
@@ -406,55 +408,61 @@ __global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
   const int64_t t0 = (int64_t)blk * a.block;
 
   auto frame = [&](const uint32_t (&dw)[4]) {
-    // data operands of the first E-W radix-2 stage (x0 + x2, x1 + x3,
-    // x0 - x2, x1 - x3; exact in e4m3): (Re, Im) at the lane's four N-S
-    // positions, once per term (times 2^-shift), then zeros
-    i32x8 A[4];
+    // one pair of first-stage E-W columns at a time: (S02, S13) gives E-W
+    // beams 0 and 2, (D02, D13) beams 1 and 3, through both beam tiles, so
+    // only the pair's operands are live and stage 2 takes one E-W beam pair
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int wre, wim;
-      ew_half_weights(q, wre, wim);
-      int v[8];
+    for (int cp = 0; cp < 2; ++cp) {
+      // data operands of the first E-W radix-2 stage (x0 + x2, x1 + x3,
+      // x0 - x2, x1 - x3; exact in e4m3): (Re, Im) at the lane's four N-S
+      // positions, once per term (times 2^-shift), then zeros
+      i32x8 A[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        v[2 * i] = sdot8((int)dw[i], wre);
-        v[2 * i + 1] = sdot8((int)dw[i], wim);
+      for (int h = 0; h < 2; ++h) {
+        int wre, wim;
+        ew_half_weights(2 * cp + h, wre, wim);
+        int v[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          v[2 * i] = sdot8((int)dw[i], wre);
+          v[2 * i + 1] = sdot8((int)dw[i], wim);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const long w = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
+          A[h][2 * p] = (int)w;
+          A[h][2 * p + 1] = (int)(w >> 32);
+        }
+        A[h][6] = 0;
+        A[h][7] = 0;
       }
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        const long w = to_fp8(v, 1.0f / (float)(1 << fp8_shift(p)));
-        A[q][2 * p] = (int)w;
-        A[q][2 * p + 1] = (int)(w >> 32);
-      }
-      A[q][6] = 0;
-      A[q][7] = 0;
-    }
+      for (int kt = 0; kt < 2; ++kt) {
+        // ---- stage 1, the second E-W stage and the twiddle, into the tile
+        // (row: beam of the pair bs, k2 = 16 kt + n) ----
+        f32x4 y[2][2];
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt) {
-      // ---- stage 1 per first-stage E-W column, then the second E-W stage and the twiddle, into the tile ----
-      f32x4 y[4][2];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+          for (int part = 0; part < 2; ++part)
+            y[h][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                A[h], B[kt][part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, kUnitScale, 0, kUnitScale);
 #pragma unroll
-        for (int part = 0; part < 2; ++part)
-          y[q][part] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-              A[q], B[kt][part], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0, kUnitScale, 0, kUnitScale);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        // second E-W stage: X_0 = S02 + S13, X_1 = D02 - i D13,
-        // X_2 = S02 - S13, X_3 = D02 + i D13
-        const cf s02{y[0][0][i], y[0][1][i]}, s13{y[1][0][i], y[1][1][i]};
-        const cf d02{y[2][0][i], y[2][1][i]}, d13{y[3][0][i], y[3][1][i]};
-        const cf x[4] = {cadd(s02, s13), cf{d02.r + d13.i, d02.i - d13.r}, csub(s02, s13),
-                         cf{d02.r - d13.i, d02.i + d13.r}};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) tile[(e * 16 + n) * ROW + 4 * g + i] = cmul(x[e], tw[kt][i]);
+        for (int i = 0; i < 4; ++i) {
+          // X_0 = S02 + S13, X_2 = S02 - S13 (cp = 0); X_1 = D02 - i D13,
+          // X_3 = D02 + i D13 (cp = 1)
+          const cf u{y[0][0][i], y[0][1][i]}, v{y[1][0][i], y[1][1][i]};
+          const cf xa = cp == 0 ? cadd(u, v) : cf{u.r + v.i, u.i - v.r};
+          const cf xb = cp == 0 ? csub(u, v) : cf{u.r - v.i, u.i + v.r};
+          tile[(16 * kt + n) * ROW + 4 * g + i] = cmul(xa, tw[kt][i]);
+          tile[(32 + 16 * kt + n) * ROW + 4 * g + i] = cmul(xb, tw[kt][i]);
+        }
       }
       wave_lds_sync();
-      // ---- stage 2: 16-point DFT over a1 for (E-W beam es, k2 = 16 kt + ks) ----
+      // ---- stage 2: 16-point DFT over a1 for (E-W beam cp + 2 bs, k2s) ----
       cf x[16];
       {
-        const float4* src = reinterpret_cast<const float4*>(&tile[(es * 16 + ks) * ROW]);
+        const float4* src = reinterpret_cast<const float4*>(&tile[(bs * 32 + k2s) * ROW]);
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
           const float4 v = src[m];
@@ -465,7 +473,7 @@ __global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
       wave_lds_sync();
       dit<16>(x);
 #pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) acc[kt][k1] = cnorm_acc(x[k1], acc[kt][k1]);
+      for (int k1 = 0; k1 < 16; ++k1) acc[cp][k1] = cnorm_acc(x[k1], acc[cp][k1]);
     }
   };
 
@@ -489,12 +497,12 @@ __global__ __launch_bounds__(64) void k_mix256_fp8(MixArgs a) {
     }
   }
 
-  // ---- block end: beams A = 16 kt + ks + 32 k1 of E-W beam es, clamp, store ----
+  // ---- block end: beams A = k2s + 32 k1 of E-W beam cp + 2 bs, clamp, store ----
   float* lds_i = reinterpret_cast<float*>(lds_raw);
 #pragma unroll
-  for (int kt = 0; kt < 2; ++kt)
+  for (int cp = 0; cp < 2; ++cp)
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) lds_i[es * M + 16 * kt + ks + 32 * k1] = acc[kt][k1];
+    for (int k1 = 0; k1 < 16; ++k1) lds_i[(cp + 2 * bs) * M + k2s + 32 * k1] = acc[cp][k1];
   wave_lds_sync();
   const int keep = a.n_keep;
   const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
