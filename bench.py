@@ -303,7 +303,7 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
                    v=sg.volts(w, blk * 16, 16, chans=[c], pols=[p]), m_ew=w.m_ew, m_ns=w.m_ns,
                    index=(0, 0, 0), sel=sel[c])
     alg = w.n_time * w.n_chan * w.n_pol * w.frame_bytes + out.numel() * 4
-    # the FP8 matrix-core plan on the same voltages (exact int4 columns, three stacked e4m3 terms)
+    # the FP8 matrix-core plan on the same voltages (exact first-stage E-W sums, three stacked e4m3 terms)
     plan8 = bf.Plan(n_ew=w.n_ew, n_ns=w.n_ns, m_ew=w.m_ew, m_ns=w.m_ns, n_pol=w.n_pol, n_chan=w.n_chan,
                     block=w.block, ns_select=w.ns_select(), d_over_lambda=w.d_over_lambda(),
                     precision=bf.BF_PREC_FP8_MFMA)
@@ -311,8 +311,9 @@ def run_chime_mixed(dev, w, volts, fp32_ms: float, checks: OracleChecks) -> dict
     plan8.close()
     # per frame: 4 E-W columns x 2 beam tiles x (Re, Im) of v_mfma_scale_f32_16x16x128_f8f6f4
     mf8 = w.n_time * w.n_chan * w.n_pol * 4 * 2 * 2 * (16 * 16 * 128 * 2)
-    fp8_rec = {"precision": "fp8 (e4m3) mfma for stage 1 (exact int4 of each E-W column, three coefficient terms "
-                            "stacked along K = 128); E-W DFT, twiddle and 16-point stage 2 in fp32",
+    fp8_rec = {"precision": "fp8 (e4m3) mfma for stage 1 (exact first-stage E-W sums x0 +- x2, x1 +- x3, three "
+                            "coefficient terms stacked along K = 128); second E-W stage, twiddle and 16-point "
+                            "stage 2 in fp32",
                "kernel_ms": ms8, "antenna_samples_per_s": w.antenna_samples / (ms8 / 1e3),
                "speedup_vs_fp32": fp32_ms / ms8,
                "mfma_tflops": mf8 / (ms8 / 1e3) / 1e12, "mfma_frac_of_fp8_peak": mf8 / (ms8 / 1e3) / 1e12 / 5000.0}
