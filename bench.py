@@ -765,7 +765,7 @@ def _serve_saturated(srv, reqs) -> dict:
 
 
 def run_serving(dev, n_req: int = 5200, n_warm: int = 200, rate_hz: float = 200.0, n_sat: int = 1000,
-                writer_rate: float = 390625.0) -> dict:
+                writer_rate: float = 390625.0, blocks_per_tile: int = 32) -> dict:
     """Open-loop serving of tied-beam requests from a 1 GiB device voltage ring,
     with a writer appending voltages at ``writer_rate`` samples/s meanwhile
     (one sample every 2.56 us, a CHIME-like channelised sample rate)."""
@@ -777,7 +777,8 @@ def run_serving(dev, n_req: int = 5200, n_warm: int = 200, rate_hz: float = 200.
     w = sg.make_workload("c5")
     plan = bf.Plan(n_ew=4, n_ns=16, n_chan=w.n_chan, n_pol=1, block=16, d_over_lambda=w.d_over_lambda())
     budget = 16 << 30
-    srv = bf.Server(plan, ring_samples=w.n_time, hbm_budget=budget, blocks_per_tile=16, max_tiles_per_launch=8192)
+    srv = bf.Server(plan, ring_samples=w.n_time, hbm_budget=budget, blocks_per_tile=blocks_per_tile,
+                    max_tiles_per_launch=8192)
     plan.close()
     step = 4096
     for t0 in range(0, w.n_time, step):          # the writer fills the ring

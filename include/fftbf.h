@@ -343,7 +343,9 @@ bf_status bf_localize(const bf_plan *plan, const float *fft_intensity, int64_t n
  *
  * Requests are admitted against a fixed device-memory budget (outputs and
  * pointing tables live in one pool of hbm_budget bytes), cut into tiles
- * (channel x up to 64 pointings x blocks_per_tile blocks of 16 samples) and
+ * (channel x up to 64 pointings x blocks_per_tile blocks of 16 samples; each
+ * tile forms its FP64 interpolation weights once, so longer tiles amortise
+ * them: 32 blocks served the benchmark's request mix with the lowest p99) and
  * batched -- round robin over the active requests, at most
  * max_tiles_per_launch tiles and two launches in flight -- into launches of
  * a persistent tile worker on the server's own stream.  Requests that arrive

@@ -410,7 +410,7 @@ class Server:
     """
 
     def __init__(self, plan: Plan, ring_samples: int = 65536, hbm_budget: int = 16 << 30,
-                 blocks_per_tile: int = 16, max_tiles_per_launch: int = 8192):
+                 blocks_per_tile: int = 32, max_tiles_per_launch: int = 8192):
         h = C.c_void_p()
         check(lib().bf_server_create(plan.handle, ring_samples, hbm_budget, blocks_per_tile,
                                      max_tiles_per_launch, C.byref(h)), "bf_server_create")

@@ -76,7 +76,7 @@ struct Config {
   int64_t ring_samples = 65536;
   size_t pool_bytes = size_t(16) << 30;   // memory budget for outputs + pointing tables
   int32_t n_chan = 256, n_pol = 1, block = 16;
-  int32_t blocks_per_tile = 16;
+  int32_t blocks_per_tile = 32;
   int32_t max_tiles_per_launch = 8192;
   int32_t tiles_per_turn = 256;          // round-robin quantum per request per batch
   int32_t max_in_flight = 2;
