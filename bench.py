@@ -261,19 +261,20 @@ def _no_gc():
         gc.enable()
 
 
-def _time_launches(fn, n: int, warmup: int = 2, each: list = None, warm_ms: float = 100.0) -> float:
+def _time_launches(fn, n: int, warmup: int = 2, each: list = None, warm_ms: float = 500.0) -> float:
     """Average milliseconds of fn() (one launch on the current stream);
     with ``each`` the time of every launch is appended to it.  Warm-up runs
-    at least ``warmup`` launches and at least ``warm_ms`` of them (up to 200
+    at least ``warmup`` launches and at least ``warm_ms`` of them (up to 400
     launches), so that the clocks have left an idle state before the timed
-    launches (the host-side checks between legs leave the GPU idle)."""
+    launches (the host-side checks between legs leave the GPU idle; after
+    100 ms of warm-up a leg's five launches still fell from 5.6 to 4.6 ms)."""
     import torch
     t0 = time.perf_counter()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     done = warmup
-    while (time.perf_counter() - t0) * 1e3 < warm_ms and done < 200:
+    while (time.perf_counter() - t0) * 1e3 < warm_ms and done < 400:
         fn()
         done += 1
         if done % 8 == 0:
