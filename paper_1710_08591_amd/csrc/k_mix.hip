@@ -160,7 +160,8 @@ __device__ __forceinline__ half8 ew_sums_f16(const uint32_t* dw, int w) {
 // window is scaled per wavefront by a power of two so that its largest
 // weight lies in [1/2, 1), and the block sums are scaled back exactly.
 template <int PREC, bool WIN = false>
-__global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WIN ? 4 : PREC == kPrecFp16 ? 6 : 4)))
+void k_mix16(MixArgs a) {
   static_assert(!WIN || PREC == kPrecFp16, "windows run on the FP16 path");
   constexpr int P = Mix<PREC>::P;
   using op_t = typename Mix<PREC>::op_t;
@@ -201,7 +202,16 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
   const int pol_lo = (a.pol_iter == 1) ? pg : 0;
   const int pol_hi = (a.pol_iter == 1) ? pg + 1 : a.n_pol;
   const int keep = a.n_keep;
-  const int32_t* sel = a.sel ? a.sel + (int64_t)chan * keep : nullptr;
+  // the block-end gather: output idx = e keep + j (idx = lane, lane + 64; at
+  // most 4 x 32) reads the block sum of E-W beam e at N-S beam sel[j] (or j);
+  // the channel is the wavefront's, so the sources are fixed per lane
+  int gsrc[2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int idx = lane + 64 * it;
+    const int e = idx / keep, j = idx - e * keep;
+    gsrc[it] = idx < 4 * keep ? e * 32 + (a.sel ? a.sel[(int64_t)chan * keep + j] : j) : 0;
+  }
 
   // the window at the lane's N-S positions 8 (g & 1) + j, scaled by 2^-E with
   // 2^E the power of two just above the wavefront's largest |h|
@@ -229,6 +239,7 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
   }
   const bool im_lane = (g >> 1) != 0;         // this lane's component of the data operand
 
+#pragma unroll 1
   for (int64_t blk = blk0; blk < blk1; ++blk) {
     float ia[4][2];
 #pragma unroll
@@ -382,10 +393,9 @@ __global__ __launch_bounds__(64) void k_mix16(MixArgs a) {
     }
     __syncthreads();
     float* o = a.out + ((blk * a.n_chan + chan) * a.n_pg + pg) * 4 * keep;
-    for (int idx = lane; idx < 4 * keep; idx += 64) {
-      const int e = idx / keep, j = idx - e * keep;
-      o[idx] = lds_i[e * 32 + (sel ? sel[j] : j)];
-    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+      if (lane + 64 * it < 4 * keep) o[lane + 64 * it] = lds_i[gsrc[it]];
     __syncthreads();
   }
 }
