@@ -177,3 +177,21 @@ def test_regrid2d_c2_shape_sampled():
     plan.close()
     del fft_i, got
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("block", [4, 48])
+def test_ew8_fused_block_lengths(block):
+    """The one-launch padded-E-W kernel of the 4 x 256 lattice runs each
+    block twice (even, then odd E-W beams); blocks of 4 and 48 samples
+    (several blocks per channel, the frame prefetch crossing block and
+    polarisation boundaries) against the oracle."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=256, n_chan=2, n_pol=2, n_time=96, seed=block, n_src=2, snr=5.0)
+    v = sg.volts(w)
+    plan = bf.Plan(n_ew=4, n_ns=256, m_ew=8, n_chan=2, n_pol=2, block=block, d_over_lambda=w.d_over_lambda())
+    got = bf.beamform_fft(plan, torch.from_numpy(v).cuda()).cpu().numpy()
+    plan.close()
+    ref = orc.beamform_fft(v, 8, 512, block)
+    assert got.shape == ref.shape == (96 // block, 2, 2, 8, 512)
+    assert rel_err(got, ref) < TOL_FP32
