@@ -243,19 +243,40 @@ __device__ __forceinline__ void v16_fft_to_lds(const uint32_t (&dw)[kV16N], cons
   }
 }
 
-// Interpolation weight c_A(y) of one FFT beam, in FP64 (series summed term by
-// term with a unit-modulus recurrence).
+// Interpolation weight c_A(y) = (1/m) sum_{a<n} z^a, z = e^{2 pi i (A/m - y)},
+// of one FFT beam, in FP64.  For n a power of two the geometric series is the
+// product (1 + z)(1 + z^2)(1 + z^4)... of log2 n factors (z^2k by squaring),
+// which has no singular point; otherwise it is summed term by term with a
+// unit-modulus recurrence.
 __device__ __forceinline__ void interp_weight_d(int A, int m, int n, double y, double* wr_out, double* wi_out) {
   const double u = (double)A / (double)m - y;
   double s, co;
   sincospi(2.0 * u, &s, &co);
-  double wr = 1.0, wi = 0.0, ar = 0.0, ai = 0.0;
-  for (int a = 0; a < n; ++a) {
-    ar += wr;
-    ai += wi;
-    const double t = wr * co - wi * s;
-    wi = wr * s + wi * co;
-    wr = t;
+  double ar, ai;
+  if (n >= 2 && (n & (n - 1)) == 0) {
+    ar = 1.0 + co;
+    ai = s;
+    double zr = co, zi = s;
+    for (int k = 2; k < n; k <<= 1) {
+      const double t = zr * zr - zi * zi;
+      zi = 2.0 * zr * zi;
+      zr = t;
+      const double fr = 1.0 + zr;
+      const double q = ar * fr - ai * zi;
+      ai = ar * zi + ai * fr;
+      ar = q;
+    }
+  } else {
+    double wr = 1.0, wi = 0.0;
+    ar = 0.0;
+    ai = 0.0;
+    for (int a = 0; a < n; ++a) {
+      ar += wr;
+      ai += wi;
+      const double t = wr * co - wi * s;
+      wi = wr * s + wi * co;
+      wr = t;
+    }
   }
   *wr_out = ar / m;
   *wi_out = ai / m;
