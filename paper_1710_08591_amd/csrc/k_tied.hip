@@ -243,40 +243,42 @@ __device__ __forceinline__ void v16_fft_to_lds(const uint32_t (&dw)[kV16N], cons
   }
 }
 
+// (1/m) sum_{a<n} z^a for |z| = 1 and n a power of two, as the product
+// (1 + z)(1 + z^2)(1 + z^4)... of log2 n factors (z^2k by squaring): no
+// singular point, log2 n complex products instead of n terms.
+__device__ __forceinline__ void geom_pow2(double zr, double zi, int n, int m, double* wr_out, double* wi_out) {
+  double ar = 1.0 + zr, ai = zi;
+  for (int k = 2; k < n; k <<= 1) {
+    const double t = zr * zr - zi * zi;
+    zi = 2.0 * zr * zi;
+    zr = t;
+    const double fr = 1.0 + zr;
+    const double q = ar * fr - ai * zi;
+    ai = ar * zi + ai * fr;
+    ar = q;
+  }
+  *wr_out = ar / m;
+  *wi_out = ai / m;
+}
+
 // Interpolation weight c_A(y) = (1/m) sum_{a<n} z^a, z = e^{2 pi i (A/m - y)},
-// of one FFT beam, in FP64.  For n a power of two the geometric series is the
-// product (1 + z)(1 + z^2)(1 + z^4)... of log2 n factors (z^2k by squaring),
-// which has no singular point; otherwise it is summed term by term with a
-// unit-modulus recurrence.
+// of one FFT beam, in FP64: the product above for n a power of two, else the
+// series summed term by term with a unit-modulus recurrence.
 __device__ __forceinline__ void interp_weight_d(int A, int m, int n, double y, double* wr_out, double* wi_out) {
   const double u = (double)A / (double)m - y;
   double s, co;
   sincospi(2.0 * u, &s, &co);
-  double ar, ai;
   if (n >= 2 && (n & (n - 1)) == 0) {
-    ar = 1.0 + co;
-    ai = s;
-    double zr = co, zi = s;
-    for (int k = 2; k < n; k <<= 1) {
-      const double t = zr * zr - zi * zi;
-      zi = 2.0 * zr * zi;
-      zr = t;
-      const double fr = 1.0 + zr;
-      const double q = ar * fr - ai * zi;
-      ai = ar * zi + ai * fr;
-      ar = q;
-    }
-  } else {
-    double wr = 1.0, wi = 0.0;
-    ar = 0.0;
-    ai = 0.0;
-    for (int a = 0; a < n; ++a) {
-      ar += wr;
-      ai += wi;
-      const double t = wr * co - wi * s;
-      wi = wr * s + wi * co;
-      wr = t;
-    }
+    geom_pow2(co, s, n, m, wr_out, wi_out);
+    return;
+  }
+  double wr = 1.0, wi = 0.0, ar = 0.0, ai = 0.0;
+  for (int a = 0; a < n; ++a) {
+    ar += wr;
+    ai += wi;
+    const double t = wr * co - wi * s;
+    wi = wr * s + wi * co;
+    wr = t;
   }
   *wr_out = ar / m;
   *wi_out = ai / m;
@@ -288,16 +290,46 @@ struct TiedW {
   half8 rh[8], rl[8], ih[8], il[8];
 };
 
+// e^{i pi j / 16}, j < 4, and e^{i pi g / 4}, g < 4, as the nearest doubles
+__device__ __constant__ double kRot16[4][2] = {{1.0, 0.0},
+                                               {0.9807852804032304, 0.19509032201612825},
+                                               {0.9238795325112867, 0.3826834323650898},
+                                               {0.8314696123025452, 0.5555702330196022}};
+__device__ __constant__ double kRot4[4][2] = {{1.0, 0.0},
+                                              {0.7071067811865476, 0.7071067811865476},
+                                              {0.0, 1.0},
+                                              {-0.7071067811865476, 0.7071067811865476}};
+
 __device__ __forceinline__ void tied_weights(double y_ew, double y_ns, int g, TiedW& w) {
+  static_assert(kV16M == 32 && kV16N == 16, "the 4 x 16 lattice's beams");
+  // E-W: z_e = e^{2 pi i (e/4 - y)} = i^e b with b = e^{-2 pi i y} (one
+  // sine and cosine per pointing)
   double ewr[4], ewi[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) interp_weight_d(e, 4, 4, y_ew, &ewr[e], &ewi[e]);
-  // this lane's k rows hold beams 16 kb + 4 g + jj (jj < 4): N-S beams 16 h + 4 g + jj
+  {
+    double bs, bc;
+    sincospi(-2.0 * y_ew, &bs, &bc);
+    geom_pow2(bc, bs, 4, 4, &ewr[0], &ewi[0]);
+    geom_pow2(-bs, bc, 4, 4, &ewr[1], &ewi[1]);
+    geom_pow2(-bc, -bs, 4, 4, &ewr[2], &ewi[2]);
+    geom_pow2(bs, -bc, 4, 4, &ewr[3], &ewi[3]);
+  }
+  // N-S: this lane's k rows hold beams 16 kb + 4 g + jj (jj < 4), N-S beams
+  // A = 16 h + 4 g + jj, and z_A = e^{2 pi i (A/32 - y)} =
+  // (-1)^h e^{i pi g/4} e^{i pi jj/16} c with c = e^{-2 pi i y}
   double nsr[2][4], nsi[2][4];
+  {
+    double cs, cc;
+    sincospi(-2.0 * y_ns, &cs, &cc);
+    const double gr = kRot4[g][0], gi = kRot4[g][1];
+    const double dr = gr * cc - gi * cs, di = gr * cs + gi * cc;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) interp_weight_d(16 * h + 4 * g + jj, kV16M, kV16N, y_ns, &nsr[h][jj], &nsi[h][jj]);
+    for (int jj = 0; jj < 4; ++jj) {
+      const double rr = kRot16[jj][0], ri = kRot16[jj][1];
+      const double zr = rr * dr - ri * di, zi = rr * di + ri * dr;
+      geom_pow2(zr, zi, kV16N, kV16M, &nsr[0][jj], &nsi[0][jj]);
+      geom_pow2(-zr, -zi, kV16N, kV16M, &nsr[1][jj], &nsi[1][jj]);
+    }
+  }
   const double sc = (double)(1 << kV16Wscale);
 #pragma unroll
   for (int kb = 0; kb < 8; ++kb) {
