@@ -738,28 +738,13 @@ __global__ __launch_bounds__(256) void k_serve(const ServeTile* __restrict__ til
 // into three accumulators).  Lane (g, n) takes A = g (M/4) + kb at step kb,
 // so its beam reads walk contiguous memory (16-byte loads, two steps each)
 // and its weights sit in one LDS row.  The N-S weights of the tile's
-// pointings are generated once per workgroup in FP64 (closed form below) and
-// held in LDS as FP32; the E-W weights of the lane's four pointings (rows
+// pointings are generated once per workgroup in FP64 (the product form of
+// interp_weight_d) and held in LDS as FP32; the E-W weights of the lane's four pointings (rows
 // 4 g + i) and E-W beam (n mod 4) in registers.  The E-W sum is a sum over
 // the four lanes of a column quad; |B_p|^2 is summed over the quad's samples
 // by two more cross-lane adds.  Each wavefront owns whole output units
 // (blocks of the intensity, or quads of samples for complex output).
 constexpr int kTmfP = 16;                  // pointings per workgroup
-
-// c_A(y) = (1/M) sum_{a<n} e^{+i 2 pi a u}, u = A/M - y, in closed form:
-// e^{i pi (n-1) u} sin(n pi u) / (M sin(pi u)), with the limit n / M where
-// sin(pi u) = 0.  Numerator and denominator are taken from the same u, so
-// the ratio stays accurate as u approaches an integer.
-__device__ __forceinline__ void interp_weight_closed(int A, int m, int n, double y, double* wr, double* wi) {
-  const double u = (double)A / (double)m - y;
-  double s1, c1, sn, cn, sp, cp;
-  sincospi(u, &s1, &c1);
-  sincospi((double)n * u, &sn, &cn);
-  sincospi((double)(n - 1) * u, &sp, &cp);
-  const double amp = fabs(s1) > 1e-300 ? sn / (s1 * (double)m) : (double)n / (double)m * (c1 > 0.0 ? 1.0 : ((n - 1) & 1 ? -1.0 : 1.0));
-  *wr = amp * cp;
-  *wi = amp * sp;
-}
 
 template <int M>
 __global__ __launch_bounds__(256) void k_tied_mf(TiedArgs a) {
@@ -779,7 +764,7 @@ __global__ __launch_bounds__(256) void k_tied_mf(TiedArgs a) {
     const int pl = i / M, A = i - pl * M;
     const int p = min(ptile * kTmfP + pl, a.n_point - 1);
     double wr, wi;
-    interp_weight_closed(A, M, a.n_ns, dl_ns * a.dircos[2 * p + 1], &wr, &wi);
+    interp_weight_d(A, M, a.n_ns, dl_ns * a.dircos[2 * p + 1], &wr, &wi);
     const int gg = A / KS, kb = A - gg * KS;
     float* row = lds_w + (pl * 4 + gg) * ROW;
     row[2 * kb] = (float)wr;
