@@ -266,8 +266,9 @@ def _time_launches(fn, n: int, warmup: int = 2, each: list = None, warm_ms: floa
     with ``each`` the time of every launch is appended to it.  Warm-up runs
     at least ``warmup`` launches and at least ``warm_ms`` of them (up to 400
     launches), so that the clocks have left an idle state before the timed
-    launches (the host-side checks between legs leave the GPU idle; after
-    100 ms of warm-up a leg's five launches still fell from 5.6 to 4.6 ms)."""
+    launches (the host-side checks between legs leave the GPU idle), and the
+    first timed launch is queued behind two more, not after a synchronisation
+    (after one, a 14 ms launch read 17 ms)."""
     import torch
     t0 = time.perf_counter()
     for _ in range(warmup):
@@ -279,10 +280,13 @@ def _time_launches(fn, n: int, warmup: int = 2, each: list = None, warm_ms: floa
         done += 1
         if done % 8 == 0:
             torch.cuda.synchronize()
-    torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
     with _no_gc():
+        # two more launches queued ahead of the first event, so that the GPU
+        # does not idle (and lower its clock) between warm-up and timing
+        fn()
+        fn()
         ev[0].record(s)
         for i in range(n):
             fn()

@@ -475,12 +475,13 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
 // takes column k2 = 2 m + h of half h.  The pass-1 tangent values and the
 // pass-2 multipliers live in one LDS copy per workgroup (its four waves
 // share it), not in registers, and the next frame's voltages are loaded
-// during the second half only: 128 registers and about 10 KB of LDS per
+// during the second half only: about 125 registers and 10 KB of LDS per
 // wavefront, so four wavefronts fit per SIMD (two for the kernel above).
-// Unwindowed intensities; the window, gain and complex-output variants of
-// this lattice take the kernel above.  k_fft32_ew8 is the same kernel for
-// an E-W axis zero-padded to 8 beams: each wavefront runs its block twice,
-// for the even and then the odd E-W beams, so one launch writes all eight.
+// Intensities: k_fft32_h unwindowed, k_fft32_hw with a real window (three
+// wavefronts per SIMD); the gain and complex-output variants of this lattice
+// take the kernel above.  k_fft32_ew8 is the unwindowed kernel for an E-W
+// axis zero-padded to 8 beams: each wavefront runs its block twice, for the
+// even and then the odd E-W beams, so one launch writes all eight.
 constexpr int kHWpg = 4;                 // wavefronts per workgroup
 constexpr int kHRow = 44;                // LDS floats per (half, a1) row: 16 tangents, 25 multipliers, pad
 
@@ -517,8 +518,12 @@ template <bool B> struct BoolC {
 // reading its voltages a second time.  The odd pass forms four dot products
 // per position instead of two and keeps three values in scratch memory
 // across its frame loop (three scratch accesses per frame).
-template <bool EW8>
+// WIN: real per-antenna weights h (Sec. "Controlling beam shape with
+// windowing"), applied to the decoded nibbles before the E-W DFT as in the
+// kernel above (WindowLane), from one LDS copy of the window per workgroup.
+template <bool EW8, bool WIN = false>
 __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
+  static_assert(!(EW8 && WIN), "the windowed odd E-W beams take the kernel above");
   constexpr int N = 256, G = 16, L = 16, M = 512;
   constexpr int NSL = dit_slots(G);
   constexpr int YS = L + 1;
@@ -531,6 +536,7 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
   __shared__ cf lds_c16[G];                                           // whole twiddle of column k2 = 16
   __shared__ int4 lds_w8[EW8 ? 4 : 1];                                // odd E-W beams' dot8 weights
+  __shared__ __attribute__((aligned(16))) float lds_h[WIN ? N * 4 : 1];   // the window [a_ns][a_ew]
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -554,6 +560,9 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
     const float2 w = p.tw[threadIdx.x * 32 + 16];
     lds_c16[threadIdx.x] = cf{w.x, w.y};
   }
+  if constexpr (WIN) {
+    for (int i = threadIdx.x; i < N * 4; i += 64 * kHWpg) lds_h[i] = p.taper[i];
+  }
   __syncthreads();
   const int64_t task = (int64_t)blockIdx.x * kHWpg + wave;
   if (task >= p.n_wg) return;
@@ -572,7 +581,9 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   auto pass = [&](auto odd_c) {
     constexpr bool ODD = decltype(odd_c)::value;
     int wre = 0, wim = 0;
-    if constexpr (!ODD) ew_weights(e1, wre, wim);
+    WindowLane wl{};
+    if constexpr (WIN) wl = window_lane(e1);
+    else if constexpr (!ODD) ew_weights(e1, wre, wim);
 
     float acc[2][G];
 #pragma unroll
@@ -600,6 +611,18 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
             const float pr = (float)sdot8((int)b[j], wpr), pim = (float)sdot8((int)b[j], wpi);
             const float qr = (float)sdot8((int)b[j], wqr), qi = (float)sdot8((int)b[j], wqi);
             x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pim)};
+          }
+        } else if constexpr (WIN) {
+#pragma unroll
+          for (int j = 0; j < L; ++j) {
+            const uint32_t d = b[j];
+            const float4 h = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 4]);
+            const float h2 = wl.s * h.z, h3 = wl.s * h.w;
+            const float pr = fmaf(h2, nib(d, 20), h.x * nib(d, 4));
+            const float pim = fmaf(h2, nib(d, 16), h.x * nib(d, 0));
+            const float qr = fmaf(h3, nib(d, wl.ou + 16), h.y * nib(d, wl.ou));
+            const float qi = fmaf(h3, nib(d, wl.ov + 16), h.y * nib(d, wl.ov));
+            x[j] = cf{fmaf(wl.tr, qr, pr), fmaf(wl.ti, qi, pim)};
           }
         } else {
 #pragma unroll
@@ -694,6 +717,12 @@ __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4)))
   fft32_h_run<true>(p);
 }
 
+// the window's LDS copy (4 KB) leaves room for three workgroups of four
+// wavefronts per CU, so the registers may take three wavefronts per SIMD
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_hw(Fft32Args p) {
+  fft32_h_run<false, true>(p);
+}
+
 template <int N, int G, int T, int FOLD = 1>
 void launch_nt(const Fft32Args& a, bool cplx, hipStream_t s) {
   constexpr int W = fft32_wpg<N, G, T, FOLD>();
@@ -735,6 +764,11 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
       const dim3 grid((unsigned)((a.n_wg + kHWpg - 1) / kHWpg)), threads(64 * kHWpg);
       if (a.ew_rows == 8) hipLaunchKernelGGL(k_fft32_ew8, grid, threads, 0, s, a);   // even and odd E-W beams
       else hipLaunchKernelGGL(k_fft32_h, grid, threads, 0, s, a);
+      return hipGetLastError();
+    }
+    if (taper == 1 && !cplx) {       // windowed 4 x 256 intensities (even E-W beams when padded)
+      const dim3 grid((unsigned)((a.n_wg + kHWpg - 1) / kHWpg)), threads(64 * kHWpg);
+      hipLaunchKernelGGL(k_fft32_hw, grid, threads, 0, s, a);
       return hipGetLastError();
     }
   }
