@@ -477,9 +477,9 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
 // share it), not in registers, and the next frame's voltages are loaded
 // during the second half only: about 125 registers and 10 KB of LDS per
 // wavefront, so four wavefronts fit per SIMD (two for the kernel above).
-// Intensities: k_fft32_h unwindowed, k_fft32_hw with a real window (three
-// wavefronts per SIMD); the gain and complex-output variants of this lattice
-// take the kernel above.  k_fft32_ew8 is the unwindowed kernel for an E-W
+// Intensities: k_fft32_h unwindowed, k_fft32_hw with a real window and
+// k_fft32_hg with complex gains (three wavefronts per SIMD); the
+// complex-output variants of this lattice take the kernel above.  k_fft32_ew8 is the unwindowed kernel for an E-W
 // axis zero-padded to 8 beams: each wavefront runs its block twice, for the
 // even and then the odd E-W beams, so one launch writes all eight.
 constexpr int kHWpg = 4;                 // wavefronts per workgroup
@@ -518,12 +518,14 @@ template <bool B> struct BoolC {
 // reading its voltages a second time.  The odd pass forms four dot products
 // per position instead of two and keeps three values in scratch memory
 // across its frame loop (three scratch accesses per frame).
-// WIN: real per-antenna weights h (Sec. "Controlling beam shape with
-// windowing"), applied to the decoded nibbles before the E-W DFT as in the
-// kernel above (WindowLane), from one LDS copy of the window per workgroup.
-template <bool EW8, bool WIN = false>
+// TAPER 1: real per-antenna weights h (Sec. "Controlling beam shape with
+// windowing"); 2: complex per-antenna gains g (or the real weights, times
+// W_8^{a_ew} when twisting for the odd beams of a padded E-W axis).  Both are
+// applied to the decoded nibbles before the E-W DFT as in the kernel above
+// (WindowLane), from one LDS copy of the factors per workgroup.
+template <bool EW8, int TAPER = 0>
 __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
-  static_assert(!(EW8 && WIN), "the windowed odd E-W beams take the kernel above");
+  static_assert(!(EW8 && TAPER), "one-launch padded E-W beams are unwindowed");
   constexpr int N = 256, G = 16, L = 16, M = 512;
   constexpr int NSL = dit_slots(G);
   constexpr int YS = L + 1;
@@ -536,7 +538,8 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
   __shared__ cf lds_c16[G];                                           // whole twiddle of column k2 = 16
   __shared__ int4 lds_w8[EW8 ? 4 : 1];                                // odd E-W beams' dot8 weights
-  __shared__ __attribute__((aligned(16))) float lds_h[WIN ? N * 4 : 1];   // the window [a_ns][a_ew]
+  // the window [a_ns][a_ew] (TAPER 1) or the complex factors (TAPER 2)
+  __shared__ __attribute__((aligned(16))) float lds_h[TAPER == 2 ? N * 8 : TAPER == 1 ? N * 4 : 1];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -560,8 +563,30 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
     const float2 w = p.tw[threadIdx.x * 32 + 16];
     lds_c16[threadIdx.x] = cf{w.x, w.y};
   }
-  if constexpr (WIN) {
+  if constexpr (TAPER == 1) {
     for (int i = threadIdx.x; i < N * 4; i += 64 * kHWpg) lds_h[i] = p.taper[i];
+  } else if constexpr (TAPER == 2) {
+    // per antenna (a_ns, q): the real weight or the complex gain, times W_8^q when twisting
+    constexpr float kS = 0.70710678118654752f;
+    for (int i = threadIdx.x; i < N * 4; i += 64 * kHWpg) {
+      float gr = 1.f, gi = 0.f;
+      if (p.gain_src == 2) {
+        gr = p.taper[2 * i];
+        gi = p.taper[2 * i + 1];
+      } else if (p.gain_src == 1) {
+        gr = p.taper[i];
+      }
+      if (p.twist) {
+        const int q = i & 3;
+        const float wr = q == 0 ? 1.f : q == 1 ? kS : q == 2 ? 0.f : -kS;
+        const float wi = q == 0 ? 0.f : q == 1 ? -kS : q == 2 ? -1.f : -kS;
+        const float tr = gr * wr - gi * wi;
+        gi = gr * wi + gi * wr;
+        gr = tr;
+      }
+      lds_h[2 * i] = gr;
+      lds_h[2 * i + 1] = gi;
+    }
   }
   __syncthreads();
   const int64_t task = (int64_t)blockIdx.x * kHWpg + wave;
@@ -582,7 +607,7 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
     constexpr bool ODD = decltype(odd_c)::value;
     int wre = 0, wim = 0;
     WindowLane wl{};
-    if constexpr (WIN) wl = window_lane(e1);
+    if constexpr (TAPER != 0) wl = window_lane(e1);
     else if constexpr (!ODD) ew_weights(e1, wre, wim);
 
     float acc[2][G];
@@ -612,7 +637,26 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
             const float qr = (float)sdot8((int)b[j], wqr), qi = (float)sdot8((int)b[j], wqi);
             x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pim)};
           }
-        } else if constexpr (WIN) {
+        } else if constexpr (TAPER == 2) {
+#pragma unroll
+          for (int j = 0; j < L; ++j) {
+            // w_q = g_q z_q, split as for real weights (WindowLane)
+            const uint32_t d = b[j];
+            const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
+            const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
+            const float s2r = wl.s * g23.x, s2i = wl.s * g23.y;     // s g2
+            const float r1i = wl.r * g01.w;                          // r g1i
+            const float s3r = wl.s * g23.z;                          // s g3r (s r g3i = -g3i)
+            const float xr0 = nib(d, 4), xi0 = nib(d, 0), xr2 = nib(d, 20), xi2 = nib(d, 16);
+            const float u1 = nib(d, wl.ou), v1 = nib(d, wl.ov);
+            const float u3 = nib(d, wl.ou + 16), v3 = nib(d, wl.ov + 16);
+            const float pr = fmaf(-s2i, xi2, fmaf(s2r, xr2, fmaf(-g01.y, xi0, g01.x * xr0)));
+            const float pim = fmaf(s2i, xr2, fmaf(s2r, xi2, fmaf(g01.y, xr0, g01.x * xi0)));
+            const float qr = fmaf(-g23.w, v3, fmaf(s3r, u3, fmaf(r1i, v1, g01.z * u1)));
+            const float qi = fmaf(g23.w, u3, fmaf(s3r, v3, fmaf(-r1i, u1, g01.z * v1)));
+            x[j] = cf{fmaf(wl.tr, qr, pr), fmaf(wl.ti, qi, pim)};
+          }
+        } else if constexpr (TAPER == 1) {
 #pragma unroll
           for (int j = 0; j < L; ++j) {
             const uint32_t d = b[j];
@@ -720,7 +764,12 @@ __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4)))
 // the window's LDS copy (4 KB) leaves room for three workgroups of four
 // wavefronts per CU, so the registers may take three wavefronts per SIMD
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_hw(Fft32Args p) {
-  fft32_h_run<false, true>(p);
+  fft32_h_run<false, 1>(p);
+}
+
+// complex gains (8 KB of factors per workgroup): three workgroups per CU
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_hg(Fft32Args p) {
+  fft32_h_run<false, 2>(p);
 }
 
 template <int N, int G, int T, int FOLD = 1>
@@ -766,9 +815,10 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
       else hipLaunchKernelGGL(k_fft32_h, grid, threads, 0, s, a);
       return hipGetLastError();
     }
-    if (taper == 1 && !cplx) {       // windowed 4 x 256 intensities (even E-W beams when padded)
+    if ((taper == 1 || taper == 2) && !cplx) {   // windowed or gain-weighted 4 x 256 intensities
       const dim3 grid((unsigned)((a.n_wg + kHWpg - 1) / kHWpg)), threads(64 * kHWpg);
-      hipLaunchKernelGGL(k_fft32_hw, grid, threads, 0, s, a);
+      if (taper == 1) hipLaunchKernelGGL(k_fft32_hw, grid, threads, 0, s, a);
+      else hipLaunchKernelGGL(k_fft32_hg, grid, threads, 0, s, a);
       return hipGetLastError();
     }
   }

@@ -23,7 +23,8 @@ def _plan(bf, w, m_ew=8, pol_sum=False, sel=None):
                    ns_select=sel, d_over_lambda=w.d_over_lambda())
 
 
-@pytest.mark.parametrize("n_ns,window", [(16, None), (64, "real"), (256, None), (128, "gains")])
+@pytest.mark.parametrize("n_ns,window", [(16, None), (64, "real"), (256, None), (128, "gains"), (256, "real"),
+                                          (256, "gains")])
 def test_ew8_beams_parity(n_ns, window):
     torch = _torch()
     import paper_1710_08591_amd as bf
