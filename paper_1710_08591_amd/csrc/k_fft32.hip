@@ -479,9 +479,10 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
 // wavefront, so four wavefronts fit per SIMD (two for the kernel above).
 // Intensities: k_fft32_h unwindowed, k_fft32_hw with a real window and
 // k_fft32_hg with complex gains (three wavefronts per SIMD); the
-// complex-output variants of this lattice take the kernel above.  k_fft32_ew8 is the unwindowed kernel for an E-W
-// axis zero-padded to 8 beams: each wavefront runs its block twice, for the
-// even and then the odd E-W beams, so one launch writes all eight.
+// complex-output variants of this lattice take the kernel above.
+// k_fft32_ew8 is the unwindowed kernel for an E-W axis zero-padded to 8
+// beams (the N-S transform on the four E-W antenna columns, then the
+// padded E-W transform per N-S beam; below).
 constexpr int kHWpg = 4;                 // wavefronts per workgroup
 constexpr int kHRow = 44;                // LDS floats per (half, a1) row: 16 tangents, 25 multipliers, pad
 
@@ -508,24 +509,13 @@ struct HalfTw {
   }
 };
 
-template <bool B> struct BoolC {
-  static constexpr bool value = B;
-};
-
-// EW8: the E-W axis zero-padded to 8 beams in one launch.  After the even
-// beams (the 4-point DFT, rows 2e) of a block, the wavefront runs the block
-// again for the odd beams (rows 2e + 1: the 4-point DFT of x_a W_8^{a_ew}),
-// reading its voltages a second time.  The odd pass forms four dot products
-// per position instead of two and keeps three values in scratch memory
-// across its frame loop (three scratch accesses per frame).
 // TAPER 1: real per-antenna weights h (Sec. "Controlling beam shape with
 // windowing"); 2: complex per-antenna gains g (or the real weights, times
 // W_8^{a_ew} when twisting for the odd beams of a padded E-W axis).  Both are
 // applied to the decoded nibbles before the E-W DFT as in the kernel above
 // (WindowLane), from one LDS copy of the factors per workgroup.
-template <bool EW8, int TAPER = 0>
+template <int TAPER = 0>
 __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
-  static_assert(!(EW8 && TAPER), "one-launch padded E-W beams are unwindowed");
   constexpr int N = 256, G = 16, L = 16, M = 512;
   constexpr int NSL = dit_slots(G);
   constexpr int YS = L + 1;
@@ -537,7 +527,6 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   // put the 16 rows a lane group reads on different bank groups
   __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
   __shared__ cf lds_c16[G];                                           // whole twiddle of column k2 = 16
-  __shared__ int4 lds_w8[EW8 ? 4 : 1];                                // odd E-W beams' dot8 weights
   // the window [a_ns][a_ew] (TAPER 1) or the complex factors (TAPER 2)
   __shared__ __attribute__((aligned(16))) float lds_h[TAPER == 2 ? N * 8 : TAPER == 1 ? N * 4 : 1];
 
@@ -545,11 +534,6 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cf* const lds_y = lds_tiles + wave * 64 * YS;
   const int e1 = lane >> 4, a1 = lane & 15;
-  if (EW8 && threadIdx.x < 4) {
-    int4 w;
-    ew8_odd_weights((int)threadIdx.x, w.x, w.y, w.z, w.w);
-    lds_w8[threadIdx.x] = w;
-  }
 
   for (int i = threadIdx.x; i < 2 * G * L; i += 64 * kHWpg) {
     const int h = i / (G * L), r = i % (G * L), aa = r / L, m = r % L;
@@ -603,12 +587,11 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   const int n_valid = (int)((p.n_time - t_base) < p.block ? (p.n_time - t_base) : p.block);
   cf* const row = &lds_y[lane * YS];
 
-  auto pass = [&](auto odd_c) {
-    constexpr bool ODD = decltype(odd_c)::value;
+  {
     int wre = 0, wim = 0;
     WindowLane wl{};
     if constexpr (TAPER != 0) wl = window_lane(e1);
-    else if constexpr (!ODD) ew_weights(e1, wre, wim);
+    else ew_weights(e1, wre, wim);
 
     float acc[2][G];
 #pragma unroll
@@ -625,19 +608,7 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
       for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + a1 + G * j);
       for (int it = 0; it < n_it; ++it) {
         cf x[L];
-        if constexpr (ODD) {
-          // P + Q / sqrt(2) (the weights are read from the LDS per frame:
-          // held across the loop they would cost two more registers)
-          constexpr float kS = 0.70710678118654752f;
-          const int4 w8 = lds_w8[e1];
-          const int wpr = w8.x, wpi = w8.y, wqr = w8.z, wqi = w8.w;
-#pragma unroll
-          for (int j = 0; j < L; ++j) {
-            const float pr = (float)sdot8((int)b[j], wpr), pim = (float)sdot8((int)b[j], wpi);
-            const float qr = (float)sdot8((int)b[j], wqr), qi = (float)sdot8((int)b[j], wqi);
-            x[j] = cf{fmaf(kS, qr, pr), fmaf(kS, qi, pim)};
-          }
-        } else if constexpr (TAPER == 2) {
+        if constexpr (TAPER == 2) {
 #pragma unroll
           for (int j = 0; j < L; ++j) {
             // w_q = g_q z_q, split as for real weights (WindowLane)
@@ -738,38 +709,214 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
     float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int r = EW8 ? 2 * e + (ODD ? 1 : 0) : e * p.ew_mul + p.ew_off;
+      const int r = e * p.ew_mul + p.ew_off;
       for (int j = lane; j < keep; j += 64) {
         const int A = sel ? sel[j] : j;
         o[r * keep + j] = lds_i[ebase(e) + A] * p.norm;
       }
     }
-  };
-
-  pass(BoolC<false>{});
-  if constexpr (EW8) {
-    wave_lds_sync();          // the block-end reads of the tile before the odd pass writes it
-    pass(BoolC<true>{});
   }
 }
 
-__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_h(Fft32Args p) {
-  fft32_h_run<false>(p);
+// |B|^2 of the eight beams of the zero-padded 8-point E-W transform of one
+// N-S beam, from its four E-W antenna columns z_q, added to acc[E]: the even
+// beams 2e are the 4-point DFT of z_q, the odd beams 2e + 1 that of
+// w_q = z_q W_8^q, with w_0 = z_0, w_2 = -i z_2 and the factor 1/sqrt(2) of
+// w_1 and w_3 applied in the last fused multiply-adds.
+__device__ __forceinline__ void ew8_beams_acc(const cf* z, float* acc) {
+  constexpr float kS = 0.70710678118654752f;
+  const cf s02 = cadd(z[0], z[2]), d02 = csub(z[0], z[2]), s13 = cadd(z[1], z[3]), d13 = csub(z[1], z[3]);
+  acc[0] = cnorm_acc(cadd(s02, s13), acc[0]);
+  acc[4] = cnorm_acc(csub(s02, s13), acc[4]);
+  acc[2] = cnorm_acc(cf{d02.r + d13.i, d02.i - d13.r}, acc[2]);   // d02 - i d13
+  acc[6] = cnorm_acc(cf{d02.r - d13.i, d02.i + d13.r}, acc[6]);   // d02 + i d13
+  const cf S02 = cf{z[0].r + z[2].i, z[0].i - z[2].r};            // w_0 + w_2
+  const cf D02 = cf{z[0].r - z[2].i, z[0].i + z[2].r};            // w_0 - w_2
+  // sqrt(2) w_1 = z_1 (1 - i), sqrt(2) w_3 = -z_3 (1 + i), so their sum and
+  // difference come from s13 and d13
+  const cf S13 = cf{d13.r + s13.i, d13.i - s13.r};                 // sqrt(2) (w_1 + w_3)
+  const cf D13 = cf{s13.r + d13.i, s13.i - d13.r};                 // sqrt(2) (w_1 - w_3)
+  acc[1] = cnorm_acc(cf{fmaf(kS, S13.r, S02.r), fmaf(kS, S13.i, S02.i)}, acc[1]);
+  acc[5] = cnorm_acc(cf{fmaf(-kS, S13.r, S02.r), fmaf(-kS, S13.i, S02.i)}, acc[5]);
+  acc[3] = cnorm_acc(cf{fmaf(kS, D13.i, D02.r), fmaf(-kS, D13.r, D02.i)}, acc[3]);   // D02 - i D13
+  acc[7] = cnorm_acc(cf{fmaf(-kS, D13.i, D02.r), fmaf(kS, D13.r, D02.i)}, acc[7]);   // D02 + i D13
 }
 
-__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_ew8(Fft32Args p) {
-  fft32_h_run<true>(p);
+// The 4 x 256 intensities with the E-W axis zero-padded to 8 beams, N-S
+// transform first.  The transforms along the two axes commute, so the
+// zero-padded N-S transform runs on the four E-W antenna columns (lane
+// (q, a1) of pass 1 takes the nibbles of antenna q instead of an E-W beam's
+// dot products): the same work as the unpadded step.  After pass 2 the four
+// columns of each N-S beam meet in one lane through the wavefront's LDS
+// tile, which forms all eight E-W beams and their |B|^2: lane (g, m) holds
+// the N-S beams A = (2 m + h) + 32 (4 g + r), r < 4, of half h.  The block
+// sums leave in two rounds, the even E-W beams and then the odd ones, so
+// that each round fits the tile.
+__device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
+  constexpr int N = 256, G = 16, L = 16, M = 512;
+  constexpr int NSL = dit_slots(G);
+  constexpr int YS = L + 1;
+  static_assert(L + NSL <= kHRow && kHRow % 4 == 0 && (kHRow / 4) % 2 == 1, "table rows");
+  static_assert((4 * M + 34) * 4 <= 64 * YS * 8, "block-end sums of four E-W rows must fit the tile");
+  static_assert(G * 4 * 16 <= 64 * YS, "the E-W transposition must fit the tile");
+  __shared__ cf lds_tiles[kHWpg * 64 * YS];
+  __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
+  __shared__ cf lds_c16[G];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  cf* const lds_y = lds_tiles + wave * 64 * YS;
+  const int e1 = lane >> 4, a1 = lane & 15;      // pass 1 and 2: E-W antenna column e1
+
+  for (int i = threadIdx.x; i < 2 * G * L; i += 64 * kHWpg) {
+    const int h = i / (G * L), r = i % (G * L), aa = r / L, m = r % L;
+    lds_tab[h][aa][m] = p.tw[aa * 32 + 2 * m + h].x;
+  }
+  for (int i = threadIdx.x; i < 32 * NSL; i += 64 * kHWpg) {
+    const int k2 = i / NSL;
+    lds_tab[k2 & 1][k2 >> 1][L + i % NSL] = p.mult[i];
+  }
+  if (threadIdx.x < G) {
+    const float2 w = p.tw[threadIdx.x * 32 + 16];
+    lds_c16[threadIdx.x] = cf{w.x, w.y};
+  }
+  __syncthreads();
+  const int64_t task = (int64_t)blockIdx.x * kHWpg + wave;
+  if (task >= p.n_wg) return;
+  int wg = (int)task;
+  const int pg = wg % p.n_pg;
+  wg /= p.n_pg;
+  const int chan = wg % p.n_chan;
+  const int blk = wg / p.n_chan;
+
+  const int64_t t_base = (int64_t)blk * p.block;
+  const int n_it = p.block;
+  const int64_t frame_stride = (int64_t)(p.chan_stride ? p.chan_stride : p.n_chan) * p.n_pol * N;
+  const int n_valid = (int)((p.n_time - t_base) < p.block ? (p.n_time - t_base) : p.block);
+  cf* const row = &lds_y[lane * YS];
+  const int sh_re = 8 * e1 + 4, sh_im = 8 * e1;    // antenna e1: real part high nibble, imaginary low
+
+  float acc[2][4][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[h][r][e] = 0.f;
+
+  for (int pi = 0; pi < p.pol_iter; ++pi) {
+    const int pol = (p.pol_iter == 1) ? pg : pi;
+    const uint32_t* q = p.volts + ((int64_t)chan * p.n_pol + pol) * N + t_base * frame_stride;
+    uint32_t b[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + a1 + G * j);
+    for (int it = 0; it < n_it; ++it) {
+      cf x[L];
+#pragma unroll
+      for (int j = 0; j < L; ++j) x[j] = cf{nib(b[j], sh_re), nib(b[j], sh_im)};
+      cf xo[L];
+      padded_odd_t<L>(x, xo);
+      dit<L>(x);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const cf* y = h ? xo : x;
+        if (h == 1) {
+          q = (it + 1 >= n_it) ? p.volts : ((it + 1 < n_valid) ? q + frame_stride : q);
+#pragma unroll
+          for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + a1 + G * j);
+        }
+        {
+          float t1[L];
+          const float4* tp = reinterpret_cast<const float4*>(&lds_tab[h][a1][0]);
+#pragma unroll
+          for (int k = 0; k < L / 4; ++k) {
+            const float4 v = tp[k];
+            t1[4 * k] = v.x;
+            t1[4 * k + 1] = v.y;
+            t1[4 * k + 2] = v.z;
+            t1[4 * k + 3] = v.w;
+          }
+          if (h == 0) HalfTw<0, 0>::run(y, t1, lds_c16[a1], row);
+          else HalfTw<1, 0>::run(y, t1, cf{}, row);
+        }
+        wave_lds_sync();
+        cf z[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) z[j] = lds_y[(e1 * 16 + j) * YS + a1];
+        wave_lds_sync();
+        {
+          float mu[28];
+          const float4* mp = reinterpret_cast<const float4*>(&lds_tab[h][a1][L]);
+#pragma unroll
+          for (int k = 0; k < 7; ++k) {
+            const float4 v = mp[k];
+            mu[4 * k] = v.x;
+            mu[4 * k + 1] = v.y;
+            mu[4 * k + 2] = v.z;
+            mu[4 * k + 3] = v.w;
+          }
+          dit_rs<G>(z, mu);
+        }
+        // z[k1]: N-S beam (2 a1 + h) + 32 k1 of column e1, to slot (k1, e1, a1)
+#pragma unroll
+        for (int k1 = 0; k1 < G; ++k1) lds_y[k1 * 64 + lane] = z[k1];
+        wave_lds_sync();
+        // lane (g, m) = (e1, a1) takes k1 = 4 g + r of every column
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cf zq[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) zq[c] = lds_y[(4 * e1 + r) * 64 + c * 16 + a1];
+          ew8_beams_acc(zq, acc[h][r]);
+        }
+        wave_lds_sync();
+      }
+    }
+  }
+
+  // ---- block end: the kept beams of the channel, even E-W rows, then odd ----
+  float* lds_i = reinterpret_cast<float*>(lds_y);
+  auto ebase = [](int e) { return e * M + (e & 1) + 32 * (e >> 1); };
+  const int keep = p.n_keep;
+  const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
+  float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * 8 * keep;
+#pragma unroll
+  for (int odd = 0; odd < 2; ++odd) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) lds_i[ebase(e) + 2 * a1 + h + 32 * (4 * e1 + r)] = acc[h][r][2 * e + odd];
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      for (int j = lane; j < keep; j += 64) {
+        const int A = sel ? sel[j] : j;
+        o[(2 * e + odd) * keep + j] = lds_i[ebase(e) + A] * p.norm;
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ew8(Fft32Args p) {
+  fft32_ew8_run(p);
+}
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_h(Fft32Args p) {
+  fft32_h_run<0>(p);
 }
 
 // the window's LDS copy (4 KB) leaves room for three workgroups of four
 // wavefronts per CU, so the registers may take three wavefronts per SIMD
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_hw(Fft32Args p) {
-  fft32_h_run<false, 1>(p);
+  fft32_h_run<1>(p);
 }
 
 // complex gains (8 KB of factors per workgroup): three workgroups per CU
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_hg(Fft32Args p) {
-  fft32_h_run<false, 2>(p);
+  fft32_h_run<2>(p);
 }
 
 template <int N, int G, int T, int FOLD = 1>
