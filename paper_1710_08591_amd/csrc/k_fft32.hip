@@ -751,7 +751,10 @@ __device__ __forceinline__ void ew8_beams_acc(const cf* z, float* acc) {
 // tile, which forms all eight E-W beams and their |B|^2: lane (g, m) holds
 // the N-S beams A = (2 m + h) + 32 (4 g + r), r < 4, of half h.  The block
 // sums leave in two rounds, the even E-W beams and then the odd ones, so
-// that each round fits the tile.
+// that each round fits the tile.  TAPER 1 (real per-antenna weights) and 2
+// (complex gains, or real weights when gain_src is 1) scale each decoded
+// antenna value before the N-S transform, from one LDS copy per workgroup.
+template <int TAPER>
 __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
   constexpr int N = 256, G = 16, L = 16, M = 512;
   constexpr int NSL = dit_slots(G);
@@ -762,11 +765,22 @@ __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
   __shared__ cf lds_tiles[kHWpg * 64 * YS];
   __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
   __shared__ cf lds_c16[G];
+  // the factor of antenna (a_ns, q) at [q][a_ns] (TAPER 2: complex, interleaved)
+  __shared__ float lds_h[TAPER == 2 ? N * 8 : TAPER == 1 ? N * 4 : 1];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   cf* const lds_y = lds_tiles + wave * 64 * YS;
   const int e1 = lane >> 4, a1 = lane & 15;      // pass 1 and 2: E-W antenna column e1
+  if constexpr (TAPER == 1) {
+    for (int i = threadIdx.x; i < N * 4; i += 64 * kHWpg) lds_h[(i & 3) * N + (i >> 2)] = p.taper[i];
+  } else if constexpr (TAPER == 2) {
+    for (int i = threadIdx.x; i < N * 4; i += 64 * kHWpg) {
+      const int o = 2 * ((i & 3) * N + (i >> 2));
+      lds_h[o] = p.gain_src == 2 ? p.taper[2 * i] : p.gain_src == 1 ? p.taper[i] : 1.f;
+      lds_h[o + 1] = p.gain_src == 2 ? p.taper[2 * i + 1] : 0.f;
+    }
+  }
 
   for (int i = threadIdx.x; i < 2 * G * L; i += 64 * kHWpg) {
     const int h = i / (G * L), r = i % (G * L), aa = r / L, m = r % L;
@@ -813,7 +827,18 @@ __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
     for (int it = 0; it < n_it; ++it) {
       cf x[L];
 #pragma unroll
-      for (int j = 0; j < L; ++j) x[j] = cf{nib(b[j], sh_re), nib(b[j], sh_im)};
+      for (int j = 0; j < L; ++j) {
+        const float xr = nib(b[j], sh_re), xi = nib(b[j], sh_im);
+        if constexpr (TAPER == 1) {
+          const float hh = lds_h[e1 * N + a1 + G * j];
+          x[j] = cf{hh * xr, hh * xi};
+        } else if constexpr (TAPER == 2) {
+          const float2 gg = *reinterpret_cast<const float2*>(&lds_h[2 * (e1 * N + a1 + G * j)]);
+          x[j] = cf{fmaf(-gg.y, xi, gg.x * xr), fmaf(gg.y, xr, gg.x * xi)};
+        } else {
+          x[j] = cf{xr, xi};
+        }
+      }
       cf xo[L];
       padded_odd_t<L>(x, xo);
       dit<L>(x);
@@ -901,7 +926,15 @@ __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
 }
 
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ew8(Fft32Args p) {
-  fft32_ew8_run(p);
+  fft32_ew8_run<0>(p);
+}
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ew8w(Fft32Args p) {
+  fft32_ew8_run<1>(p);
+}
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ew8g(Fft32Args p) {
+  fft32_ew8_run<2>(p);
 }
 
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_h(Fft32Args p) {
@@ -964,8 +997,14 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
     }
     if ((taper == 1 || taper == 2) && !cplx) {   // windowed or gain-weighted 4 x 256 intensities
       const dim3 grid((unsigned)((a.n_wg + kHWpg - 1) / kHWpg)), threads(64 * kHWpg);
-      if (taper == 1) hipLaunchKernelGGL(k_fft32_hw, grid, threads, 0, s, a);
-      else hipLaunchKernelGGL(k_fft32_hg, grid, threads, 0, s, a);
+      if (a.ew_rows == 8) {                      // with the E-W axis padded: all eight E-W beams
+        if (taper == 1) hipLaunchKernelGGL(k_fft32_ew8w, grid, threads, 0, s, a);
+        else hipLaunchKernelGGL(k_fft32_ew8g, grid, threads, 0, s, a);
+      } else if (taper == 1) {
+        hipLaunchKernelGGL(k_fft32_hw, grid, threads, 0, s, a);
+      } else {
+        hipLaunchKernelGGL(k_fft32_hg, grid, threads, 0, s, a);
+      }
       return hipGetLastError();
     }
   }
@@ -981,7 +1020,7 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
 int fft32_group(int n_ns, int fold) { return fft32_g(n_ns, fold); }
 
 bool fft32_fuses_ew8(int n_ns, int taper, bool cplx, int fold) {
-  return n_ns == 256 && taper == 0 && !cplx && fold == 1;
+  return n_ns == 256 && taper >= 0 && taper <= 2 && !cplx && fold == 1;
 }
 
 hipError_t launch_fft32(const Fft32Args& a, int n_ns, int taper, bool cplx, int64_t n_wg,
