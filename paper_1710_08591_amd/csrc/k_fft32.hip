@@ -477,12 +477,11 @@ __attribute__((amdgpu_waves_per_eu(fft32_min_waves<N, G, TAPER, CPLX, FOLD>())))
 // share it), not in registers, and the next frame's voltages are loaded
 // during the second half only: about 125 registers and 10 KB of LDS per
 // wavefront, so four wavefronts fit per SIMD (two for the kernel above).
-// Intensities: k_fft32_h unwindowed, k_fft32_hw with a real window and
-// k_fft32_hg with complex gains (three wavefronts per SIMD); the
-// complex-output variants of this lattice take the kernel above.
-// k_fft32_ew8 is the unwindowed kernel for an E-W axis zero-padded to 8
-// beams (the N-S transform on the four E-W antenna columns, then the
-// padded E-W transform per N-S beam; below).
+// Intensities: k_fft32_h unwindowed and k_fft32_hw with a real window
+// (three wavefronts per SIMD); the complex-output variants of this lattice
+// take the kernel above.  Complex gains and an E-W axis zero-padded to 8
+// beams take the N-S-first kernels below (the N-S transform on the four E-W
+// antenna columns, then the E-W transform per N-S beam).
 constexpr int kHWpg = 4;                 // wavefronts per workgroup
 constexpr int kHRow = 44;                // LDS floats per (half, a1) row: 16 tangents, 25 multipliers, pad
 
@@ -510,10 +509,8 @@ struct HalfTw {
 };
 
 // TAPER 1: real per-antenna weights h (Sec. "Controlling beam shape with
-// windowing"); 2: complex per-antenna gains g (or the real weights, times
-// W_8^{a_ew} when twisting for the odd beams of a padded E-W axis).  Both are
-// applied to the decoded nibbles before the E-W DFT as in the kernel above
-// (WindowLane), from one LDS copy of the factors per workgroup.
+// windowing"), applied to the decoded nibbles before the E-W DFT as in the
+// kernel above (WindowLane), from one LDS copy per workgroup.
 template <int TAPER = 0>
 __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   constexpr int N = 256, G = 16, L = 16, M = 512;
@@ -527,8 +524,9 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   // put the 16 rows a lane group reads on different bank groups
   __shared__ __attribute__((aligned(16))) float lds_tab[2][G][kHRow];
   __shared__ cf lds_c16[G];                                           // whole twiddle of column k2 = 16
-  // the window [a_ns][a_ew] (TAPER 1) or the complex factors (TAPER 2)
-  __shared__ __attribute__((aligned(16))) float lds_h[TAPER == 2 ? N * 8 : TAPER == 1 ? N * 4 : 1];
+  static_assert(TAPER == 0 || TAPER == 1, "unwindowed or a real window");
+  // the window [a_ns][a_ew] (TAPER 1)
+  __shared__ __attribute__((aligned(16))) float lds_h[TAPER == 1 ? N * 4 : 1];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -549,28 +547,6 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   }
   if constexpr (TAPER == 1) {
     for (int i = threadIdx.x; i < N * 4; i += 64 * kHWpg) lds_h[i] = p.taper[i];
-  } else if constexpr (TAPER == 2) {
-    // per antenna (a_ns, q): the real weight or the complex gain, times W_8^q when twisting
-    constexpr float kS = 0.70710678118654752f;
-    for (int i = threadIdx.x; i < N * 4; i += 64 * kHWpg) {
-      float gr = 1.f, gi = 0.f;
-      if (p.gain_src == 2) {
-        gr = p.taper[2 * i];
-        gi = p.taper[2 * i + 1];
-      } else if (p.gain_src == 1) {
-        gr = p.taper[i];
-      }
-      if (p.twist) {
-        const int q = i & 3;
-        const float wr = q == 0 ? 1.f : q == 1 ? kS : q == 2 ? 0.f : -kS;
-        const float wi = q == 0 ? 0.f : q == 1 ? -kS : q == 2 ? -1.f : -kS;
-        const float tr = gr * wr - gi * wi;
-        gi = gr * wi + gi * wr;
-        gr = tr;
-      }
-      lds_h[2 * i] = gr;
-      lds_h[2 * i + 1] = gi;
-    }
   }
   __syncthreads();
   const int64_t task = (int64_t)blockIdx.x * kHWpg + wave;
@@ -608,26 +584,7 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
       for (int j = 0; j < L; ++j) b[j] = __builtin_nontemporal_load(q + a1 + G * j);
       for (int it = 0; it < n_it; ++it) {
         cf x[L];
-        if constexpr (TAPER == 2) {
-#pragma unroll
-          for (int j = 0; j < L; ++j) {
-            // w_q = g_q z_q, split as for real weights (WindowLane)
-            const uint32_t d = b[j];
-            const float4 g01 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8]);
-            const float4 g23 = *reinterpret_cast<const float4*>(&lds_h[(a1 + G * j) * 8 + 4]);
-            const float s2r = wl.s * g23.x, s2i = wl.s * g23.y;     // s g2
-            const float r1i = wl.r * g01.w;                          // r g1i
-            const float s3r = wl.s * g23.z;                          // s g3r (s r g3i = -g3i)
-            const float xr0 = nib(d, 4), xi0 = nib(d, 0), xr2 = nib(d, 20), xi2 = nib(d, 16);
-            const float u1 = nib(d, wl.ou), v1 = nib(d, wl.ov);
-            const float u3 = nib(d, wl.ou + 16), v3 = nib(d, wl.ov + 16);
-            const float pr = fmaf(-s2i, xi2, fmaf(s2r, xr2, fmaf(-g01.y, xi0, g01.x * xr0)));
-            const float pim = fmaf(s2i, xr2, fmaf(s2r, xi2, fmaf(g01.y, xr0, g01.x * xi0)));
-            const float qr = fmaf(-g23.w, v3, fmaf(s3r, u3, fmaf(r1i, v1, g01.z * u1)));
-            const float qi = fmaf(g23.w, u3, fmaf(s3r, v3, fmaf(-r1i, u1, g01.z * v1)));
-            x[j] = cf{fmaf(wl.tr, qr, pr), fmaf(wl.ti, qi, pim)};
-          }
-        } else if constexpr (TAPER == 1) {
+        if constexpr (TAPER == 1) {
 #pragma unroll
           for (int j = 0; j < L; ++j) {
             const uint32_t d = b[j];
@@ -718,6 +675,16 @@ __device__ __forceinline__ void fft32_h_run(const Fft32Args& p) {
   }
 }
 
+// |B|^2 of the four beams of the unpadded 4-point E-W transform of one N-S
+// beam, from its four E-W antenna columns z_q, added to acc[e]
+__device__ __forceinline__ void ew4_beams_acc(const cf* z, float* acc) {
+  const cf s02 = cadd(z[0], z[2]), d02 = csub(z[0], z[2]), s13 = cadd(z[1], z[3]), d13 = csub(z[1], z[3]);
+  acc[0] = cnorm_acc(cadd(s02, s13), acc[0]);
+  acc[2] = cnorm_acc(csub(s02, s13), acc[2]);
+  acc[1] = cnorm_acc(cf{d02.r + d13.i, d02.i - d13.r}, acc[1]);   // d02 - i d13
+  acc[3] = cnorm_acc(cf{d02.r - d13.i, d02.i + d13.r}, acc[3]);   // d02 + i d13
+}
+
 // |B|^2 of the eight beams of the zero-padded 8-point E-W transform of one
 // N-S beam, from its four E-W antenna columns z_q, added to acc[E]: the even
 // beams 2e are the 4-point DFT of z_q, the odd beams 2e + 1 that of
@@ -754,8 +721,9 @@ __device__ __forceinline__ void ew8_beams_acc(const cf* z, float* acc) {
 // that each round fits the tile.  TAPER 1 (real per-antenna weights) and 2
 // (complex gains, or real weights when gain_src is 1) scale each decoded
 // antenna value before the N-S transform, from one LDS copy per workgroup.
-template <int TAPER>
-__device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
+template <int TAPER, int MEW>
+__device__ __forceinline__ void fft32_nsf_run(const Fft32Args& p) {
+  static_assert(MEW == 4 || MEW == 8, "E-W transform of 4 or 8 beams");
   constexpr int N = 256, G = 16, L = 16, M = 512;
   constexpr int NSL = dit_slots(G);
   constexpr int YS = L + 1;
@@ -810,13 +778,13 @@ __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
   cf* const row = &lds_y[lane * YS];
   const int sh_re = 8 * e1 + 4, sh_im = 8 * e1;    // antenna e1: real part high nibble, imaginary low
 
-  float acc[2][4][8];
+  float acc[2][4][MEW];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) acc[h][r][e] = 0.f;
+      for (int e = 0; e < MEW; ++e) acc[h][r][e] = 0.f;
 
   for (int pi = 0; pi < p.pol_iter; ++pi) {
     const int pol = (p.pol_iter == 1) ? pg : pi;
@@ -892,7 +860,8 @@ __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
           cf zq[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) zq[c] = lds_y[(4 * e1 + r) * 64 + c * 16 + a1];
-          ew8_beams_acc(zq, acc[h][r]);
+          if constexpr (MEW == 8) ew8_beams_acc(zq, acc[h][r]);
+          else ew4_beams_acc(zq, acc[h][r]);
         }
         wave_lds_sync();
       }
@@ -904,21 +873,22 @@ __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
   auto ebase = [](int e) { return e * M + (e & 1) + 32 * (e >> 1); };
   const int keep = p.n_keep;
   const int32_t* sel = p.sel ? p.sel + (int64_t)chan * keep : nullptr;
-  float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * 8 * keep;
+  float* o = static_cast<float*>(p.out) + (((int64_t)blk * p.n_chan + chan) * p.n_pg + pg) * p.ew_rows * keep;
 #pragma unroll
-  for (int odd = 0; odd < 2; ++odd) {
+  for (int odd = 0; odd < MEW / 4; ++odd) {
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) lds_i[ebase(e) + 2 * a1 + h + 32 * (4 * e1 + r)] = acc[h][r][2 * e + odd];
+        for (int e = 0; e < 4; ++e)
+          lds_i[ebase(e) + 2 * a1 + h + 32 * (4 * e1 + r)] = acc[h][r][MEW == 8 ? 2 * e + odd : e];
     wave_lds_sync();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       for (int j = lane; j < keep; j += 64) {
         const int A = sel ? sel[j] : j;
-        o[(2 * e + odd) * keep + j] = lds_i[ebase(e) + A] * p.norm;
+        o[(MEW == 8 ? 2 * e + odd : e * p.ew_mul + p.ew_off) * keep + j] = lds_i[ebase(e) + A] * p.norm;
       }
     }
     wave_lds_sync();
@@ -926,15 +896,19 @@ __device__ __forceinline__ void fft32_ew8_run(const Fft32Args& p) {
 }
 
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ew8(Fft32Args p) {
-  fft32_ew8_run<0>(p);
+  fft32_nsf_run<0, 8>(p);
 }
 
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ew8w(Fft32Args p) {
-  fft32_ew8_run<1>(p);
+  fft32_nsf_run<1, 8>(p);
 }
 
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ew8g(Fft32Args p) {
-  fft32_ew8_run<2>(p);
+  fft32_nsf_run<2, 8>(p);
+}
+
+__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_ng(Fft32Args p) {
+  fft32_nsf_run<2, 4>(p);
 }
 
 __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(4))) void k_fft32_h(Fft32Args p) {
@@ -947,10 +921,6 @@ __global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3)))
   fft32_h_run<1>(p);
 }
 
-// complex gains (8 KB of factors per workgroup): three workgroups per CU
-__global__ __launch_bounds__(64 * kHWpg) __attribute__((amdgpu_waves_per_eu(3))) void k_fft32_hg(Fft32Args p) {
-  fft32_h_run<2>(p);
-}
 
 template <int N, int G, int T, int FOLD = 1>
 void launch_nt(const Fft32Args& a, bool cplx, hipStream_t s) {
@@ -1003,7 +973,7 @@ hipError_t launch_n(const Fft32Args& a, int taper, bool cplx, hipStream_t s) {
       } else if (taper == 1) {
         hipLaunchKernelGGL(k_fft32_hw, grid, threads, 0, s, a);
       } else {
-        hipLaunchKernelGGL(k_fft32_hg, grid, threads, 0, s, a);
+        hipLaunchKernelGGL(k_fft32_ng, grid, threads, 0, s, a);
       }
       return hipGetLastError();
     }
