@@ -181,7 +181,9 @@ constexpr int fft32_wpg() {
 // registers (four wavefronts per SIMD, the occupancy its shared table is
 // sized for; it fits without spilling, the complex-output variant does not).
 template <int N, int G, int TAPER, bool CPLX, int FOLD>
-constexpr int fft32_min_waves() { return TAPER == 2 && !CPLX && N * FOLD < 256 ? 4 : 1; }
+constexpr int fft32_min_waves() {
+  return (TAPER == 2 && !CPLX && N * FOLD < 256) || (FOLD > 1 && FOLD < 16 && N * FOLD == 256 && TAPER <= 1 && !CPLX) ? 4 : 1;
+}
 
 template <int N, int G, int TAPER, bool CPLX, int FOLD = 1>
 __global__ __launch_bounds__((64 * fft32_wpg<N, G, TAPER, FOLD>()))
