@@ -433,7 +433,7 @@ __global__ void k_mixp_twiddles(void* tab, int R) {
 }
 
 template <int PREC, int R, bool WIN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_mixp(MixArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R == 2 ? 4 : R == 4 && PREC == kPrecFp16 ? 3 : 2))) void k_mixp(MixArgs a) {
   static_assert(!WIN || PREC == kPrecFp16, "windows run on the FP16 path");
   constexpr int N = 16 * R, M = 2 * N;
   constexpr bool PAIR = PREC == kPrecFp8 && R <= 4;
