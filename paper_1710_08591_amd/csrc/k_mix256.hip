@@ -187,7 +187,7 @@ __device__ __forceinline__ void ew_windowed(const uint32_t* dw, const float (&h)
 // weight lies in [1/2, 1) and the low terms stay in FP16's normal range;
 // the block sums are scaled back exactly.
 template <bool WIN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WIN ? 2 : 3))) void k_mix256(MixArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_mix256(MixArgs a) {
   constexpr int N = 256, M = 512;
   constexpr int ROW = 18;                     // complex values per (E-W beam, k2) row: 16 a1 + 2 pad
   __shared__ float4 lds_raw[2 * 32 * ROW / 2];
