@@ -28,6 +28,10 @@
 //   * |B|^2 accumulates in registers across the block; at the block end the
 //     sums go through LDS once more so the kept beams can be gathered in
 //     the channel's clamp-table order and stored with coalesced writes.
+//   * the two axes' transforms commute: on the 4 x 256 lattice, with complex
+//     gains or with the E-W axis zero-padded to 8 beams, the N-S transform
+//     runs first on the four E-W antenna columns and the E-W transform runs
+//     per N-S beam after pass 2 (fft32_nsf_run below).
 #include "dev_common.h"
 #include "kernels.h"
 
