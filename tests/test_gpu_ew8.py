@@ -182,10 +182,11 @@ def test_regrid2d_c2_shape_sampled():
 
 @pytest.mark.parametrize("block", [4, 48])
 def test_ew8_fused_block_lengths(block):
-    """The one-launch padded-E-W kernel of the 4 x 256 lattice runs each
-    block twice (even, then odd E-W beams); blocks of 4 and 48 samples
-    (several blocks per channel, the frame prefetch crossing block and
-    polarisation boundaries) against the oracle."""
+    """The one-launch padded-E-W kernel of the 4 x 256 lattice (the N-S
+    transform of the four E-W antenna columns, then all eight E-W beams per
+    N-S beam); blocks of 4 and 48 samples (several blocks per channel, the
+    frame prefetch crossing block and polarisation boundaries) against the
+    oracle."""
     torch = _torch()
     import paper_1710_08591_amd as bf
     w = sg.custom_workload(n_ew=4, n_ns=256, n_chan=2, n_pol=2, n_time=96, seed=block, n_src=2, snr=5.0)
@@ -195,4 +196,33 @@ def test_ew8_fused_block_lengths(block):
     plan.close()
     ref = orc.beamform_fft(v, 8, 512, block)
     assert got.shape == ref.shape == (96 // block, 2, 2, 8, 512)
+    assert rel_err(got, ref) < TOL_FP32
+
+
+@pytest.mark.parametrize("window", [None, "real", "gains"])
+def test_ew8_fused_partial_workgroup(window):
+    """The one-launch padded-E-W kernels of the 4 x 256 lattice with a task
+    count that leaves the last workgroup partly empty (5 blocks x 3 channels
+    x 1 polarisation = 15 tasks for four-wavefront workgroups), a clamp to
+    200 N-S beams, unwindowed, with a real window and with complex gains."""
+    torch = _torch()
+    import paper_1710_08591_amd as bf
+    w = sg.custom_workload(n_ew=4, n_ns=256, n_chan=3, n_pol=1, n_time=80, seed=31, n_src=2, snr=5.0,
+                           n_ns_keep=200)
+    v = sg.volts(w)
+    sel = w.ns_select()
+    plan = _plan(bf, w, sel=sel)
+    kw, h = {}, None
+    if window == "real":
+        h = sg.gaussian_taper(4, 256)
+        kw["taper"] = torch.from_numpy(h).cuda()
+    elif window == "gains":
+        rng = np.random.default_rng(5)
+        h = np.exp(0.2 * rng.normal(size=(256, 4)) + 1j * rng.uniform(-3, 3, (256, 4))).astype(np.complex64)
+        kw["gains"] = torch.from_numpy(h).cuda()
+    got = bf.beamform_fft(plan, torch.from_numpy(v).cuda(), **kw).cpu().numpy()
+    plan.close()
+    ref = orc.beamform_fft(v, 8, 512, 16, ns_select=sel, taper=None if h is None else h.astype(
+        np.complex128 if np.iscomplexobj(h) else np.float64))
+    assert got.shape == ref.shape == (5, 3, 1, 8, 200)
     assert rel_err(got, ref) < TOL_FP32
