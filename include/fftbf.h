@@ -67,9 +67,10 @@ typedef struct bf_plan bf_plan;
  * or, for FP32 plans, m_ew = 8 (E-W zero-padded to M_ew >= 2 n_ew - 1, so
  * that intensity regridding is exact on both axes; the odd E-W beams are
  * the 4-point DFT of x_a W_8^{a_ew}, formed by a second launch over the
- * voltages, except for unwindowed 4 x 256 intensities, where one launch
- * transforms the four E-W antenna columns along N-S and forms all eight
- * E-W beams of each N-S beam; tied beams and the server need m_ew = 4);
+ * voltages, except for 4 x 256 intensities (with or without a window or
+ * gains), where one launch transforms the four E-W antenna columns along
+ * N-S and forms all eight E-W beams of each N-S beam; tied beams and the
+ * server need m_ew = 4);
  * n_ns a power of two in [16, 256] with m_ns = 2 n_ns (zero padding by two,
  * the smallest power of two with M >= 2n - 1, eq. e:b2n-1), or, for FP32
  * plans with m_ew = 4 and no clamp, m_ns a power of two in [16, 128] below
