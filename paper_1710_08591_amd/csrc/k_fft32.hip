@@ -186,7 +186,12 @@ constexpr int fft32_wpg() {
 // sized for; it fits without spilling, the complex-output variant does not).
 template <int N, int G, int TAPER, bool CPLX, int FOLD>
 constexpr int fft32_min_waves() {
-  return (TAPER == 2 && !CPLX && N * FOLD < 256) || (FOLD > 1 && FOLD < 16 && N * FOLD == 256 && TAPER <= 1 && !CPLX) ? 4 : 1;
+  // co-adding 256 N-S antennas (folds 2 to 8; with a window from fold 4 on,
+  // the windowed 2-fold kernel does not fit 128 registers)
+  return (TAPER == 2 && !CPLX && N * FOLD < 256) ||
+                 (N * FOLD == 256 && FOLD > 1 && FOLD < 16 && !CPLX && (TAPER == 0 || (TAPER == 1 && FOLD >= 4)))
+             ? 4
+             : 1;
 }
 
 template <int N, int G, int TAPER, bool CPLX, int FOLD = 1>
